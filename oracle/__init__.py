@@ -1,0 +1,9 @@
+"""FP64 CPU oracle for the variable-speed-of-sound D2Q9 lattice Boltzmann step.
+
+TEST INFRASTRUCTURE. Only the tests, the smoke check and the benchmark's
+CPU-baseline leg load this package. The product library never does, and the
+two share no code.
+"""
+from .lbmref import Oracle, lattice, alpha, equilibrium, source, load, set_threads, get_threads
+
+__all__ = ["Oracle", "lattice", "alpha", "equilibrium", "source", "load", "set_threads", "get_threads"]

@@ -1,0 +1,64 @@
+"""The pins must catch a plausible mistake anywhere in the oracle.
+
+Each case plants one mistake in a copy of the oracle's C source (a dropped
+term, a wrong sign, index, factor or operand), builds it, and runs the fast
+pin suite against it with LBMREF_LIB: the suite must fail. The mistakes are
+planted on the CPU, in the oracle only.
+"""
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+ORACLE = os.path.join(ROOT, "oracle")
+
+MUTANTS = {
+    "drop_u2_term": ("4.5 * eu * eu - 1.5 * usq", "4.5 * eu * eu"),
+    "wrong_quadratic_coeff": ("4.5 * eu * eu", "3.0 * eu * eu"),
+    "source_sign": ("s[i] = 3.0 * w[i] * alpha", "s[i] = -3.0 * w[i] * alpha"),
+    "alpha_sign": ("return 1.0 / 3.0 - c2;", "return c2 - 1.0 / 3.0;"),
+    "forward_difference_x": ("L->R[(size_t)y * nx + wrap(x - 1, nx)]) / 2.0", "L->R[s]) / 1.0"),
+    "missing_half_y": ("L->R[(size_t)wrap(y - 1, ny) * nx + x]) / 2.0", "L->R[(size_t)wrap(y - 1, ny) * nx + x]) / 1.0"),
+    "swapped_gradient": ("lbmref_source(L->alpha, gx, gy, src)", "lbmref_source(L->alpha, gy, gx, src)"),
+    "y_gradient_wrong_column": ("L->R[(size_t)wrap(y + 1, ny) * nx + x]", "L->R[(size_t)wrap(y + 1, ny) * nx + wrap(x + 1, nx)]"),
+    "stream_backwards_x": ("int xd = wrap(x + e[2 * i], nx);", "int xd = wrap(x - e[2 * i], nx);"),
+    "stream_transposed": ("int yd = wrap(y + e[2 * i + 1], ny);", "int yd = wrap(y + e[2 * i], ny);"),
+    "relaxation_off": ("(fi - feq[i]) / L->tau", "(fi - feq[i]) / (L->tau + 0.01)"),
+    "diagonal_weight": ("w[i] = 1.0 / 36.0;", "w[i] = 1.0 / 35.0;"),
+    "link_angle": ("double a = pi * (i - 4.5) / 2.0;", "double a = pi * (i - 5.5) / 2.0;"),
+    "momentum_not_velocity": ("L->UX[s] = jx / rho;", "L->UX[s] = jx;"),
+    "u_x_for_u_y": ("double eu = e[2 * i] * ux + e[2 * i + 1] * uy;", "double eu = e[2 * i] * ux + e[2 * i + 1] * ux;"),
+}
+
+FAST_PINS = [os.path.join(ROOT, "tests", "test_oracle_pins.py"),
+             os.path.join(ROOT, "tests", "test_oracle_physics.py")]
+
+
+def run_pins_against(source_text, tmp_path):
+    (tmp_path / "lbmref.c").write_text(source_text)
+    shutil.copy(os.path.join(ORACLE, "lbmref.h"), tmp_path / "lbmref.h")
+    lib = tmp_path / "liblbmref.so"
+    subprocess.run(["make", "-s", "-C", ORACLE, f"SRC={tmp_path / 'lbmref.c'}", f"OUT={lib}"],
+                   check=True, capture_output=True)
+    env = dict(os.environ, LBMREF_LIB=str(lib), OMP_NUM_THREADS="4")
+    return subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-m", "not slow", "-p", "no:cacheprovider",
+                           *FAST_PINS], cwd=ROOT, env=env, capture_output=True, text=True)
+
+
+def test_unmutated_copy_passes(tmp_path):
+    """Control: the harness itself does not make the pins fail."""
+    r = run_pins_against(open(os.path.join(ORACLE, "lbmref.c")).read(), tmp_path)
+    assert r.returncode == 0, r.stdout[-2000:]
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_planted_mistake(name, tmp_path):
+    old, new = MUTANTS[name]
+    src = open(os.path.join(ORACLE, "lbmref.c")).read()
+    assert src.count(old) >= 1, f"mutation target for {name} not found"
+    r = run_pins_against(src.replace(old, new, 1), tmp_path)
+    assert r.returncode == 1, f"pins did not catch mutant {name} (exit {r.returncode}):\n{r.stdout[-2000:]}"
+    assert "failed" in r.stdout.splitlines()[-1]
