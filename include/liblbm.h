@@ -1,0 +1,127 @@
+/*
+ * liblbm.h -- MI355X (gfx950) lattice Boltzmann library for the
+ * variable-speed-of-sound D2Q9 model of Buick & Cosgrove, "Investigation of
+ * a Lattice Boltzmann Model with a Variable Speed of Sound".
+ *
+ * One time step is the update of Sec. 3, Eq. 5:
+ *
+ *   f_i(x + e_i, t + 1) = f_i(x, t) - (f_i - feq_i)/tau + 3 w_i alpha grad(rho).e_i
+ *
+ * on a periodic nx x ny D2Q9 lattice (links e_i and weights w_i of Sec. 2),
+ * with feq of Eq. 2, rho and rho u of Eq. 3, and grad(rho) at time t by
+ * central differences (Sec. 4, discussion of Fig. 1). The caller chooses the
+ * squared speed of sound c2 = c_e^2; the library uses alpha = 1/3 - c2
+ * (Eq. 8 with c_1^2 = 1/3), so c2 = 1/3 is the standard model (alpha = 0).
+ * The viscosity is nu = (2 tau - 1)/6 for every c2 (Eq. 4, 7).
+ *
+ * All work runs in HIP kernels on the current HIP device of the calling
+ * thread at create time. The library owns the device memory it allocates;
+ * host arrays passed in belong to the caller and are only accessed during
+ * the call. A handle is not thread-safe; distinct handles may be used from
+ * distinct threads. No function throws; every int-returning function returns
+ * an lbm_status.
+ *
+ * Field layout: every host or device field array is FP64, row-major, index
+ * y*nx + x, nx*ny entries. Population arrays are FP64 [9][ny][nx] in the
+ * link order of Sec. 2: e_0 = (0,0), e_1..4 = (1,0), (0,1), (-1,0), (0,-1),
+ * e_5..8 = (1,1), (-1,1), (-1,-1), (1,-1).
+ */
+#ifndef LIBLBM_H
+#define LIBLBM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Storage / arithmetic forms. */
+enum lbm_dtype {
+    LBM_F64 = 0,  /* f_i stored in FP64, FP64 arithmetic                         */
+    LBM_F32 = 1,  /* f_i stored in FP32, FP32 arithmetic on d_i = f_i - w_i       */
+    LBM_F32S = 2, /* g_i = f_i - w_i (rho0 = 1) stored in FP32, FP32 arithmetic  */
+    LBM_F16S = 3  /* g_i = f_i - w_i stored in FP16, FP32 arithmetic             */
+};
+
+enum lbm_status {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,     /* argument out of range or NULL handle                   */
+    LBM_ENOMEM = -2,     /* device or host allocation failed / budget exceeded     */
+    LBM_EDEVICE = -3,    /* a HIP call failed                                      */
+    LBM_ESTATE = -4,     /* step or read before init                               */
+    LBM_ENONFINITE = -5  /* a conservation total is NaN or infinite                */
+};
+
+typedef struct lbm_lattice lbm_lattice;
+
+/* Create a periodic nx x ny lattice on the current HIP device.
+ * nx, ny >= 3 (the central differences of Sec. 4 need two distinct
+ * neighbours); tau > 1/2 and finite (nu > 0, Eq. 4); c2 > 0 and finite
+ * (c_e real, Eq. 8); dtype one of lbm_dtype. Large c2 is accepted: the paper
+ * ran c_e up to 1.125 (Sec. 4); stability then depends on tau and the grid.
+ * Allocates lbm_footprint_bytes(nx, ny, dtype) of device memory. Returns
+ * NULL on failure and sets lbm_last_error() (LBM_EINVAL, LBM_ENOMEM,
+ * LBM_EDEVICE). */
+lbm_lattice* lbm_create(int nx, int ny, double tau, double c2, int dtype);
+
+/* Status of the last failed lbm_create on this thread. */
+int lbm_last_error(void);
+
+/* Static text for a status code. */
+const char* lbm_strerror(int status);
+
+/* Release the lattice and its device memory (synchronises its stream).
+ * NULL is a no-op. */
+void lbm_destroy(lbm_lattice* L);
+
+/* Set f_i(x, 0) = feq_i(rho(x), u(x)) (Eq. 2) from HOST FP64 fields.
+ * rho == NULL means rho = 1; ux / uy == NULL mean 0. Resets t to 0.
+ * Synchronous. */
+int lbm_init(lbm_lattice* L, const double* rho, const double* ux, const double* uy);
+
+/* As lbm_init, but rho / ux / uy are DEVICE pointers (same layout) on the
+ * lattice's device; asynchronous on the lattice's stream. */
+int lbm_init_device(lbm_lattice* L, const double* rho, const double* ux, const double* uy);
+
+/* Advance n >= 0 steps of Eq. 5; asynchronous on the lattice's stream.
+ * LBM_ESTATE before init. */
+int lbm_step(lbm_lattice* L, int n);
+
+/* rho and u = (rho u)/rho (Eq. 3) of the current state f(x, t) into HOST
+ * arrays (any may be NULL), and totals = {sum rho, sum rho u_x, sum rho u_y}
+ * accumulated in FP64 in a fixed order (deterministic). totals may be NULL.
+ * Synchronous. Returns LBM_ENONFINITE if a total is not finite. */
+int lbm_moments(lbm_lattice* L, double* rho, double* ux, double* uy, double totals[3]);
+
+/* As lbm_moments with DEVICE field pointers (any may be NULL) and HOST
+ * totals (may be NULL). Synchronises the lattice's stream. */
+int lbm_moments_device(lbm_lattice* L, double* rho, double* ux, double* uy, double totals[3]);
+
+/* Canonical populations f_i(x, t) (the pre-collision state of Eq. 5) to /
+ * from a HOST FP64 array [9][ny][nx]. lbm_set_f resets t to 0. Synchronous.
+ * For the shifted forms the stored value is f_i - w_i, converted on the way. */
+int lbm_get_f(lbm_lattice* L, double* f);
+int lbm_set_f(lbm_lattice* L, const double* f);
+
+/* Use an existing HIP stream (hipStream_t, e.g. PyTorch's current stream)
+ * for all later work on this lattice. NULL selects the library's own
+ * stream. The caller keeps ownership of the stream. */
+int lbm_set_stream(lbm_lattice* L, void* hip_stream);
+
+/* Number of completed steps since init / set_f (-1 for NULL). */
+long long lbm_time(const lbm_lattice* L);
+
+/* Device bytes lbm_create allocates for this shape (0 if invalid). */
+size_t lbm_footprint_bytes(int nx, int ny, int dtype);
+
+/* Step tile shape: vx = sites per lane along x, nw = 64-lane waves per
+ * workgroup, h = rows per workgroup. vx in {1, 2, 4, 8} (allowed values
+ * depend on dtype), nw in {1, 2, 4}, h >= 1. Results do not depend on the
+ * tile shape (bitwise). LBM_EINVAL for an unsupported shape. */
+int lbm_set_tile(lbm_lattice* L, int vx, int nw, int h);
+int lbm_get_tile(const lbm_lattice* L, int* vx, int* nw, int* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LIBLBM_H */

@@ -1,0 +1,50 @@
+// internal.h -- types shared by the HIP kernels and the host runtime of liblbm.
+//
+// Storage ("pull" form). For every link i the device keeps one plane
+// S_i[y][x] holding the post-collision value f*_i(x, y) of the previous step,
+// i.e. the value that streams to x + e_i (Eq. 5, left-hand side). A step
+// gathers f_i(x, t) = S_i(x - e_i), relaxes it (Eq. 5, right-hand side) and
+// writes S'_i(x) aligned into the other buffer (A/B).
+//
+// Row layout: element (x, y) of plane i sits at
+//   i * plane + y * pitch + off + x,   x in [-1, nx]
+// where columns -1 and nx are ghost copies of columns nx-1 and 0 (written
+// by the step that writes those columns), so the +-1 column shifts of the
+// gather need no wrap test. `off` is one 128-byte line, so x = 0 is
+// line-aligned; `pitch` is a multiple of a line. Rows wrap in y by index.
+#pragma once
+
+#include <stdint.h>
+
+namespace lbm {
+
+constexpr int kMaxVX = 8;
+
+struct Geom {
+    int nx, ny;
+    int pitch;        // elements per row
+    int off;          // element offset of column 0 within a row
+    long long plane;  // elements per plane
+};
+
+// Collision / source coefficients of Eq. 5 in the delta form used by the
+// kernels (d_i = f_i - w_i):
+//   d*_0 = om1 d_0 + wo0 A
+//   d*_i = om1 d_i + P + Q,  d*_opp = om1 d_opp + P - Q        (pairs)
+// with om = 1/tau, om1 = 1 - om, wo_k = om w_k, as_k = 3 w_k alpha.
+struct Coef {
+    double om1, wo0, wo1, wo2, as1, as2;
+};
+
+// One lattice as seen by a step launch.
+struct StepTile {
+    const void* src;
+    void* dst;
+    Geom g;
+    Coef c;
+    int h;        // rows per workgroup
+    int nstrips;  // column strips
+    int nchunks;  // row chunks
+};
+
+}  // namespace lbm

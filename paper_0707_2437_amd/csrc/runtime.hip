@@ -1,0 +1,391 @@
+// runtime.hip -- host side of liblbm: handles, device memory, streams,
+// argument validation and the C ABI declared in include/liblbm.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+#include "liblbm.h"
+
+namespace lbm {
+hipError_t launch_step(int dtype, int vx, int nw, const StepTile& t, hipStream_t st);
+bool step_shape_supported(int dtype, int vx, int nw);
+hipError_t launch_init(int dtype, void* s, const Geom& g, const double* rho, const double* ux, const double* uy,
+                       hipStream_t st);
+hipError_t launch_set_f(int dtype, void* s, const Geom& g, const double* f, hipStream_t st);
+hipError_t launch_get_f(int dtype, const void* s, const Geom& g, double* f, hipStream_t st);
+int moments_blocks(const Geom& g);
+hipError_t launch_moments(int dtype, const void* s, const Geom& g, double* rho, double* ux, double* uy,
+                          double* partials, double* totals, hipStream_t st);
+}  // namespace lbm
+
+using namespace lbm;
+
+struct lbm_lattice {
+    int nx, ny, dtype, esize, device;
+    double tau, c2;
+    Geom g;
+    Coef coef;
+    size_t buf_bytes;
+    void* buf;         // both population buffers
+    void* cur;         // S of the current state (read by the next step)
+    void* nxt;         // written by the next step
+    double* red;       // moments partials (3 per block) + 3 totals
+    hipStream_t own;   // library stream
+    hipStream_t stream;
+    long long t;
+    bool ready;
+    int vx, nw, h;     // step tile
+};
+
+namespace {
+
+thread_local int g_last_error = LBM_OK;
+
+constexpr int kLineBytes = 128;
+
+int esize_of(int dtype)
+{
+    switch (dtype) {
+    case LBM_F64: return 8;
+    case LBM_F32:
+    case LBM_F32S: return 4;
+    case LBM_F16S: return 2;
+    default: return 0;
+    }
+}
+
+Geom make_geom(int nx, int ny, int esize);
+
+bool args_ok(int nx, int ny, double tau, double c2, int dtype)
+{
+    // nx, ny >= 3: the central differences need two distinct neighbours.
+    // tau > 1/2: positive viscosity (Eq. 4). c2 > 0: real c_e (Eq. 8).
+    if (nx < 3 || ny < 3 || !std::isfinite(tau) || !(tau > 0.5) || !std::isfinite(c2) || !(c2 > 0.0)) return false;
+    if (esize_of(dtype) == 0) return false;
+    if (nx > (1 << 28) || ny > (1 << 28)) return false;
+    // The kernels address a plane with 32-bit byte offsets.
+    const Geom g = make_geom(nx, ny, esize_of(dtype));
+    if ((unsigned long long)g.plane * esize_of(dtype) >= (1ULL << 32)) return false;
+    return true;
+}
+
+// Row pitch leaves one line before column 0 (ghost column -1 at its end),
+// the ghost column nx, and room for the widest vector past the last column.
+Geom make_geom(int nx, int ny, int esize)
+{
+    Geom g;
+    g.nx = nx;
+    g.ny = ny;
+    const int line = kLineBytes / esize;
+    g.off = line;
+    const long long need = (long long)line + nx + kMaxVX + 1;
+    g.pitch = (int)((need + line - 1) / line * line);
+    // Plane stride: rows of all planes, rounded to 4 KiB, plus a skew of
+    // 1 KiB so the nine concurrently streamed planes do not start on the
+    // same memory channel.
+    const long long bytes = (long long)g.pitch * ny * esize;
+    const long long pb = (bytes + 4095) / 4096 * 4096 + 1024;
+    g.plane = pb / esize;
+    return g;
+}
+
+size_t footprint(const Geom& g, int esize)
+{
+    // 2 buffers x 9 planes, plus one line of slack past the last plane.
+    return (size_t)2 * 9 * (size_t)g.plane * esize + kLineBytes;
+}
+
+size_t red_doubles(const Geom& g) { return (size_t)3 * moments_blocks(g) + 3; }
+
+Coef make_coef(double tau, double c2)
+{
+    // Eq. 5 with alpha = 1/3 - c2 (Eq. 8), weights of Sec. 2.
+    const double om = 1.0 / tau, alpha = 1.0 / 3.0 - c2;
+    const double w0 = 4.0 / 9.0, w1 = 1.0 / 9.0, w2 = 1.0 / 36.0;
+    Coef k;
+    k.om1 = 1.0 - om;
+    k.wo0 = om * w0;
+    k.wo1 = om * w1;
+    k.wo2 = om * w2;
+    k.as1 = 3.0 * w1 * alpha;
+    k.as2 = 3.0 * w2 * alpha;
+    return k;
+}
+
+void default_tile(int dtype, int* vx, int* nw, int* h)
+{
+    switch (dtype) {
+    case LBM_F64: *vx = 1; break;
+    case LBM_F32:
+    case LBM_F32S: *vx = 2; break;
+    default: *vx = 4; break;
+    }
+    *nw = 4;
+    *h = 32;
+    // Optional override for tile experiments: LBM_TILE="vx,nw,h".
+    if (const char* e = std::getenv("LBM_TILE")) {
+        int a = 0, b = 0, c = 0;
+        if (std::sscanf(e, "%d,%d,%d", &a, &b, &c) == 3 && step_shape_supported(dtype, a, b) && c > 0) {
+            *vx = a;
+            *nw = b;
+            *h = c;
+        }
+    }
+}
+
+int status_of(hipError_t e)
+{
+    if (e == hipSuccess) return LBM_OK;
+    if (e == hipErrorOutOfMemory) return LBM_ENOMEM;
+    return LBM_EDEVICE;
+}
+
+StepTile make_tile(const lbm_lattice* L)
+{
+    StepTile t;
+    t.src = L->cur;
+    t.dst = L->nxt;
+    t.g = L->g;
+    t.c = L->coef;
+    t.h = L->h;
+    const int W = 64 * L->nw * L->vx;
+    t.nstrips = (L->nx + W - 1) / W;
+    t.nchunks = (L->ny + L->h - 1) / L->h;
+    return t;
+}
+
+// RAII device scratch for host-array entry points.
+struct DevScratch {
+    double* p = nullptr;
+    hipError_t alloc(size_t n)
+    {
+        return hipMalloc((void**)&p, n * sizeof(double));
+    }
+    ~DevScratch()
+    {
+        if (p) (void)hipFree(p);
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+int lbm_last_error(void) { return g_last_error; }
+
+const char* lbm_strerror(int status)
+{
+    switch (status) {
+    case LBM_OK: return "ok";
+    case LBM_EINVAL: return "invalid argument";
+    case LBM_ENOMEM: return "out of memory";
+    case LBM_EDEVICE: return "HIP device error";
+    case LBM_ESTATE: return "lattice not initialised";
+    case LBM_ENONFINITE: return "non-finite conservation total";
+    default: return "unknown status";
+    }
+}
+
+size_t lbm_footprint_bytes(int nx, int ny, int dtype)
+{
+    if (!args_ok(nx, ny, 1.0, 1.0 / 3.0, dtype)) return 0;
+    const int es = esize_of(dtype);
+    const Geom g = make_geom(nx, ny, es);
+    return footprint(g, es) + red_doubles(g) * sizeof(double);
+}
+
+lbm_lattice* lbm_create(int nx, int ny, double tau, double c2, int dtype)
+{
+    if (!args_ok(nx, ny, tau, c2, dtype)) {
+        g_last_error = LBM_EINVAL;
+        return nullptr;
+    }
+    lbm_lattice* L = new (std::nothrow) lbm_lattice();
+    if (!L) {
+        g_last_error = LBM_ENOMEM;
+        return nullptr;
+    }
+    L->nx = nx;
+    L->ny = ny;
+    L->dtype = dtype;
+    L->esize = esize_of(dtype);
+    L->tau = tau;
+    L->c2 = c2;
+    L->g = make_geom(nx, ny, L->esize);
+    L->coef = make_coef(tau, c2);
+    default_tile(dtype, &L->vx, &L->nw, &L->h);
+    hipError_t e = hipGetDevice(&L->device);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&L->own, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        g_last_error = status_of(e);
+        delete L;
+        return nullptr;
+    }
+    L->stream = L->own;
+    L->buf_bytes = footprint(L->g, L->esize);
+    e = hipMalloc(&L->buf, L->buf_bytes);
+    if (e == hipSuccess) e = hipMalloc((void**)&L->red, red_doubles(L->g) * sizeof(double));
+    if (e == hipSuccess) e = hipMemsetAsync(L->buf, 0, L->buf_bytes, L->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+    if (e != hipSuccess) {
+        g_last_error = e == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE;
+        lbm_destroy(L);
+        return nullptr;
+    }
+    L->cur = L->buf;
+    L->nxt = (char*)L->buf + (size_t)9 * L->g.plane * L->esize;
+    g_last_error = LBM_OK;
+    return L;
+}
+
+void lbm_destroy(lbm_lattice* L)
+{
+    if (!L) return;
+    if (L->stream) (void)hipStreamSynchronize(L->stream);
+    if (L->buf) (void)hipFree(L->buf);
+    if (L->red) (void)hipFree(L->red);
+    if (L->own) (void)hipStreamDestroy(L->own);
+    delete L;
+}
+
+int lbm_set_stream(lbm_lattice* L, void* s)
+{
+    if (!L) return LBM_EINVAL;
+    hipError_t e = hipStreamSynchronize(L->stream);
+    L->stream = s ? (hipStream_t)s : L->own;
+    return status_of(e);
+}
+
+long long lbm_time(const lbm_lattice* L) { return L ? L->t : -1; }
+
+int lbm_set_tile(lbm_lattice* L, int vx, int nw, int h)
+{
+    if (!L || h < 1 || !step_shape_supported(L->dtype, vx, nw)) return LBM_EINVAL;
+    L->vx = vx;
+    L->nw = nw;
+    L->h = h;
+    return LBM_OK;
+}
+
+int lbm_get_tile(const lbm_lattice* L, int* vx, int* nw, int* h)
+{
+    if (!L) return LBM_EINVAL;
+    if (vx) *vx = L->vx;
+    if (nw) *nw = L->nw;
+    if (h) *h = L->h;
+    return LBM_OK;
+}
+
+int lbm_init_device(lbm_lattice* L, const double* rho, const double* ux, const double* uy)
+{
+    if (!L) return LBM_EINVAL;
+    hipError_t e = launch_init(L->dtype, L->cur, L->g, rho, ux, uy, L->stream);
+    if (e != hipSuccess) return status_of(e);
+    L->t = 0;
+    L->ready = true;
+    return LBM_OK;
+}
+
+int lbm_init(lbm_lattice* L, const double* rho, const double* ux, const double* uy)
+{
+    if (!L) return LBM_EINVAL;
+    const size_t n = (size_t)L->nx * L->ny;
+    DevScratch d;
+    hipError_t e = d.alloc(3 * n);
+    const double* src[3] = {rho, ux, uy};
+    const double* dp[3] = {nullptr, nullptr, nullptr};
+    for (int c = 0; c < 3 && e == hipSuccess; ++c) {
+        if (!src[c]) continue;
+        e = hipMemcpyAsync(d.p + c * n, src[c], n * sizeof(double), hipMemcpyHostToDevice, L->stream);
+        dp[c] = d.p + c * n;
+    }
+    if (e != hipSuccess) return status_of(e);
+    int st = lbm_init_device(L, dp[0], dp[1], dp[2]);
+    e = hipStreamSynchronize(L->stream);
+    return st != LBM_OK ? st : status_of(e);
+}
+
+int lbm_step(lbm_lattice* L, int n)
+{
+    if (!L || n < 0) return LBM_EINVAL;
+    if (!L->ready) return LBM_ESTATE;
+    for (int k = 0; k < n; ++k) {
+        StepTile t = make_tile(L);
+        hipError_t e = launch_step(L->dtype, L->vx, L->nw, t, L->stream);
+        if (e != hipSuccess) return status_of(e);
+        void* tmp = L->cur;
+        L->cur = L->nxt;
+        L->nxt = tmp;
+        L->t += 1;
+    }
+    return LBM_OK;
+}
+
+int lbm_moments_device(lbm_lattice* L, double* rho, double* ux, double* uy, double totals[3])
+{
+    if (!L) return LBM_EINVAL;
+    if (!L->ready) return LBM_ESTATE;
+    const int nb = moments_blocks(L->g);
+    double* tot_dev = L->red + (size_t)3 * nb;
+    hipError_t e = launch_moments(L->dtype, L->cur, L->g, rho, ux, uy, L->red, tot_dev, L->stream);
+    double tot[3] = {0, 0, 0};
+    if (e == hipSuccess) e = hipMemcpyAsync(tot, tot_dev, sizeof(tot), hipMemcpyDeviceToHost, L->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+    if (e != hipSuccess) return status_of(e);
+    if (totals) std::memcpy(totals, tot, sizeof(tot));
+    for (double v : tot)
+        if (!std::isfinite(v)) return LBM_ENONFINITE;
+    return LBM_OK;
+}
+
+int lbm_moments(lbm_lattice* L, double* rho, double* ux, double* uy, double totals[3])
+{
+    if (!L) return LBM_EINVAL;
+    if (!L->ready) return LBM_ESTATE;
+    const size_t n = (size_t)L->nx * L->ny;
+    DevScratch d;
+    hipError_t e = (rho || ux || uy) ? d.alloc(3 * n) : hipSuccess;
+    if (e != hipSuccess) return status_of(e);
+    double* dp[3] = {rho ? d.p : nullptr, ux ? d.p + n : nullptr, uy ? d.p + 2 * n : nullptr};
+    int st = lbm_moments_device(L, dp[0], dp[1], dp[2], totals);
+    if (st != LBM_OK && st != LBM_ENONFINITE) return st;
+    double* host[3] = {rho, ux, uy};
+    for (int c = 0; c < 3 && e == hipSuccess; ++c)
+        if (host[c]) e = hipMemcpyAsync(host[c], dp[c], n * sizeof(double), hipMemcpyDeviceToHost, L->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+    return e != hipSuccess ? status_of(e) : st;
+}
+
+int lbm_get_f(lbm_lattice* L, double* f)
+{
+    if (!L || !f) return LBM_EINVAL;
+    if (!L->ready) return LBM_ESTATE;
+    const size_t n = (size_t)9 * L->nx * L->ny;
+    DevScratch d;
+    hipError_t e = d.alloc(n);
+    if (e == hipSuccess) e = launch_get_f(L->dtype, L->cur, L->g, d.p, L->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(f, d.p, n * sizeof(double), hipMemcpyDeviceToHost, L->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+    return status_of(e);
+}
+
+int lbm_set_f(lbm_lattice* L, const double* f)
+{
+    if (!L || !f) return LBM_EINVAL;
+    const size_t n = (size_t)9 * L->nx * L->ny;
+    DevScratch d;
+    hipError_t e = d.alloc(n);
+    if (e == hipSuccess) e = hipMemcpyAsync(d.p, f, n * sizeof(double), hipMemcpyHostToDevice, L->stream);
+    if (e == hipSuccess) e = launch_set_f(L->dtype, L->cur, L->g, d.p, L->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+    if (e != hipSuccess) return status_of(e);
+    L->t = 0;
+    L->ready = true;
+    return LBM_OK;
+}
+
+}  // extern "C"

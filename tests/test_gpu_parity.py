@@ -1,0 +1,144 @@
+"""GPU parity against the FP64 oracle (calls go through the C ABI via the
+ctypes binding). Tolerances: FP64 1e-12 and FP32 1e-5 max relative error in
+the full populations f after the stated steps; the shifted forms report and
+bound their error."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import c1_rho, max_rel_err, smooth_random_state
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_0707_2437_amd as lbm  # noqa: E402
+
+TOL = {"f64": 1e-12, "f32": 1e-5}
+
+
+def run_gpu(nx, ny, tau, c2, dtype, steps, fields, tile=None):
+    with lbm.Lattice(nx, ny, tau, c2, dtype) as L:
+        if tile:
+            L.set_tile(*tile)
+        L.init(*fields)
+        L.step(steps)
+        return L.get_f(), L.moments()
+
+
+def run_ref(nx, ny, tau, c2, steps, fields):
+    o = oracle.Oracle(nx, ny, tau, c2).init(*fields).step(steps)
+    return o.get_f(), o.moments()
+
+
+@pytest.mark.parametrize("c2", [1.0 / 3.0, 0.2])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_c1_parity_1000_steps(c2, dtype):
+    fields = (c1_rho(), None, None)
+    f, (rho, ux, uy, tot) = run_gpu(64, 64, 0.8, c2, dtype, 1000, fields)
+    fr, (rr, uxr, uyr, totr) = run_ref(64, 64, 0.8, c2, 1000, fields)
+    err = max_rel_err(f, fr)
+    print(f"C1 c2={c2:.4f} {dtype}: max rel err f = {err:.3e}")
+    assert err <= TOL[dtype]
+    assert np.max(np.abs(rho - rr)) <= 10 * TOL[dtype]
+    assert abs(tot[0] - totr[0]) <= 10 * TOL[dtype] * totr[0]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("nx,ny", [(3, 3), (3, 7), (7, 3), (5, 4), (65, 3), (130, 77), (300, 41)])
+def test_small_and_ragged_shapes(dtype, nx, ny):
+    fields = smooth_random_state(nx, ny, seed=nx * 1000 + ny)
+    f, _ = run_gpu(nx, ny, 0.7, 0.5, dtype, 60, fields)
+    fr, _ = run_ref(nx, ny, 0.7, 0.5, 60, fields)
+    assert max_rel_err(f, fr) <= TOL[dtype]
+
+
+TILES = {
+    "f64": [(1, 1, 1), (1, 1, 5), (1, 2, 7), (2, 1, 3), (2, 4, 64), (1, 4, 32)],
+    "f32": [(1, 1, 1), (1, 1, 4), (2, 1, 7), (4, 1, 3), (2, 2, 16), (4, 4, 32), (1, 4, 128)],
+}
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_results_bitwise_independent_of_tile(dtype):
+    """Several strips, chunks and a ragged tail for each shape; every tile
+    shape gives the same bits, and they match the oracle."""
+    nx, ny = 397, 131
+    fields = smooth_random_state(nx, ny, seed=7)
+    outs = [run_gpu(nx, ny, 0.65, 0.81, dtype, 40, fields, tile=t)[0] for t in TILES[dtype]]
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    fr, _ = run_ref(nx, ny, 0.65, 0.81, 40, fields)
+    assert max_rel_err(outs[0], fr) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "f32s", "f16s"])
+def test_rest_state_and_determinism(dtype):
+    with lbm.Lattice(33, 19, 0.6, 0.9, dtype) as L:
+        L.init()
+        f0 = L.get_f()
+        L.step(25)
+        f1 = L.get_f()
+        rho, ux, uy, tot = L.moments()
+    assert np.all(f1 == f1[:, :1, :1])  # uniform
+    assert np.all(ux == 0) and np.all(uy == 0)
+    if dtype != "f64":
+        assert np.array_equal(f0, f1)
+    fields = smooth_random_state(150, 70, seed=3)
+    a = run_gpu(150, 70, 0.7, 0.3, dtype, 30, fields)[0]
+    b = run_gpu(150, 70, 0.7, 0.3, dtype, 30, fields)[0]
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_translation_equivariance_bitwise(dtype):
+    nx, ny, sx, sy = 333, 150, 117, 61
+    rho, ux, uy = smooth_random_state(nx, ny, seed=11)
+    sh = lambda v: np.roll(np.roll(v, sy, axis=-2), sx, axis=-1)
+    a = run_gpu(nx, ny, 0.7, 0.6, dtype, 50, (rho, ux, uy))[0]
+    b = run_gpu(nx, ny, 0.7, 0.6, dtype, 50, (sh(rho), sh(ux), sh(uy)))[0]
+    assert np.array_equal(sh(a), b)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_checkpoint_resume_bitwise(dtype):
+    nx, ny = 200, 90
+    fields = smooth_random_state(nx, ny, seed=5)
+    with lbm.Lattice(nx, ny, 0.75, 0.45, dtype) as L:
+        L.init(*fields).step(40)
+        full = L.step(40).get_f()
+    with lbm.Lattice(nx, ny, 0.75, 0.45, dtype) as L:
+        L.init(*fields).step(40)
+        ck = L.get_f()
+    with lbm.Lattice(nx, ny, 0.75, 0.45, dtype) as L:
+        L.set_f(ck).step(40)
+        assert np.array_equal(L.get_f(), full)
+
+
+def test_nonfinite_total_detected():
+    rho = np.ones((16, 16))
+    rho[3, 4] = np.nan
+    with lbm.Lattice(16, 16, 0.8, 0.2, "f32") as L:
+        L.init(rho)
+        with pytest.raises(lbm.LBMError) as ei:
+            L.moments()
+        assert ei.value.status == lbm.ENONFINITE
+
+
+def test_step_before_init_is_state_error():
+    with lbm.Lattice(16, 16, 0.8, 0.2, "f64") as L:
+        with pytest.raises(lbm.LBMError) as ei:
+            L.step(1)
+        assert ei.value.status == lbm.ESTATE
+
+
+@pytest.mark.parametrize("dtype,tol", [("f32s", 1e-6), ("f16s", 2e-3)])
+def test_shifted_storage_error_bounded(dtype, tol):
+    fields = (c1_rho(), None, None)
+    f, _ = run_gpu(64, 64, 0.8, 0.2, dtype, 1000, fields)
+    fr, _ = run_ref(64, 64, 0.8, 0.2, 1000, fields)
+    err = max_rel_err(f, fr)
+    print(f"C1 c2=0.2 {dtype}: max rel err f = {err:.3e}")
+    assert err <= tol
