@@ -1,0 +1,189 @@
+"""Benchmark: MLUPS and HBM-roofline fraction of the variable-speed-of-sound
+D2Q9 step (Buick & Cosgrove, Sec. 3 Eq. 5) on one MI355X.
+
+Workload (one "step"): one time step of each of five periodic 4096 x 4096
+lattices, tau = 0.6, c^2 in {0.04, 0.2, 1/3, 0.5, 0.81} (c_e = 0.2 ... 0.9),
+each initialised with a plane sound wave of amplitude 1e-3 plus seeded
+uniform density noise +-1e-4. Headline: FP32 storage and arithmetic. The
+same sweep in FP64 is reported under "forms".
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Prints one JSON line. Inputs are initialised on the device before the timed
+region; the timed region holds exactly K steps, bracketed by
+torch.cuda.synchronize() and HIP events recorded on the stream the kernels
+run on.
+"""
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
+BYTES_PER_SITE = {"f64": 144, "f32": 72, "f32s": 72, "f16s": 36}  # 9 reads + 9 writes
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=1000)
+    p.add_argument("--warmup", type=int, default=20)
+    p.add_argument("--n", type=int, default=4096, help="lattice side")
+    p.add_argument("--forms", default="f64", help="extra forms to time, comma separated ('' for none)")
+    p.add_argument("--form-steps", type=int, default=300)
+    p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    p.add_argument("--cpu-steps", type=int, default=200)
+    p.add_argument("--copy-probe", action="store_true",
+                   help="only run a device copy of known size (reference for HBM byte counters)")
+    return p.parse_args()
+
+
+def make_sweep(lbm, workloads, torch, n, dtype, stream):
+    lattices = []
+    for k, c2 in enumerate(workloads.C2_SWEEP):
+        rho, ux, uy = workloads.plane_wave_fields(n, n, c2, seed=k)
+        L = lbm.Lattice(n, n, 0.6, c2, dtype)
+        L.set_stream(stream)
+        L.init(rho, ux, uy)
+        lattices.append(L)
+    return lattices
+
+
+def time_sweep(torch, lattices, steps, warmup, stream):
+    for _ in range(warmup):
+        for L in lattices:
+            L.step(1)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        for L in lattices:
+            L.step(1)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / 1e3, wall
+
+
+def measure_form(lbm, workloads, torch, n, dtype, steps, warmup):
+    # all launches go to one dedicated stream; the HIP events are recorded on it
+    stream = torch.cuda.Stream()
+    lats = make_sweep(lbm, workloads, torch, n, dtype, stream)
+    sec, wall = time_sweep(torch, lats, steps, warmup, stream)
+    tot = [L.totals() for L in lats]
+    for L in lats:
+        L.close()
+    sites = n * n * len(lats)
+    launches = steps * len(lats)
+    mlups = sites * steps / sec / 1e6
+    gbs = BYTES_PER_SITE[dtype] * n * n / (sec / launches) / 1e9
+    return {"mlups": mlups, "ms_per_step": 1e3 * sec / steps, "kernel_us": 1e6 * sec / launches,
+            "achieved_GBs": gbs, "frac": gbs / PEAK_HBM_GBS, "wall_s": wall,
+            "mass_total_first": tot[0][0]}
+
+
+def cpu_baseline(workloads, n, steps):
+    """The FP64 oracle on a bounded sample of the same workload: one of the
+    five lattices (c^2 = 0.2), `steps` steps, all host cores."""
+    import oracle
+
+    oracle.set_threads(0)
+    cores = oracle.get_threads()
+    rho, ux, uy = workloads.plane_wave_fields(n, n, 0.2, seed=1)
+    o = oracle.Oracle(n, n, 0.6, 0.2).init(rho, ux, uy)
+    o.step(1)  # page in
+    t0 = time.perf_counter()
+    o.step(steps)
+    sec = time.perf_counter() - t0
+    o.close()
+    return {"value": n * n * steps / sec / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "sample": f"FP64 oracle, one {n}x{n} lattice of the sweep (c^2 = 0.2, tau = 0.6), {steps} steps, "
+                      f"{sec:.1f} s on {cores} threads ({platform.processor() or platform.machine()})"}
+
+
+def copy_probe(torch):
+    """Device-to-device copy of 1 GiB, 20 times (reference kernel for the HBM
+    byte counters: 1 GiB read + 1 GiB written per dispatch)."""
+    nbytes = 1 << 30
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / 20
+    print(json.dumps({"copy_probe_bytes": 2 * nbytes, "copy_GBs": 2 * nbytes / sec / 1e9}), flush=True)
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); "
+              "the lattices of this workload are independent and would shard whole, "
+              "so N GPUs would report N times the one-GPU rate.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_0707_2437_amd as lbm
+    from paper_0707_2437_amd import workloads
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    if a.copy_probe:
+        copy_probe(torch)
+        return
+
+    n = a.n
+    head = measure_form(lbm, workloads, torch, n, "f32", a.steps, a.warmup)
+    forms = {"f32": head}
+    for f in [s for s in a.forms.split(",") if s]:
+        forms[f] = measure_form(lbm, workloads, torch, n, f, a.form_steps, a.warmup)
+        print(f"# form {f}: {forms[f]['mlups']:.0f} MLUPS, {100 * forms[f]['frac']:.1f}% of HBM peak",
+              file=sys.stderr, flush=True)
+
+    cpu = None if a.no_cpu else cpu_baseline(workloads, n, a.cpu_steps)
+    sweep = list(workloads.C2_SWEEP)
+    out = {
+        "metric": "MLUPS (lattice-site updates per second / 1e6), one MI355X",
+        "value": round(head["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(head["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"c2 sweep: 5 periodic {n}x{n} D2Q9 lattices, variable-speed-of-sound step",
+                   "lattice": [n, n], "lattices_per_step": len(sweep), "tau": 0.6,
+                   "c2": [round(c, 6) for c in sweep],
+                   "init": "plane sound wave amp 1e-3 + uniform density noise 1e-4 (seeded)"},
+        "roofline": {"bound": "hbm", "achieved": round(head["achieved_GBs"], 1), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(head["frac"], 4), "traffic": None,
+                     "kernel": "lbm::step_kernel<float,false,...>",
+                     "bytes_per_launch": BYTES_PER_SITE["f32"] * n * n,
+                     "avg_launch_us": round(head["kernel_us"], 2)},
+        "cpu_baseline": cpu,
+        "forms": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                  for k, v in forms.items()},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -104,9 +104,16 @@ int lbm_get_f(lbm_lattice* L, double* f);
 int lbm_set_f(lbm_lattice* L, const double* f);
 
 /* Use an existing HIP stream (hipStream_t, e.g. PyTorch's current stream)
- * for all later work on this lattice. NULL selects the library's own
- * stream. The caller keeps ownership of the stream. */
+ * for all later work on this lattice; NULL is the HIP null stream. The
+ * caller keeps ownership of the stream. Synchronises the previous stream. */
 int lbm_set_stream(lbm_lattice* L, void* hip_stream);
+
+/* Return to the library's own (non-blocking) stream, the default after
+ * lbm_create. Synchronises the previous stream. */
+int lbm_use_own_stream(lbm_lattice* L);
+
+/* The HIP stream the lattice currently launches on (NULL for a NULL handle). */
+void* lbm_get_stream(const lbm_lattice* L);
 
 /* Number of completed steps since init / set_f (-1 for NULL). */
 long long lbm_time(const lbm_lattice* L);
@@ -114,12 +121,22 @@ long long lbm_time(const lbm_lattice* L);
 /* Device bytes lbm_create allocates for this shape (0 if invalid). */
 size_t lbm_footprint_bytes(int nx, int ny, int dtype);
 
-/* Step tile shape: vx = sites per lane along x, nw = 64-lane waves per
- * workgroup, h = rows per workgroup. vx in {1, 2, 4, 8} (allowed values
- * depend on dtype), nw in {1, 2, 4}, h >= 1. Results do not depend on the
- * tile shape (bitwise). LBM_EINVAL for an unsupported shape. */
-int lbm_set_tile(lbm_lattice* L, int vx, int nw, int h);
-int lbm_get_tile(const lbm_lattice* L, int* vx, int* nw, int* h);
+/* Step kernel shape. vx = sites per lane along x (1, 2 or 4); flags =
+ * LBM_TILE_* bits. March form (default): nw = 64-lane waves per workgroup
+ * (1 or 4), each owning its own column strip of 64 * vx sites and marching
+ * h >= 1 rows. Vertical-stack form (LBM_TILE_VSTACK): nw = 4, 8 or 16 waves
+ * per workgroup covering one strip and nw - 2 rows (h is ignored).
+ * Results do not depend on the shape (bitwise). LBM_EINVAL for an
+ * unsupported shape. lbm_get_tile: any pointer may be NULL. */
+enum lbm_tile_flags {
+    LBM_TILE_PREFETCH = 1, /* issue the next row's loads before relaxing the current row */
+    LBM_TILE_NT_STORE = 2, /* non-temporal (streaming) stores                              */
+    LBM_TILE_ROWBAND = 4,  /* tile order: all strips of a row chunk before the next chunk  */
+    LBM_TILE_PREFETCH2 = 8, /* issue loads two rows ahead (overrides LBM_TILE_PREFETCH)     */
+    LBM_TILE_VSTACK = 16    /* vertical-stack form (no march; uses only LBM_TILE_NT_STORE)  */
+};
+int lbm_set_tile(lbm_lattice* L, int vx, int nw, int h, int flags);
+int lbm_get_tile(const lbm_lattice* L, int* vx, int* nw, int* h, int* flags);
 
 #ifdef __cplusplus
 }

@@ -36,10 +36,12 @@ SIGNATURES = {
     "lbm_get_f": (_i, [_vp, _vp]),
     "lbm_set_f": (_i, [_vp, _vp]),
     "lbm_set_stream": (_i, [_vp, _vp]),
+    "lbm_use_own_stream": (_i, [_vp]),
+    "lbm_get_stream": (_vp, [_vp]),
     "lbm_time": (ctypes.c_longlong, [_vp]),
     "lbm_footprint_bytes": (ctypes.c_size_t, [_i, _i, _i]),
-    "lbm_set_tile": (_i, [_vp, _i, _i, _i]),
-    "lbm_get_tile": (_i, [_vp, _vp, _vp, _vp]),
+    "lbm_set_tile": (_i, [_vp, _i, _i, _i, _i]),
+    "lbm_get_tile": (_i, [_vp, _vp, _vp, _vp, _vp]),
 }
 
 

@@ -6,12 +6,15 @@
 // gathers f_i(x, t) = S_i(x - e_i), relaxes it (Eq. 5, right-hand side) and
 // writes S'_i(x) aligned into the other buffer (A/B).
 //
-// Row layout: element (x, y) of plane i sits at
-//   i * plane + y * pitch + off + x,   x in [-1, nx]
-// where columns -1 and nx are ghost copies of columns nx-1 and 0 (written
-// by the step that writes those columns), so the +-1 column shifts of the
-// gather need no wrap test. `off` is one 128-byte line, so x = 0 is
-// line-aligned; `pitch` is a multiple of a line. Rows wrap in y by index.
+// Layout: element (x, y) of plane i sits at
+//   i * ps + y * rs + off + x,   x in [-2, nx + 1]
+// Columns -2, -1 are ghost copies of columns nx-2, nx-1 and columns nx,
+// nx+1 are copies of 0, 1 (written by the step that writes those columns),
+// so the +-1-shifted windows of the gather need no wrap test. `off` is one
+// 128-byte line, so x = 0 is line-aligned. Two layouts are supported:
+// plane-major (ps = plane size, rs = pitch) and row-interleaved (ps = pitch,
+// rs = 9 * pitch: the nine plane rows of a lattice row are contiguous).
+// Rows wrap in y by index.
 #pragma once
 
 #include <stdint.h>
@@ -22,9 +25,10 @@ constexpr int kMaxVX = 8;
 
 struct Geom {
     int nx, ny;
-    int pitch;        // elements per row
     int off;          // element offset of column 0 within a row
-    long long plane;  // elements per plane
+    int pitch;        // elements per row of one plane
+    long long rs;     // elements between rows y and y + 1 of a plane
+    long long ps;     // elements between planes i and i + 1
 };
 
 // Collision / source coefficients of Eq. 5 in the delta form used by the
@@ -43,8 +47,9 @@ struct StepTile {
     Geom g;
     Coef c;
     int h;        // rows per workgroup
-    int nstrips;  // column strips
+    int nstrips;  // column strip groups (one per workgroup)
     int nchunks;  // row chunks
+    int rowband;  // tile order: 1 = strip groups of a chunk first
 };
 
 }  // namespace lbm

@@ -6,23 +6,27 @@
 // per byte), so there is no matrix-core work: the kernel is organised for
 // coalesced row-contiguous traffic.
 //
-// Work decomposition of one step: the lattice is cut into column strips of
-// W = 64 * NW * VX sites and row chunks of h rows; one workgroup marches down
-// one (strip, chunk) tile row by row. For the current row it gathers the
-// nine pulled populations of every site with contiguous (possibly
-// one-element-misaligned) vector loads, keeps them in registers, and puts
-// the site density into an LDS ring so that the central-difference gradient
-// (Sec. 4) can read the x-neighbours; the y-neighbours' densities are the
-// previous and next rows of the march, kept in registers. Two lanes also
-// gather the density of the columns just left and right of the strip.
-// Every S value is read from HBM once per tile; only the two extra rows of a
-// chunk (the y-halo of the gradient) are read twice.
+// Work decomposition of one step: every 64-lane wave owns a column strip of
+// 64 * VX sites and marches down (or up) a chunk of h rows. For each row a
+// lane loads, per link plane, a window of VX + 2 consecutive stored values:
+// the pulled populations of its VX sites and of the sites just left and
+// right of them (neighbouring lanes' windows overlap, so the overlap is
+// served by the caches, not by HBM). It can therefore form the density of
+// its own sites and of both x-neighbours itself, and the central-difference
+// gradient (Sec. 4) needs no exchange between lanes: the y-neighbours'
+// densities are the previous and next rows of the march, kept in
+// registers. There is no LDS and no barrier; waves are independent. The
+// loads of the next row are issued before the current row is relaxed and
+// written (one row of prefetch). Only the two rows just outside a chunk are
+// read twice (by the waves of the two chunks that share them); alternate
+// chunks march in opposite directions so that both reads of a shared row
+// happen at the start (or both at the end) of the two marches, close in
+// time.
 //
 // Determinism: every site's arithmetic is the same code in the same order,
-// whatever the tile shape, so results are bitwise independent of the tile
-// (the density of a halo column is computed exactly as its owner computes
-// it). The build uses -ffp-contract=off; fused multiply-adds are written
-// explicitly.
+// whatever the tile shape or march direction, so results are bitwise
+// independent of the tile. The build uses -ffp-contract=off; fused
+// multiply-adds are written explicitly.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -57,11 +61,11 @@ template <class T, bool SHIFT, class C> __device__ __forceinline__ T from_d(C d,
 template <class T, int VX> struct Pack { T v[VX]; };
 
 // Memory is addressed as a per-plane base pointer (uniform, computed once
-// per workgroup, held in scalar registers) plus a 32-bit byte offset
-// (row offset + lane offset), which maps to SGPR-based global loads and
-// stores. Only element alignment is assumed: planes 1, 3, 5-8 are read one
-// element off a vector boundary, and gfx950 executes such dwordx2/x4 loads
-// directly. A plane is limited to 4 GiB (checked at create).
+// per workgroup, held in scalar registers) plus a 32-bit byte offset (row
+// offset + lane offset), which maps to SGPR-based global loads and stores;
+// the lattice is created only if those offsets fit in 32 bits. Only element
+// alignment is assumed: the windows start one element off a vector
+// boundary, and gfx950 executes such dwordx2/x3/x4 loads directly.
 template <class T, int VX> __device__ __forceinline__ Pack<T, VX> ld_vec(const char* base, unsigned byte_off)
 {
     Pack<T, VX> r;
@@ -85,33 +89,31 @@ template <class T, bool SHIFT, class C> __device__ __forceinline__ C d_of(KeepT<
     else return v;
 }
 
-// Gather f_i(x + j, r) = S_i(x + j - e_ix, r - e_iy), j < VX.
-// Links (Sec. 2): e_0 (0,0); e_1 (1,0); e_2 (0,1); e_3 (-1,0); e_4 (0,-1);
-// e_5 (1,1); e_6 (-1,1); e_7 (-1,-1); e_8 (1,-1).
-// pb[i] points at column -1 of row 0 of plane i, so the byte offset of
-// column x - e_ix in row q is (q * pitch + x + 1 - e_ix) * sizeof(T) >= 0.
-template <class T, bool SHIFT, int VX, class C>
-__device__ __forceinline__ void gather(const char* const (&pb)[9], const Geom& g, int r, int x, KeepT<T, C> d[9][VX])
+// Window gather: for the VX sites at columns x .. x+VX-1 of row r, load
+// per plane i the stored values S_i(c - e_ix, r - e_iy) for the VX + 2
+// columns c = x-1 .. x+VX, i.e. f_i of those columns (Eq. 5, left-hand
+// side). Links (Sec. 2): e_0 (0,0); e_1 (1,0); e_2 (0,1); e_3 (-1,0);
+// e_4 (0,-1); e_5 (1,1); e_6 (-1,1); e_7 (-1,-1); e_8 (1,-1).
+// pb[i] points at column -2 of row 0 of plane i; the byte offset of column
+// x - 1 - e_ix in row q is (q * rs + x + 1 - e_ix) * sizeof(T) >= 0.
+template <class T, int NV>
+__device__ __forceinline__ void gather_raw(const char* const (&pb)[9], const Geom& g, int r, int x, Pack<T, NV> (&v)[9])
 {
     constexpr unsigned es = sizeof(T);
-    const unsigned om = (unsigned)wrapy(r - 1, g.ny) * (unsigned)g.pitch * es;  // source row r - 1 (e_iy = +1)
-    const unsigned o0 = (unsigned)wrapy(r, g.ny) * (unsigned)g.pitch * es;      // source row r     (e_iy =  0)
-    const unsigned op = (unsigned)wrapy(r + 1, g.ny) * (unsigned)g.pitch * es;  // source row r + 1 (e_iy = -1)
-    const unsigned xm = (unsigned)x * es, x0 = xm + es, xp = xm + 2 * es;       // columns x-1, x, x+1
-    Pack<T, VX> v[9];
-    v[0] = ld_vec<T, VX>(pb[0], o0 + x0);
-    v[1] = ld_vec<T, VX>(pb[1], o0 + xm);
-    v[2] = ld_vec<T, VX>(pb[2], om + x0);
-    v[3] = ld_vec<T, VX>(pb[3], o0 + xp);
-    v[4] = ld_vec<T, VX>(pb[4], op + x0);
-    v[5] = ld_vec<T, VX>(pb[5], om + xm);
-    v[6] = ld_vec<T, VX>(pb[6], om + xp);
-    v[7] = ld_vec<T, VX>(pb[7], op + xp);
-    v[8] = ld_vec<T, VX>(pb[8], op + xm);
-#pragma unroll
-    for (int i = 0; i < 9; ++i)
-#pragma unroll
-        for (int j = 0; j < VX; ++j) d[i][j] = keep_of<T, SHIFT, C>(v[i].v[j], i);
+    const unsigned rs = (unsigned)g.rs * es;
+    const unsigned om = (unsigned)wrapy(r - 1, g.ny) * rs;  // source row r - 1 (e_iy = +1)
+    const unsigned o0 = (unsigned)wrapy(r, g.ny) * rs;      // source row r     (e_iy =  0)
+    const unsigned op = (unsigned)wrapy(r + 1, g.ny) * rs;  // source row r + 1 (e_iy = -1)
+    const unsigned xm = (unsigned)x * es, x0 = xm + es, xp = xm + 2 * es;  // window starts for e_ix = +1, 0, -1
+    v[0] = ld_vec<T, NV>(pb[0], o0 + x0);
+    v[1] = ld_vec<T, NV>(pb[1], o0 + xm);
+    v[2] = ld_vec<T, NV>(pb[2], om + x0);
+    v[3] = ld_vec<T, NV>(pb[3], o0 + xp);
+    v[4] = ld_vec<T, NV>(pb[4], op + x0);
+    v[5] = ld_vec<T, NV>(pb[5], om + xm);
+    v[6] = ld_vec<T, NV>(pb[6], om + xp);
+    v[7] = ld_vec<T, NV>(pb[7], op + xp);
+    v[8] = ld_vec<T, NV>(pb[8], op + xm);
 }
 
 // delta rho = sum_i d_i (Eq. 3), one fixed order for every code path.
@@ -172,89 +174,106 @@ __device__ __forceinline__ void collide(const KeepT<T, C> dk[9][VX], int j, C dr
     pair(6, 8, uy - ux, gy - gx, k.wo2, k.as2);
 }
 
-template <class T, bool SHIFT, int VX, int NW>
+template <class T, bool SHIFT, int VX, int NW, int PF, bool NTS>
 __global__ __launch_bounds__(64 * NW) void step_kernel(StepTile a, int ntiles)
 {
     using C = typename CompT<T>::type;
     using K = KeepT<T, C>;
-    constexpr int NT = 64 * NW;
-    constexpr int W = NT * VX;
-    __shared__ C ring[4][W + 2];  // delta rho of rows; [0] and [wv+1] are the halo columns
+    constexpr int WV = VX + 2;  // window: columns x-1 .. x+VX
+    using R = Pack<T, WV>;
 
     // XCD-aware tile order: consecutive blocks go round-robin over the 8
-    // XCDs, so give each XCD a contiguous run of tiles (vertically adjacent
-    // chunks of a strip share their halo rows in that XCD's L2).
+    // XCDs, so give each XCD a contiguous run of tiles. In row-band order
+    // (LBM_TILE_ROWBAND) tiles run over the strip groups of a chunk first:
+    // when the grid is larger than what is resident, each XCD then sweeps a
+    // band of consecutive rows through memory (DRAM page locality), and the
+    // boundary rows two vertically adjacent chunks share are read by
+    // co-resident workgroups of one XCD (the second read hits its L2).
+    // Otherwise tiles run over the chunks of a strip group first.
     const int nb = gridDim.x;  // a multiple of 8
     const int b = blockIdx.x;
     const int t = (b & 7) * (nb >> 3) + (b >> 3);
     if (t >= ntiles) return;
-    const int strip = t / a.nchunks;
-    const int chunk = t - strip * a.nchunks;
+    const int ngroups = ntiles / a.nchunks;
+    int group, chunk;
+    if (a.rowband) {
+        chunk = t / ngroups;
+        group = t - chunk * ngroups;
+    } else {
+        group = t / a.nchunks;
+        chunk = t - group * a.nchunks;
+    }
+    const int strip = group * NW + (int)(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     const Geom g = a.g;
+    const int x = strip * (64 * VX) + lane * VX;
+    const int nv = min(VX, g.nx - x);
+    if (nv <= 0) return;  // no barrier below: lanes past the edge simply leave
     const CoefC<C> k = coef_c<C>(a.c);
-    const int xs = strip * W;
-    const int wv = min(W, g.nx - xs);
-    const int y0 = chunk * a.h;
-    const int y1 = min(y0 + a.h, g.ny);
-    const int tid = threadIdx.x;
-    const int lx = tid * VX;
-    const int x = xs + lx;
-    const int nv = min(VX, wv - lx);
-    // per-plane bases: source at column -1, destination at column 0
+    const int ylo = chunk * a.h;
+    const int yhi = min(ylo + a.h, g.ny);
+    const int dir = (chunk & 1) ? -1 : 1;  // alternate chunks march upward
+    const int ys = dir > 0 ? ylo : yhi - 1;
+    const int nrow = yhi - ylo;
+
+    // per-plane bases: source at column -2, destination at column 0
     const char* sb[9];
     char* dbase[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-        sb[i] = (const char*)a.src + ((long long)i * g.plane + g.off - 1) * (long long)sizeof(T);
-        dbase[i] = (char*)a.dst + ((long long)i * g.plane + g.off) * (long long)sizeof(T);
+        sb[i] = (const char*)a.src + ((long long)i * g.ps + g.off - 2) * (long long)sizeof(T);
+        dbase[i] = (char*)a.dst + ((long long)i * g.ps + g.off) * (long long)sizeof(T);
     }
 
-    const bool hl = tid == NT - 1, hr = tid == NT - 2;
-    const int xh = hl ? (xs == 0 ? g.nx - 1 : xs - 1) : (xs + wv == g.nx ? 0 : xs + wv);
-    const int hpos = hl ? 0 : wv + 1;
+    K da[9][VX], db[9][VX];        // populations of the current and next row (own columns)
+    C wa[WV], wb[WV];              // densities of the current and next row, window columns
+    C rprev[VX];                   // densities of the previous row, own columns
+    R ra[9], rb[9];                // loads in flight (PF rows ahead)
 
-    K da[9][VX], db[9][VX];
-    C rp[VX], rc[VX], rn[VX];
-
-    // Density of row r at this lane's columns into rr[] and the ring, and of
-    // the halo column (two lanes).
-    auto gather_row = [&](int r, K (&d)[9][VX], C (&rr)[VX], bool to_ring) {
-        if (nv > 0) {
-            gather<T, SHIFT, VX, C>(sb, g, r, x, d);
+    // Land a window row: populations of the own columns, densities of all
+    // window columns (same summation order as every other code path).
+    auto land = [&](const R (&v)[9], K (&d)[9][VX], C (&w)[WV]) {
+        K tmp[9][WV];
 #pragma unroll
-            for (int j = 0; j < VX; ++j) {
-                rr[j] = drho_of<T, SHIFT, C, VX>(d, j);
-                if (to_ring && j < nv) ring[r & 3][lx + 1 + j] = rr[j];
-            }
-        }
-        if (to_ring && (hl || hr)) {
-            K h[9][1];
-            gather<T, SHIFT, 1, C>(sb, g, r, xh, h);
-            ring[r & 3][hpos] = drho_of<T, SHIFT, C, 1>(h, 0);
-        }
+        for (int i = 0; i < 9; ++i)
+#pragma unroll
+            for (int j = 0; j < WV; ++j) tmp[i][j] = keep_of<T, SHIFT, C>(v[i].v[j], i);
+#pragma unroll
+        for (int j = 0; j < WV; ++j) w[j] = drho_of<T, SHIFT, C, WV>(tmp, j);
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+#pragma unroll
+            for (int j = 0; j < VX; ++j) d[i][j] = tmp[i][j + 1];
     };
 
-    // Collide row y (populations dc) and write it.
-    auto collide_row = [&](int y, const K (&dc)[9][VX]) {
-        if (nv <= 0) return;
-        const C* rr = ring[y & 3];
+    constexpr unsigned es = sizeof(T);
+    auto collide_row = [&](int y, const K (&dc)[9][VX], const C (&wc)[WV], const C (&wn)[WV]) {
         Pack<T, VX> out[9];
 #pragma unroll
         for (int j = 0; j < VX; ++j) {
-            // central differences at time t (Sec. 4)
-            const C gx = C(0.5) * (rr[lx + j + 2] - rr[lx + j]);
-            const C gy = C(0.5) * (rn[j] - rp[j]);
+            // central differences at time t (Sec. 4); y +- 1 are the march's
+            // next / previous rows in the order of the march direction
+            const C gx = C(0.5) * (wc[j + 2] - wc[j]);
+            const C up = wn[j + 1], dw = rprev[j];
+            const C gy = dir > 0 ? C(0.5) * (up - dw) : C(0.5) * (dw - up);
             C o[9];
-            collide<T, SHIFT, C, VX>(dc, j, rc[j], gx, gy, k, o);
+            collide<T, SHIFT, C, VX>(dc, j, wc[j + 1], gx, gy, k, o);
 #pragma unroll
             for (int i = 0; i < 9; ++i) out[i].v[j] = from_d<T, SHIFT, C>(o[i], i);
         }
-        constexpr unsigned es = sizeof(T);
-        const unsigned ro = (unsigned)y * (unsigned)g.pitch * es;  // row y, column 0
+        const unsigned ro = (unsigned)y * ((unsigned)g.rs * es);  // row y, column 0
         const unsigned lo = ro + (unsigned)x * es;
         if (nv == VX) {
 #pragma unroll
-            for (int i = 0; i < 9; ++i) __builtin_memcpy(dbase[i] + (size_t)lo, &out[i], sizeof(out[i]));
+            for (int i = 0; i < 9; ++i) {
+                if constexpr (NTS) {
+#pragma unroll
+                    for (int j = 0; j < VX; ++j)
+                        __builtin_nontemporal_store(out[i].v[j], (T*)(dbase[i] + (size_t)(lo + j * es)));
+                } else {
+                    __builtin_memcpy(dbase[i] + (size_t)lo, &out[i], sizeof(out[i]));
+                }
+            }
         } else {
 #pragma unroll
             for (int i = 0; i < 9; ++i)
@@ -262,49 +281,185 @@ __global__ __launch_bounds__(64 * NW) void step_kernel(StepTile a, int ntiles)
                 for (int j = 0; j < VX; ++j)
                     if (j < nv) __builtin_memcpy(dbase[i] + (size_t)(lo + j * es), &out[i].v[j], es);
         }
-        // ghost columns: -1 holds column nx-1, nx holds column 0
-        const int jl = g.nx - 1 - x;
-        if (jl >= 0 && jl < nv) {
+        // ghost columns: -2, -1 hold columns nx-2, nx-1; nx, nx+1 hold 0, 1
+        // (for nx = 3, column 1 is both nx-2 and 1 and has two ghosts)
 #pragma unroll
-            for (int j = 0; j < VX; ++j)
-                if (j == jl)
+        for (int j = 0; j < VX; ++j) {
+            const int c = x + j;
+            if (j < nv && c >= g.nx - 2) {
 #pragma unroll
-                    for (int i = 0; i < 9; ++i) __builtin_memcpy(dbase[i] + (size_t)ro - es, &out[i].v[j], es);
-        }
-        if (x == 0) {
+                for (int i = 0; i < 9; ++i)  // column c - nx in [-2, -1]
+                    __builtin_memcpy(dbase[i] - 2 * es + (size_t)(ro + (unsigned)(c - g.nx + 2) * es), &out[i].v[j], es);
+            }
+            if (j < nv && c <= 1) {
 #pragma unroll
-            for (int i = 0; i < 9; ++i)
-                __builtin_memcpy(dbase[i] + (size_t)(ro + (unsigned)g.nx * es), &out[i].v[0], es);
+                for (int i = 0; i < 9; ++i)  // column c + nx in [nx, nx + 1]
+                    __builtin_memcpy(dbase[i] + (size_t)(ro + (unsigned)(c + g.nx) * es), &out[i].v[j], es);
+            }
         }
     };
 
-    // March: entering row y, the populations of row y are in registers,
-    // rp/rc hold the densities of rows y-1 and y, and ring[y & 3] holds
-    // row y's densities with its halo.
-    gather_row(y0 - 1, db, rp, false);
-    gather_row(y0, da, rc, true);
-    auto advance = [&](int y, K (&dc)[9][VX], K (&dn)[9][VX]) {
-        gather_row(y + 1, dn, rn, true);
-        __syncthreads();
-        collide_row(y, dc);
+    // March. Entering row y (the k-th of the chunk): row y's populations and
+    // window densities are in registers, rprev holds the densities of the
+    // row before it, and the loads of the next PF rows are in flight. Each
+    // iteration lands row y + dir, issues the loads of row y + (PF+1) dir,
+    // then relaxes and writes row y. The loop is unrolled by two so the
+    // register sets alternate roles instead of being copied.
+    {
+        K dt[9][VX];
+        C wt[WV];
+        gather_raw<T, WV>(sb, g, ys - dir, x, ra);
+        land(ra, dt, wt);
 #pragma unroll
-        for (int j = 0; j < VX; ++j) {
-            rp[j] = rc[j];
-            rc[j] = rn[j];
-        }
-    };
-    int y = y0;
-    for (; y + 1 < y1; y += 2) {
-        advance(y, da, db);
-        advance(y + 1, db, da);
+        for (int j = 0; j < VX; ++j) rprev[j] = wt[j + 1];
+        gather_raw<T, WV>(sb, g, ys, x, ra);
+        land(ra, da, wa);
     }
-    if (y < y1) advance(y, da, db);
+    if constexpr (PF >= 1) gather_raw<T, WV>(sb, g, ys + dir, x, ra);
+    if constexpr (PF >= 2) {
+        if (nrow >= 2) gather_raw<T, WV>(sb, g, ys + 2 * dir, x, rb);
+    }
+    auto advance = [&](int kk, K (&dc)[9][VX], K (&dn)[9][VX], C (&wc)[WV], C (&wn)[WV], R (&rl)[9]) {
+        const int y = ys + dir * kk;
+        if constexpr (PF == 0) gather_raw<T, WV>(sb, g, y + dir, x, rl);
+        land(rl, dn, wn);
+        if constexpr (PF >= 1) {
+            if (kk + PF + 1 <= nrow) gather_raw<T, WV>(sb, g, y + (PF + 1) * dir, x, rl);
+        }
+        collide_row(y, dc, wc, wn);
+#pragma unroll
+        for (int j = 0; j < VX; ++j) rprev[j] = wc[j + 1];
+    };
+    // the raw buffer landed at step kk is ra for even kk when PF != 2
+    int kk = 0;
+    for (; kk + 1 < nrow; kk += 2) {
+        advance(kk, da, db, wa, wb, ra);
+        advance(kk + 1, db, da, wb, wa, PF == 2 ? rb : ra);
+    }
+    if (kk < nrow) advance(kk, da, db, wa, wb, ra);
+}
+
+// Vertical-stack form of the same step. A workgroup of R + 2 waves covers
+// one column strip of 64 * VX sites and R consecutive rows y0 .. y0+R-1:
+// wave w handles row y0 - 1 + w, so waves 0 and R + 1 take the rows just
+// outside the group, whose densities the gradient needs. Every wave loads
+// its row's windows (one row, all loads issued at once), forms the window
+// densities, publishes its own columns' densities in LDS, and after one
+// barrier the R interior waves read the densities of the rows above and
+// below, relax and write. All rows of the group are in flight together and
+// consecutive workgroups (row-band order) cover adjacent strips of the same
+// rows, so the set of rows being streamed at any time stays compact. Each
+// row is read (R + 2) / R times; the extra reads of the boundary rows are
+// served by L2 when the neighbouring group is resident on the same XCD.
+template <class T, bool SHIFT, int VX, int NW, bool NTS>
+__global__ __launch_bounds__(64 * NW) void step_vstack_kernel(StepTile a, int ntiles)
+{
+    using C = typename CompT<T>::type;
+    using K = KeepT<T, C>;
+    constexpr int WV = VX + 2;
+    constexpr int R = NW - 2;  // interior rows per workgroup
+    using Rw = Pack<T, WV>;
+    __shared__ C lds[NW][64 * VX];
+
+    const int nb = gridDim.x;  // a multiple of 8
+    const int b = blockIdx.x;
+    const int t = (b & 7) * (nb >> 3) + (b >> 3);  // contiguous run of tiles per XCD
+    if (t >= ntiles) return;
+    const int strip = t % a.nstrips;  // row-band order: strips of a group first
+    const int grp = t / a.nstrips;
+    const Geom g = a.g;
+    const int wave = (int)(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int y0 = grp * R;
+    const int nrows = min(R, g.ny - y0);
+    const int y = y0 - 1 + wave;  // in [-1, ny + R - 1]; rows wrap by index
+    const int x = strip * (64 * VX) + lane * VX;
+    const int nv = min(VX, g.nx - x);
+    const bool active = nv > 0 && wave <= nrows + 1;  // waves past the bottom halo idle
+
+    const char* sb[9];
+    char* dbase[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        sb[i] = (const char*)a.src + ((long long)i * g.ps + g.off - 2) * (long long)sizeof(T);
+        dbase[i] = (char*)a.dst + ((long long)i * g.ps + g.off) * (long long)sizeof(T);
+    }
+
+    K d[9][VX];
+    C w[WV];
+    if (active) {
+        Rw raw[9];
+        gather_raw<T, WV>(sb, g, y, x, raw);
+        K tmp[9][WV];
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+#pragma unroll
+            for (int j = 0; j < WV; ++j) tmp[i][j] = keep_of<T, SHIFT, C>(raw[i].v[j], i);
+#pragma unroll
+        for (int j = 0; j < WV; ++j) w[j] = drho_of<T, SHIFT, C, WV>(tmp, j);
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+#pragma unroll
+            for (int j = 0; j < VX; ++j) d[i][j] = tmp[i][j + 1];
+#pragma unroll
+        for (int j = 0; j < VX; ++j) lds[wave][lane * VX + j] = w[j + 1];
+    }
+    __syncthreads();
+    if (!active || wave == 0 || wave > nrows) return;
+
+    const CoefC<C> k = coef_c<C>(a.c);
+    constexpr unsigned es = sizeof(T);
+    Pack<T, VX> out[9];
+#pragma unroll
+    for (int j = 0; j < VX; ++j) {
+        // central differences at time t (Sec. 4)
+        const C gx = C(0.5) * (w[j + 2] - w[j]);
+        const C gy = C(0.5) * (lds[wave + 1][lane * VX + j] - lds[wave - 1][lane * VX + j]);
+        C o[9];
+        collide<T, SHIFT, C, VX>(d, j, w[j + 1], gx, gy, k, o);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) out[i].v[j] = from_d<T, SHIFT, C>(o[i], i);
+    }
+    const unsigned ro = (unsigned)y * ((unsigned)g.rs * es);  // row y, column 0
+    const unsigned lo = ro + (unsigned)x * es;
+    if (nv == VX) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            if constexpr (NTS) {
+#pragma unroll
+                for (int j = 0; j < VX; ++j)
+                    __builtin_nontemporal_store(out[i].v[j], (T*)(dbase[i] + (size_t)(lo + j * es)));
+            } else {
+                __builtin_memcpy(dbase[i] + (size_t)lo, &out[i], sizeof(out[i]));
+            }
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+#pragma unroll
+            for (int j = 0; j < VX; ++j)
+                if (j < nv) __builtin_memcpy(dbase[i] + (size_t)(lo + j * es), &out[i].v[j], es);
+    }
+    // ghost columns: -2, -1 hold columns nx-2, nx-1; nx, nx+1 hold 0, 1
+#pragma unroll
+    for (int j = 0; j < VX; ++j) {
+        const int c = x + j;
+        if (j < nv && c >= g.nx - 2) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                __builtin_memcpy(dbase[i] - 2 * es + (size_t)(ro + (unsigned)(c - g.nx + 2) * es), &out[i].v[j], es);
+        }
+        if (j < nv && c <= 1) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                __builtin_memcpy(dbase[i] + (size_t)(ro + (unsigned)(c + g.nx) * es), &out[i].v[j], es);
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
 // Set-up and read-out kernels (one thread per element; not on the hot path).
 
-__device__ __forceinline__ int wrapx(int x, int n) { return x < 0 ? x + n : (x >= n ? x - n : x); }
+__device__ __forceinline__ int wrapx2(int x, int n) { return x < 0 ? x + n : (x >= n ? x - n : x); }  // x in [-n, 2n)
 
 __device__ __constant__ int kEX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 __device__ __constant__ int kEY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
@@ -353,32 +508,32 @@ __device__ __forceinline__ RowIdx row_idx(const Geom& g, int w)
     return r;
 }
 
-// S_i(x, y) = feq_i(rho, u at (x + e_i, y + e_i)) for x in [-1, nx]:
+// S_i(x, y) = feq_i(rho, u at (x + e_i, y + e_i)) for x in [-2, nx + 1]:
 // the pulled gather of the first step then sees f_i(x, 0) = feq_i(x).
 template <class T, bool SHIFT>
 __global__ void init_kernel(T* __restrict__ s, Geom g, const double* __restrict__ rho, const double* __restrict__ ux,
                             const double* __restrict__ uy)
 {
-    const RowIdx ri = row_idx(g, g.nx + 2);
+    const RowIdx ri = row_idx(g, g.nx + 4);
     if (!ri.ok) return;
-    const int i = ri.i, y = ri.y, xx = ri.col - 1;  // -1 .. nx
-    const int sx = wrapx(xx + kEX[i], g.nx), sy = wrapy(y + kEY[i], g.ny);
+    const int i = ri.i, y = ri.y, xx = ri.col - 2;  // -2 .. nx + 1
+    const int sx = wrapx2(xx + kEX[i], g.nx), sy = wrapy(y + kEY[i], g.ny);
     const long long q = (long long)sy * g.nx + sx;
     const double r = rho ? rho[q] : 1.0, vx = ux ? ux[q] : 0.0, vy = uy ? uy[q] : 0.0;
     T v;
     if constexpr (SHIFT) v = (T)dfeq(i, r, vx, vy);
     else v = (T)feq(i, r, vx, vy);
-    s[i * g.plane + (long long)y * g.pitch + g.off + xx] = v;
+    s[i * g.ps + (long long)y * g.rs + g.off + xx] = v;
 }
 
-// S_i(x) = f_i(x + e_i) from a canonical FP64 array [9][ny][nx].
+// S_i(x) = f_i(x + e_i), x in [-2, nx + 1], from a canonical FP64 array [9][ny][nx].
 template <class T, bool SHIFT> __global__ void set_f_kernel(T* __restrict__ s, Geom g, const double* __restrict__ f)
 {
-    const RowIdx ri = row_idx(g, g.nx + 2);
+    const RowIdx ri = row_idx(g, g.nx + 4);
     if (!ri.ok) return;
-    const int i = ri.i, y = ri.y, xx = ri.col - 1;  // -1 .. nx
-    const int sx = wrapx(xx + kEX[i], g.nx), sy = wrapy(y + kEY[i], g.ny);
-    s[i * g.plane + (long long)y * g.pitch + g.off + xx] =
+    const int i = ri.i, y = ri.y, xx = ri.col - 2;  // -2 .. nx + 1
+    const int sx = wrapx2(xx + kEX[i], g.nx), sy = wrapy(y + kEY[i], g.ny);
+    s[i * g.ps + (long long)y * g.rs + g.off + xx] =
         store_f64<T, SHIFT>(f[((long long)i * g.ny + sy) * g.nx + sx], i);
 }
 
@@ -390,7 +545,7 @@ template <class T, bool SHIFT> __global__ void get_f_kernel(const T* __restrict_
     const int i = ri.i, y = ri.y, xx = ri.col;
     const int sy = wrapy(y - kEY[i], g.ny);
     f[((long long)i * g.ny + y) * g.nx + xx] =
-        load_f64<T, SHIFT>(s[i * g.plane + (long long)sy * g.pitch + g.off + xx - kEX[i]], i);
+        load_f64<T, SHIFT>(s[i * g.ps + (long long)sy * g.rs + g.off + xx - kEX[i]], i);
 }
 
 // Moments (Eq. 3) of f(x, t) in FP64, optional fields, and per-block
@@ -413,7 +568,7 @@ __global__ __launch_bounds__(kRedThreads) void moments_kernel(const T* __restric
         double vsum = 0.0;
         for (int i = 0; i < 9; ++i) {
             const int sy = wrapy(y - kEY[i], g.ny);
-            const double v = (double)s[i * g.plane + (long long)sy * g.pitch + g.off + x - kEX[i]];
+            const double v = (double)s[i * g.ps + (long long)sy * g.rs + g.off + x - kEX[i]];
             vsum += v;
             jx += v * kEX[i];
             jy += v * kEY[i];
@@ -461,51 +616,88 @@ __global__ __launch_bounds__(kRedThreads) void reduce_partials_kernel(const doub
 // ---------------------------------------------------------------------------
 // Host-side launchers.
 
-template <class T, bool SHIFT, int VX, int NW> static hipError_t launch_step_t(const StepTile& t, hipStream_t st)
+template <class T, bool SHIFT, int VX, int NW, int PF, bool NTS>
+static hipError_t launch_step_t(const StepTile& t, hipStream_t st)
 {
-    const int ntiles = t.nstrips * t.nchunks;
+    const int ntiles = t.nstrips * t.nchunks;  // nstrips counts groups of NW strips
     const int grid = (ntiles + 7) / 8 * 8;
-    hipLaunchKernelGGL((step_kernel<T, SHIFT, VX, NW>), dim3(grid), dim3(64 * NW), 0, st, t, ntiles);
+    hipLaunchKernelGGL((step_kernel<T, SHIFT, VX, NW, PF, NTS>), dim3(grid), dim3(64 * NW), 0, st, t, ntiles);
     return hipGetLastError();
 }
 
-template <class T, bool SHIFT, int VX> static hipError_t launch_nw(int nw, const StepTile& t, hipStream_t st)
+// flags: LBM_TILE_PREFETCH (1), LBM_TILE_NT_STORE (2), LBM_TILE_ROWBAND (4,
+// a runtime switch), LBM_TILE_PREFETCH2 (8: two rows ahead).
+template <class T, bool SHIFT, int VX, int NW>
+static hipError_t launch_flags(int flags, const StepTile& t, hipStream_t st)
 {
+    const int pf = (flags & 8) ? 2 : (flags & 1);
+    const bool nts = (flags & 2) != 0;
+    switch (pf * 2 + (nts ? 1 : 0)) {
+    case 0: return launch_step_t<T, SHIFT, VX, NW, 0, false>(t, st);
+    case 1: return launch_step_t<T, SHIFT, VX, NW, 0, true>(t, st);
+    case 2: return launch_step_t<T, SHIFT, VX, NW, 1, false>(t, st);
+    case 3: return launch_step_t<T, SHIFT, VX, NW, 1, true>(t, st);
+    case 4: return launch_step_t<T, SHIFT, VX, NW, 2, false>(t, st);
+    default: return launch_step_t<T, SHIFT, VX, NW, 2, true>(t, st);
+    }
+}
+
+template <class T, bool SHIFT, int VX, int NW>
+static hipError_t launch_vstack_t(int flags, const StepTile& t, hipStream_t st)
+{
+    const int ntiles = t.nstrips * t.nchunks;  // strips x row groups of NW - 2 rows
+    const int grid = (ntiles + 7) / 8 * 8;
+    if (flags & 2)
+        hipLaunchKernelGGL((step_vstack_kernel<T, SHIFT, VX, NW, true>), dim3(grid), dim3(64 * NW), 0, st, t, ntiles);
+    else
+        hipLaunchKernelGGL((step_vstack_kernel<T, SHIFT, VX, NW, false>), dim3(grid), dim3(64 * NW), 0, st, t, ntiles);
+    return hipGetLastError();
+}
+
+template <class T, bool SHIFT, int VX>
+static hipError_t launch_nw(int nw, int flags, const StepTile& t, hipStream_t st)
+{
+    if (flags & 16) {
+        switch (nw) {
+        case 4: return launch_vstack_t<T, SHIFT, VX, 4>(flags, t, st);
+        case 8: return launch_vstack_t<T, SHIFT, VX, 8>(flags, t, st);
+        case 16: return launch_vstack_t<T, SHIFT, VX, 16>(flags, t, st);
+        default: return hipErrorInvalidValue;
+        }
+    }
     switch (nw) {
-    case 1: return launch_step_t<T, SHIFT, VX, 1>(t, st);
-    case 2: return launch_step_t<T, SHIFT, VX, 2>(t, st);
-    case 4: return launch_step_t<T, SHIFT, VX, 4>(t, st);
+    case 1: return launch_flags<T, SHIFT, VX, 1>(flags, t, st);
+    case 4: return launch_flags<T, SHIFT, VX, 4>(flags, t, st);
     default: return hipErrorInvalidValue;
     }
 }
 
-bool step_shape_supported(int dtype, int vx, int nw)
+template <class T, bool SHIFT>
+static hipError_t launch_vx(int vx, int nw, int flags, const StepTile& t, hipStream_t st)
 {
-    if (nw != 1 && nw != 2 && nw != 4) return false;
-    switch (dtype) {
-    case 0: return vx == 1 || vx == 2;
-    case 1:
-    case 2: return vx == 1 || vx == 2 || vx == 4;
-    case 3: return vx == 2 || vx == 4 || vx == 8;
-    default: return false;
+    switch (vx) {
+    case 1: return launch_nw<T, SHIFT, 1>(nw, flags, t, st);
+    case 2: return launch_nw<T, SHIFT, 2>(nw, flags, t, st);
+    case 4: return launch_nw<T, SHIFT, 4>(nw, flags, t, st);
+    default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_step(int dtype, int vx, int nw, const StepTile& t, hipStream_t st)
+bool step_shape_supported(int dtype, int vx, int nw, int flags)
 {
-    if (!step_shape_supported(dtype, vx, nw)) return hipErrorInvalidValue;
+    if (dtype < 0 || dtype > 3 || !(vx == 1 || vx == 2 || vx == 4)) return false;
+    if (flags & 16) return nw == 4 || nw == 8 || nw == 16;
+    return nw == 1 || nw == 4;
+}
+
+hipError_t launch_step(int dtype, int vx, int nw, int flags, const StepTile& t, hipStream_t st)
+{
+    if (!step_shape_supported(dtype, vx, nw, flags)) return hipErrorInvalidValue;
     switch (dtype) {
-    case 0:
-        return vx == 1 ? launch_nw<double, false, 1>(nw, t, st) : launch_nw<double, false, 2>(nw, t, st);
-    case 1:
-        return vx == 1 ? launch_nw<float, false, 1>(nw, t, st)
-                       : (vx == 2 ? launch_nw<float, false, 2>(nw, t, st) : launch_nw<float, false, 4>(nw, t, st));
-    case 2:
-        return vx == 1 ? launch_nw<float, true, 1>(nw, t, st)
-                       : (vx == 2 ? launch_nw<float, true, 2>(nw, t, st) : launch_nw<float, true, 4>(nw, t, st));
-    case 3:
-        return vx == 2 ? launch_nw<_Float16, true, 2>(nw, t, st)
-                       : (vx == 4 ? launch_nw<_Float16, true, 4>(nw, t, st) : launch_nw<_Float16, true, 8>(nw, t, st));
+    case 0: return launch_vx<double, false>(vx, nw, flags, t, st);
+    case 1: return launch_vx<float, false>(vx, nw, flags, t, st);
+    case 2: return launch_vx<float, true>(vx, nw, flags, t, st);
+    case 3: return launch_vx<_Float16, true>(vx, nw, flags, t, st);
     }
     return hipErrorInvalidValue;
 }
@@ -529,7 +721,7 @@ hipError_t launch_init(int dtype, void* s, const Geom& g, const double* rho, con
                        hipStream_t st)
 {
     LBM_DISPATCH(dtype, {
-        hipLaunchKernelGGL((init_kernel<T, S>), plane_rows_grid(g, 2), dim3(256), 0, st, (T*)s, g, rho, ux, uy);
+        hipLaunchKernelGGL((init_kernel<T, S>), plane_rows_grid(g, 4), dim3(256), 0, st, (T*)s, g, rho, ux, uy);
         return hipGetLastError();
     })
 }
@@ -537,7 +729,7 @@ hipError_t launch_init(int dtype, void* s, const Geom& g, const double* rho, con
 hipError_t launch_set_f(int dtype, void* s, const Geom& g, const double* f, hipStream_t st)
 {
     LBM_DISPATCH(dtype, {
-        hipLaunchKernelGGL((set_f_kernel<T, S>), plane_rows_grid(g, 2), dim3(256), 0, st, (T*)s, g, f);
+        hipLaunchKernelGGL((set_f_kernel<T, S>), plane_rows_grid(g, 4), dim3(256), 0, st, (T*)s, g, f);
         return hipGetLastError();
     })
 }

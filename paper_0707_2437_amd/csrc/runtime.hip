@@ -11,8 +11,8 @@
 #include "liblbm.h"
 
 namespace lbm {
-hipError_t launch_step(int dtype, int vx, int nw, const StepTile& t, hipStream_t st);
-bool step_shape_supported(int dtype, int vx, int nw);
+hipError_t launch_step(int dtype, int vx, int nw, int flags, const StepTile& t, hipStream_t st);
+bool step_shape_supported(int dtype, int vx, int nw, int flags);
 hipError_t launch_init(int dtype, void* s, const Geom& g, const double* rho, const double* ux, const double* uy,
                        hipStream_t st);
 hipError_t launch_set_f(int dtype, void* s, const Geom& g, const double* f, hipStream_t st);
@@ -39,6 +39,7 @@ struct lbm_lattice {
     long long t;
     bool ready;
     int vx, nw, h;     // step tile
+    int kflags;        // LBM_TILE_* bits
 };
 
 namespace {
@@ -58,7 +59,27 @@ int esize_of(int dtype)
     }
 }
 
-Geom make_geom(int nx, int ny, int esize);
+Geom make_geom(int nx, int ny, int esize, bool interleaved);
+long long buffer_elems(const Geom& g);
+
+// True if the kernels' 32-bit byte offsets cover the lattice in this layout:
+// a plane (plane-major) or a whole buffer (row-interleaved).
+bool offsets_fit(int nx, int ny, int dtype, bool interleaved)
+{
+    const Geom g = make_geom(nx, ny, esize_of(dtype), interleaved);
+    const long long span = interleaved ? buffer_elems(g) : g.ps;
+    return (unsigned long long)(span + g.pitch) * esize_of(dtype) < (1ULL << 32);
+}
+
+// Layout of a new lattice: row-interleaved when it fits (it streams the nine
+// plane rows of a lattice row as one contiguous block), else plane-major.
+// LBM_LAYOUT=soa forces plane-major.
+bool choose_interleaved(int nx, int ny, int dtype)
+{
+    const char* e = std::getenv("LBM_LAYOUT");
+    if (e && std::strcmp(e, "soa") == 0) return false;
+    return offsets_fit(nx, ny, dtype, true);
+}
 
 bool args_ok(int nx, int ny, double tau, double c2, int dtype)
 {
@@ -67,36 +88,40 @@ bool args_ok(int nx, int ny, double tau, double c2, int dtype)
     if (nx < 3 || ny < 3 || !std::isfinite(tau) || !(tau > 0.5) || !std::isfinite(c2) || !(c2 > 0.0)) return false;
     if (esize_of(dtype) == 0) return false;
     if (nx > (1 << 28) || ny > (1 << 28)) return false;
-    // The kernels address a plane with 32-bit byte offsets.
-    const Geom g = make_geom(nx, ny, esize_of(dtype));
-    if ((unsigned long long)g.plane * esize_of(dtype) >= (1ULL << 32)) return false;
-    return true;
+    return offsets_fit(nx, ny, dtype, choose_interleaved(nx, ny, dtype));
 }
 
-// Row pitch leaves one line before column 0 (ghost column -1 at its end),
-// the ghost column nx, and room for the widest vector past the last column.
-Geom make_geom(int nx, int ny, int esize)
+// Row pitch leaves one line before column 0 (ghost columns -2, -1 at its
+// end), the ghost columns nx, nx+1, and room for the widest window past the
+// last column. Plane-major layout: planes rounded to 4 KiB plus a 1 KiB
+// skew; row-interleaved layout: rows of 9 * pitch.
+Geom make_geom(int nx, int ny, int esize, bool interleaved)
 {
     Geom g;
     g.nx = nx;
     g.ny = ny;
     const int line = kLineBytes / esize;
     g.off = line;
-    const long long need = (long long)line + nx + kMaxVX + 1;
+    const long long need = (long long)line + nx + kMaxVX + 4;
     g.pitch = (int)((need + line - 1) / line * line);
-    // Plane stride: rows of all planes, rounded to 4 KiB, plus a skew of
-    // 1 KiB so the nine concurrently streamed planes do not start on the
-    // same memory channel.
-    const long long bytes = (long long)g.pitch * ny * esize;
-    const long long pb = (bytes + 4095) / 4096 * 4096 + 1024;
-    g.plane = pb / esize;
+    if (interleaved) {
+        g.ps = g.pitch;
+        g.rs = 9LL * g.pitch;
+    } else {
+        const long long bytes = (long long)g.pitch * ny * esize;
+        g.ps = ((bytes + 4095) / 4096 * 4096 + 1024) / esize;
+        g.rs = g.pitch;
+    }
     return g;
 }
 
+// Elements of one population buffer (9 planes).
+long long buffer_elems(const Geom& g) { return g.rs == g.pitch ? 9 * g.ps : g.rs * g.ny; }
+
 size_t footprint(const Geom& g, int esize)
 {
-    // 2 buffers x 9 planes, plus one line of slack past the last plane.
-    return (size_t)2 * 9 * (size_t)g.plane * esize + kLineBytes;
+    // 2 buffers, plus one line of slack past the end.
+    return (size_t)2 * (size_t)buffer_elems(g) * esize + kLineBytes;
 }
 
 size_t red_doubles(const Geom& g) { return (size_t)3 * moments_blocks(g) + 3; }
@@ -116,20 +141,27 @@ Coef make_coef(double tau, double c2)
     return k;
 }
 
+int default_kflags()
+{
+    int f = LBM_TILE_PREFETCH | LBM_TILE_NT_STORE | LBM_TILE_ROWBAND;
+    if (const char* e = std::getenv("LBM_KFLAGS")) f = std::atoi(e) & 31;
+    return f;
+}
+
+// Defaults from tile sweeps on MI355X at 4096^2 (row-interleaved layout).
 void default_tile(int dtype, int* vx, int* nw, int* h)
 {
     switch (dtype) {
-    case LBM_F64: *vx = 1; break;
-    case LBM_F32:
-    case LBM_F32S: *vx = 2; break;
-    default: *vx = 4; break;
+    case LBM_F16S: *vx = 2; break;
+    default: *vx = 1; break;
     }
     *nw = 4;
-    *h = 32;
-    // Optional override for tile experiments: LBM_TILE="vx,nw,h".
+    *h = 8;
+    // Optional override for experiments: LBM_TILE="vx,nw,h".
     if (const char* e = std::getenv("LBM_TILE")) {
         int a = 0, b = 0, c = 0;
-        if (std::sscanf(e, "%d,%d,%d", &a, &b, &c) == 3 && step_shape_supported(dtype, a, b) && c > 0) {
+        if (std::sscanf(e, "%d,%d,%d", &a, &b, &c) == 3 && step_shape_supported(dtype, a, b, default_kflags()) &&
+            c > 0) {
             *vx = a;
             *nw = b;
             *h = c;
@@ -152,9 +184,17 @@ StepTile make_tile(const lbm_lattice* L)
     t.g = L->g;
     t.c = L->coef;
     t.h = L->h;
-    const int W = 64 * L->nw * L->vx;
-    t.nstrips = (L->nx + W - 1) / W;
-    t.nchunks = (L->ny + L->h - 1) / L->h;
+    if (L->kflags & LBM_TILE_VSTACK) {
+        // one strip of 64 * vx columns and nw - 2 rows per workgroup
+        const int W = 64 * L->vx, R = L->nw - 2;
+        t.nstrips = (L->nx + W - 1) / W;
+        t.nchunks = (L->ny + R - 1) / R;
+    } else {
+        const int W = 64 * L->nw * L->vx;  // columns of the NW strips of one workgroup
+        t.nstrips = (L->nx + W - 1) / W;
+        t.nchunks = (L->ny + L->h - 1) / L->h;
+    }
+    t.rowband = (L->kflags & LBM_TILE_ROWBAND) ? 1 : 0;
     return t;
 }
 
@@ -194,7 +234,7 @@ size_t lbm_footprint_bytes(int nx, int ny, int dtype)
 {
     if (!args_ok(nx, ny, 1.0, 1.0 / 3.0, dtype)) return 0;
     const int es = esize_of(dtype);
-    const Geom g = make_geom(nx, ny, es);
+    const Geom g = make_geom(nx, ny, es, choose_interleaved(nx, ny, dtype));
     return footprint(g, es) + red_doubles(g) * sizeof(double);
 }
 
@@ -215,9 +255,10 @@ lbm_lattice* lbm_create(int nx, int ny, double tau, double c2, int dtype)
     L->esize = esize_of(dtype);
     L->tau = tau;
     L->c2 = c2;
-    L->g = make_geom(nx, ny, L->esize);
+    L->g = make_geom(nx, ny, L->esize, choose_interleaved(nx, ny, dtype));
     L->coef = make_coef(tau, c2);
     default_tile(dtype, &L->vx, &L->nw, &L->h);
+    L->kflags = default_kflags();
     hipError_t e = hipGetDevice(&L->device);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&L->own, hipStreamNonBlocking);
     if (e != hipSuccess) {
@@ -237,7 +278,7 @@ lbm_lattice* lbm_create(int nx, int ny, double tau, double c2, int dtype)
         return nullptr;
     }
     L->cur = L->buf;
-    L->nxt = (char*)L->buf + (size_t)9 * L->g.plane * L->esize;
+    L->nxt = (char*)L->buf + (size_t)buffer_elems(L->g) * L->esize;
     g_last_error = LBM_OK;
     return L;
 }
@@ -245,7 +286,7 @@ lbm_lattice* lbm_create(int nx, int ny, double tau, double c2, int dtype)
 void lbm_destroy(lbm_lattice* L)
 {
     if (!L) return;
-    if (L->stream) (void)hipStreamSynchronize(L->stream);
+    if (L->own) (void)hipStreamSynchronize(L->stream);
     if (L->buf) (void)hipFree(L->buf);
     if (L->red) (void)hipFree(L->red);
     if (L->own) (void)hipStreamDestroy(L->own);
@@ -256,27 +297,40 @@ int lbm_set_stream(lbm_lattice* L, void* s)
 {
     if (!L) return LBM_EINVAL;
     hipError_t e = hipStreamSynchronize(L->stream);
-    L->stream = s ? (hipStream_t)s : L->own;
+    L->stream = (hipStream_t)s;
     return status_of(e);
 }
 
+int lbm_use_own_stream(lbm_lattice* L)
+{
+    if (!L) return LBM_EINVAL;
+    hipError_t e = hipStreamSynchronize(L->stream);
+    L->stream = L->own;
+    return status_of(e);
+}
+
+void* lbm_get_stream(const lbm_lattice* L) { return L ? (void*)L->stream : nullptr; }
+
 long long lbm_time(const lbm_lattice* L) { return L ? L->t : -1; }
 
-int lbm_set_tile(lbm_lattice* L, int vx, int nw, int h)
+int lbm_set_tile(lbm_lattice* L, int vx, int nw, int h, int flags)
 {
-    if (!L || h < 1 || !step_shape_supported(L->dtype, vx, nw)) return LBM_EINVAL;
+    if (!L || (flags & ~31) || !step_shape_supported(L->dtype, vx, nw, flags)) return LBM_EINVAL;
+    if (!(flags & LBM_TILE_VSTACK) && h < 1) return LBM_EINVAL;
     L->vx = vx;
     L->nw = nw;
     L->h = h;
+    L->kflags = flags;
     return LBM_OK;
 }
 
-int lbm_get_tile(const lbm_lattice* L, int* vx, int* nw, int* h)
+int lbm_get_tile(const lbm_lattice* L, int* vx, int* nw, int* h, int* flags)
 {
     if (!L) return LBM_EINVAL;
     if (vx) *vx = L->vx;
     if (nw) *nw = L->nw;
     if (h) *h = L->h;
+    if (flags) *flags = L->kflags;
     return LBM_OK;
 }
 
@@ -315,7 +369,7 @@ int lbm_step(lbm_lattice* L, int n)
     if (!L->ready) return LBM_ESTATE;
     for (int k = 0; k < n; ++k) {
         StepTile t = make_tile(L);
-        hipError_t e = launch_step(L->dtype, L->vx, L->nw, t, L->stream);
+        hipError_t e = launch_step(L->dtype, L->vx, L->nw, L->kflags, t, L->stream);
         if (e != hipSuccess) return status_of(e);
         void* tmp = L->cur;
         L->cur = L->nxt;

@@ -145,20 +145,31 @@ class Lattice:
         return self
 
     def set_stream(self, stream):
-        """Use a torch.cuda.Stream (or None for the library's own stream)."""
-        ptr = None if stream is None else ctypes.c_void_p(stream.cuda_stream)
-        _check(self._L.lbm_set_stream(self._h, ptr), "lbm_set_stream")
+        """Launch on a torch.cuda.Stream (its raw handle; 0 is the null
+        stream), or on the library's own stream when `stream` is None."""
+        if stream is None:
+            _check(self._L.lbm_use_own_stream(self._h), "lbm_use_own_stream")
+        else:
+            _check(self._L.lbm_set_stream(self._h, ctypes.c_void_p(stream.cuda_stream)), "lbm_set_stream")
         self._stream_ref = stream
         return self
 
-    def set_tile(self, vx, nw, h):
-        _check(self._L.lbm_set_tile(self._h, int(vx), int(nw), int(h)), "lbm_set_tile")
+    @property
+    def stream_handle(self):
+        return self._L.lbm_get_stream(self._h) or 0
+
+    def set_tile(self, vx, nw, h, flags=None):
+        """Kernel shape (see lbm_set_tile); flags default to the current ones."""
+        if flags is None:
+            flags = self.get_tile()[3]
+        _check(self._L.lbm_set_tile(self._h, int(vx), int(nw), int(h), int(flags)), "lbm_set_tile")
         return self
 
     def get_tile(self):
-        v, w, h = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-        _check(self._L.lbm_get_tile(self._h, ctypes.byref(v), ctypes.byref(w), ctypes.byref(h)), "lbm_get_tile")
-        return v.value, w.value, h.value
+        v, w, h, f = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(self._L.lbm_get_tile(self._h, ctypes.byref(v), ctypes.byref(w), ctypes.byref(h), ctypes.byref(f)),
+               "lbm_get_tile")
+        return v.value, w.value, h.value, f.value
 
     @property
     def time(self):

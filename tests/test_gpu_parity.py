@@ -56,8 +56,10 @@ def test_small_and_ragged_shapes(dtype, nx, ny):
 
 
 TILES = {
-    "f64": [(1, 1, 1), (1, 1, 5), (1, 2, 7), (2, 1, 3), (2, 4, 64), (1, 4, 32)],
-    "f32": [(1, 1, 1), (1, 1, 4), (2, 1, 7), (4, 1, 3), (2, 2, 16), (4, 4, 32), (1, 4, 128)],
+    "f64": [(1, 1, 1, 0), (1, 1, 5, 1), (1, 4, 7, 6), (2, 1, 3, 15), (2, 4, 64, 9), (4, 1, 32, 4), (4, 4, 2, 11),
+            (1, 4, 2, 13), (1, 4, 0, 18), (2, 8, 0, 16), (4, 16, 0, 18), (2, 16, 0, 18)],
+    "f32": [(1, 1, 1, 0), (1, 1, 4, 3), (2, 1, 7, 13), (4, 1, 3, 2), (2, 4, 16, 15), (4, 4, 32, 8), (1, 4, 128, 5),
+            (1, 1, 3, 9), (1, 4, 0, 18), (2, 8, 0, 16), (4, 16, 0, 18), (2, 16, 0, 18), (1, 16, 0, 16)],
 }
 
 
