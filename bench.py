@@ -25,6 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "step_f32_4096_traffic.json")
 BYTES_PER_SITE = {"f64": 144, "f32": 72, "f32s": 72, "f16s": 36}  # 9 reads + 9 writes
 
 
@@ -72,10 +73,34 @@ def time_sweep(torch, lattices, steps, warmup, stream):
     return e0.elapsed_time(e1) / 1e3, wall
 
 
+def kernel_name(tile, dtype):
+    vx, nw, h, flags = tile
+    t = {"f64": "double,false", "f32": "float,false", "f32s": "float,true", "f16s": "_Float16,true"}[dtype]
+    if flags & 16:
+        return f"lbm::step_vstack_kernel<{t},{vx},{nw},{'true' if flags & 2 else 'false'}>"
+    pf = 2 if flags & 8 else (flags & 1)
+    return f"lbm::step_kernel<{t},{vx},{nw},{pf},{'true' if flags & 2 else 'false'}> (h={h})"
+
+
+def measured_traffic(kernel, n):
+    """HBM bytes per launch from the committed rocprofv3 counter record, if it
+    was taken on the current kernel source and kernel; else None."""
+    try:
+        from paper_0707_2437_amd import profiling
+        rec = json.load(open(TRAFFIC_RECORD))
+    except (OSError, ValueError, ImportError):
+        return None
+    if rec.get("kernel_source_sha256") != profiling.kernel_source_sha() or rec.get("kernel") != kernel \
+            or rec.get("algorithmic_bytes_per_launch") != BYTES_PER_SITE["f32"] * n * n:
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def measure_form(lbm, workloads, torch, n, dtype, steps, warmup):
     # all launches go to one dedicated stream; the HIP events are recorded on it
     stream = torch.cuda.Stream()
     lats = make_sweep(lbm, workloads, torch, n, dtype, stream)
+    tile = lats[0].get_tile()
     sec, wall = time_sweep(torch, lats, steps, warmup, stream)
     tot = [L.totals() for L in lats]
     for L in lats:
@@ -86,7 +111,7 @@ def measure_form(lbm, workloads, torch, n, dtype, steps, warmup):
     gbs = BYTES_PER_SITE[dtype] * n * n / (sec / launches) / 1e9
     return {"mlups": mlups, "ms_per_step": 1e3 * sec / steps, "kernel_us": 1e6 * sec / launches,
             "achieved_GBs": gbs, "frac": gbs / PEAK_HBM_GBS, "wall_s": wall,
-            "mass_total_first": tot[0][0]}
+            "mass_total_first": tot[0][0], "kernel": kernel_name(tile, dtype), "tile": list(tile)}
 
 
 def cpu_baseline(workloads, n, steps):
@@ -174,8 +199,9 @@ def main():
                    "c2": [round(c, 6) for c in sweep],
                    "init": "plane sound wave amp 1e-3 + uniform density noise 1e-4 (seeded)"},
         "roofline": {"bound": "hbm", "achieved": round(head["achieved_GBs"], 1), "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": round(head["frac"], 4), "traffic": None,
-                     "kernel": "lbm::step_kernel<float,false,...>",
+                     "unit": "GB/s", "frac": round(head["frac"], 4),
+                     "traffic": measured_traffic(head["kernel"], n),
+                     "kernel": head["kernel"],
                      "bytes_per_launch": BYTES_PER_SITE["f32"] * n * n,
                      "avg_launch_us": round(head["kernel_us"], 2)},
         "cpu_baseline": cpu,

@@ -103,6 +103,11 @@ int lbm_moments_device(lbm_lattice* L, double* rho, double* ux, double* uy, doub
 int lbm_get_f(lbm_lattice* L, double* f);
 int lbm_set_f(lbm_lattice* L, const double* f);
 
+/* Canonical populations at n sites (HOST arrays xs[n], ys[n] with
+ * 0 <= x < nx, 0 <= y < ny) into HOST f[n][9]. Synchronous. LBM_EINVAL for a
+ * site outside the lattice (nothing is read then). */
+int lbm_sample_f(lbm_lattice* L, int n, const int* xs, const int* ys, double* f);
+
 /* Use an existing HIP stream (hipStream_t, e.g. PyTorch's current stream)
  * for all later work on this lattice; NULL is the HIP null stream. The
  * caller keeps ownership of the stream. Synchronises the previous stream. */

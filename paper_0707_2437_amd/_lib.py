@@ -35,6 +35,7 @@ SIGNATURES = {
     "lbm_moments_device": (_i, [_vp, _vp, _vp, _vp, _vp]),
     "lbm_get_f": (_i, [_vp, _vp]),
     "lbm_set_f": (_i, [_vp, _vp]),
+    "lbm_sample_f": (_i, [_vp, _i, _vp, _vp, _vp]),
     "lbm_set_stream": (_i, [_vp, _vp]),
     "lbm_use_own_stream": (_i, [_vp]),
     "lbm_get_stream": (_vp, [_vp]),

@@ -548,6 +548,19 @@ template <class T, bool SHIFT> __global__ void get_f_kernel(const T* __restrict_
         load_f64<T, SHIFT>(s[i * g.ps + (long long)sy * g.rs + g.off + xx - kEX[i]], i);
 }
 
+// f_i at n listed sites into out[n][9].
+template <class T, bool SHIFT>
+__global__ void sample_f_kernel(const T* __restrict__ s, Geom g, int n, const int* __restrict__ xy,
+                                double* __restrict__ out)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= 9 * n) return;
+    const int k = q / 9, i = q - 9 * k;
+    const int x = xy[2 * k], y = xy[2 * k + 1];
+    const int sy = wrapy(y - kEY[i], g.ny);
+    out[q] = load_f64<T, SHIFT>(s[i * g.ps + (long long)sy * g.rs + g.off + x - kEX[i]], i);
+}
+
 // Moments (Eq. 3) of f(x, t) in FP64, optional fields, and per-block
 // partial sums of (rho - 1, j_x, j_y) for the conservation totals.
 constexpr int kRedThreads = 256;
@@ -738,6 +751,16 @@ hipError_t launch_get_f(int dtype, const void* s, const Geom& g, double* f, hipS
 {
     LBM_DISPATCH(dtype, {
         hipLaunchKernelGGL((get_f_kernel<T, S>), plane_rows_grid(g, 0), dim3(256), 0, st, (const T*)s, g, f);
+        return hipGetLastError();
+    })
+}
+
+hipError_t launch_sample_f(int dtype, const void* s, const Geom& g, int n, const int* xy, double* out,
+                           hipStream_t st)
+{
+    const dim3 grid((unsigned)((9LL * n + 255) / 256));
+    LBM_DISPATCH(dtype, {
+        hipLaunchKernelGGL((sample_f_kernel<T, S>), grid, dim3(256), 0, st, (const T*)s, g, n, xy, out);
         return hipGetLastError();
     })
 }

@@ -18,6 +18,8 @@ hipError_t launch_init(int dtype, void* s, const Geom& g, const double* rho, con
 hipError_t launch_set_f(int dtype, void* s, const Geom& g, const double* f, hipStream_t st);
 hipError_t launch_get_f(int dtype, const void* s, const Geom& g, double* f, hipStream_t st);
 int moments_blocks(const Geom& g);
+hipError_t launch_sample_f(int dtype, const void* s, const Geom& g, int n, const int* xy, double* out,
+                           hipStream_t st);
 hipError_t launch_moments(int dtype, const void* s, const Geom& g, double* rho, double* ux, double* uy,
                           double* partials, double* totals, hipStream_t st);
 }  // namespace lbm
@@ -141,31 +143,32 @@ Coef make_coef(double tau, double c2)
     return k;
 }
 
-int default_kflags()
-{
-    int f = LBM_TILE_PREFETCH | LBM_TILE_NT_STORE | LBM_TILE_ROWBAND;
-    if (const char* e = std::getenv("LBM_KFLAGS")) f = std::atoi(e) & 31;
-    return f;
-}
-
-// Defaults from tile sweeps on MI355X at 4096^2 (row-interleaved layout).
-void default_tile(int dtype, int* vx, int* nw, int* h)
+// Defaults from repeated tile sweeps on MI355X at 4096^2 (row-interleaved
+// layout): the vertical-stack form for every dtype.
+struct TileDefault {
+    int vx, nw, h, flags;
+};
+TileDefault default_tile(int dtype)
 {
     switch (dtype) {
-    case LBM_F16S: *vx = 2; break;
-    default: *vx = 1; break;
+    case LBM_F64: return {2, 8, 8, LBM_TILE_VSTACK | LBM_TILE_NT_STORE};
+    case LBM_F32: return {2, 8, 8, LBM_TILE_VSTACK};
+    case LBM_F32S: return {2, 16, 8, LBM_TILE_VSTACK | LBM_TILE_NT_STORE};
+    default: return {4, 8, 8, LBM_TILE_VSTACK};
     }
-    *nw = 4;
-    *h = 8;
-    // Optional override for experiments: LBM_TILE="vx,nw,h".
-    if (const char* e = std::getenv("LBM_TILE")) {
-        int a = 0, b = 0, c = 0;
-        if (std::sscanf(e, "%d,%d,%d", &a, &b, &c) == 3 && step_shape_supported(dtype, a, b, default_kflags()) &&
-            c > 0) {
-            *vx = a;
-            *nw = b;
-            *h = c;
-        }
+}
+
+// Optional override for experiments: LBM_TILE="vx,nw,h,flags".
+void apply_tile_env(int dtype, int* vx, int* nw, int* h, int* flags)
+{
+    const char* e = std::getenv("LBM_TILE");
+    int a = 0, b = 0, c = 0, f = 0;
+    if (e && std::sscanf(e, "%d,%d,%d,%d", &a, &b, &c, &f) == 4 && step_shape_supported(dtype, a, b, f) &&
+        !(f & ~31) && (c > 0 || (f & LBM_TILE_VSTACK))) {
+        *vx = a;
+        *nw = b;
+        *h = c;
+        *flags = f;
     }
 }
 
@@ -257,8 +260,12 @@ lbm_lattice* lbm_create(int nx, int ny, double tau, double c2, int dtype)
     L->c2 = c2;
     L->g = make_geom(nx, ny, L->esize, choose_interleaved(nx, ny, dtype));
     L->coef = make_coef(tau, c2);
-    default_tile(dtype, &L->vx, &L->nw, &L->h);
-    L->kflags = default_kflags();
+    const TileDefault td = default_tile(dtype);
+    L->vx = td.vx;
+    L->nw = td.nw;
+    L->h = td.h;
+    L->kflags = td.flags;
+    apply_tile_env(dtype, &L->vx, &L->nw, &L->h, &L->kflags);
     hipError_t e = hipGetDevice(&L->device);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&L->own, hipStreamNonBlocking);
     if (e != hipSuccess) {
@@ -424,6 +431,31 @@ int lbm_get_f(lbm_lattice* L, double* f)
     if (e == hipSuccess) e = launch_get_f(L->dtype, L->cur, L->g, d.p, L->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(f, d.p, n * sizeof(double), hipMemcpyDeviceToHost, L->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+    return status_of(e);
+}
+
+int lbm_sample_f(lbm_lattice* L, int n, const int* xs, const int* ys, double* f)
+{
+    if (!L || n < 0 || (n > 0 && (!xs || !ys || !f))) return LBM_EINVAL;
+    if (!L->ready) return LBM_ESTATE;
+    if (n == 0) return LBM_OK;
+    for (int k = 0; k < n; ++k)
+        if (xs[k] < 0 || xs[k] >= L->nx || ys[k] < 0 || ys[k] >= L->ny) return LBM_EINVAL;
+    int* hxy = (int*)std::malloc(sizeof(int) * 2 * (size_t)n);
+    if (!hxy) return LBM_ENOMEM;
+    for (int k = 0; k < n; ++k) {
+        hxy[2 * k] = xs[k];
+        hxy[2 * k + 1] = ys[k];
+    }
+    DevScratch d;  // 9 n doubles of output, then 2 n ints of sites
+    hipError_t e = d.alloc((size_t)9 * n + (size_t)n);
+    int* dxy = (int*)(d.p + (size_t)9 * n);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(dxy, hxy, sizeof(int) * 2 * (size_t)n, hipMemcpyHostToDevice, L->stream);
+    if (e == hipSuccess) e = launch_sample_f(L->dtype, L->cur, L->g, n, dxy, d.p, L->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(f, d.p, sizeof(double) * 9 * (size_t)n, hipMemcpyDeviceToHost, L->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+    std::free(hxy);
     return status_of(e);
 }
 

@@ -139,6 +139,15 @@ class Lattice:
         _check(self._L.lbm_get_f(self._h, _hptr(f)), "lbm_get_f")
         return f
 
+    def sample_f(self, xs, ys):
+        """f_i at the listed sites, shape (n, 9)."""
+        xs = np.ascontiguousarray(xs, dtype=np.int32)
+        ys = np.ascontiguousarray(ys, dtype=np.int32)
+        assert xs.shape == ys.shape and xs.ndim == 1
+        out = np.empty((len(xs), 9))
+        _check(self._L.lbm_sample_f(self._h, len(xs), _hptr(xs), _hptr(ys), _hptr(out)), "lbm_sample_f")
+        return out
+
     def set_f(self, f):
         f = _host(f, (9, self.ny, self.nx))
         _check(self._L.lbm_set_f(self._h, _hptr(f)), "lbm_set_f")
