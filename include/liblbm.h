@@ -143,6 +143,74 @@ enum lbm_tile_flags {
 int lbm_set_tile(lbm_lattice* L, int vx, int nw, int h, int flags);
 int lbm_get_tile(const lbm_lattice* L, int* vx, int* nw, int* h, int* flags);
 
+/* ---------------------------------------------------------------------------
+ * Pools: the batched and served forms. A pool holds resident lattices
+ * (slots) of one dtype, each with its own nx, ny, tau and c2, under a device
+ * memory budget, and steps any subset of them together: every step of the
+ * listed lattices is one launch over all their tiles (the same per-site code
+ * as the single-lattice kernel, so each slot's result is bitwise identical to
+ * stepping it alone with lbm_step). All pool work runs on the pool's stream.
+ * A pool is not thread-safe.
+ */
+typedef struct lbm_pool lbm_pool;
+
+enum lbm_pool_mode {
+    LBM_POOL_GROUPED = 0,   /* one launch per step                                     */
+    LBM_POOL_GRAPH = 1,     /* the launches of a call captured once in a hipGraph and
+                               replayed by later calls with the same shape             */
+    LBM_POOL_PERSISTENT = 2 /* one cooperative launch for all steps of a call, with a
+                               grid barrier between steps                              */
+};
+
+/* Create an empty pool for lattices of `dtype` whose device memory
+ * (lbm_pool_slot_bytes each) may total at most budget_bytes. NULL on
+ * failure; lbm_pool_last_error() tells why. */
+lbm_pool* lbm_pool_create(size_t budget_bytes, int dtype);
+int lbm_pool_last_error(void);
+/* Free every slot and the pool (synchronises its stream). NULL: no-op. */
+void lbm_pool_destroy(lbm_pool* P);
+
+/* Device bytes one slot of this shape takes (0 if the shape is invalid). */
+size_t lbm_pool_slot_bytes(int nx, int ny, int dtype);
+size_t lbm_pool_used_bytes(const lbm_pool* P);
+size_t lbm_pool_budget_bytes(const lbm_pool* P);
+
+/* Admit a lattice (arguments as lbm_create). Returns the slot id (>= 0), or
+ * LBM_EINVAL, or LBM_ENOMEM when it does not fit the remaining budget or the
+ * device allocation fails. Slot ids of removed lattices are reused. */
+int lbm_pool_add(lbm_pool* P, int nx, int ny, double tau, double c2);
+/* Release a slot (synchronises the pool's stream). */
+int lbm_pool_remove(lbm_pool* P, int slot);
+
+/* As lbm_init / lbm_init_device for one slot; resets its time to 0. */
+int lbm_pool_init(lbm_pool* P, int slot, const double* rho, const double* ux, const double* uy);
+int lbm_pool_init_device(lbm_pool* P, int slot, const double* rho, const double* ux, const double* uy);
+
+/* Advance slots[k] by nsteps[k] >= 0 steps, k < count (each slot at most
+ * once). Launch s of the call steps every listed slot with nsteps > s.
+ * Asynchronous on the pool's stream; LBM_ESTATE for an uninitialised slot. */
+int lbm_pool_step(lbm_pool* P, const int* slots, const int* nsteps, int count);
+/* Wait for the pool's stream. */
+int lbm_pool_sync(lbm_pool* P);
+
+/* As lbm_moments / lbm_get_f for one slot (synchronous). */
+int lbm_pool_moments(lbm_pool* P, int slot, double* rho, double* ux, double* uy, double totals[3]);
+int lbm_pool_get_f(lbm_pool* P, int slot, double* f);
+/* Completed steps of a slot since its init (-1 for an invalid slot). */
+long long lbm_pool_time(const lbm_pool* P, int slot);
+
+/* Launch mode (lbm_pool_mode) and, for LBM_POOL_PERSISTENT, a cap on the
+ * workgroups of the cooperative launch (0: as many as are co-resident). */
+int lbm_pool_set_mode(lbm_pool* P, int mode, int max_grid);
+/* Vertical-stack tile of the batched kernels: vx in {1, 2, 4}, nw in
+ * {4, 8, 16}, flags 0 or LBM_TILE_NT_STORE. Does not change results. */
+int lbm_pool_set_tile(lbm_pool* P, int vx, int nw, int flags);
+int lbm_pool_get_tile(const lbm_pool* P, int* vx, int* nw, int* flags);
+/* Use an existing (non-null) HIP stream for the pool's work; NULL selects
+ * the pool's own non-blocking stream (the default). Synchronises the
+ * previous stream. */
+int lbm_pool_set_stream(lbm_pool* P, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -5,8 +5,9 @@ Importing the package does not load the library; the first Lattice does,
 and raises LibraryNotBuilt if it is missing (there is no CPU fallback).
 """
 from ._lib import LibraryNotBuilt, lib
+from .pool import GRAPH, GROUPED, PERSISTENT, Pool
 from .lattice import (DTYPE_NAMES, DTYPES, EDEVICE, EINVAL, ENOMEM, ENONFINITE, ESTATE, F16S, F32, F32S, F64, OK,
                       Lattice, LBMError, footprint_bytes)
 
-__all__ = ["Lattice", "LBMError", "LibraryNotBuilt", "lib", "footprint_bytes", "DTYPES", "DTYPE_NAMES",
+__all__ = ["Lattice", "Pool", "GROUPED", "GRAPH", "PERSISTENT", "LBMError", "LibraryNotBuilt", "lib", "footprint_bytes", "DTYPES", "DTYPE_NAMES",
            "F64", "F32", "F32S", "F16S", "OK", "EINVAL", "ENOMEM", "EDEVICE", "ESTATE", "ENONFINITE"]

@@ -41,6 +41,25 @@ SIGNATURES = {
     "lbm_get_stream": (_vp, [_vp]),
     "lbm_time": (ctypes.c_longlong, [_vp]),
     "lbm_footprint_bytes": (ctypes.c_size_t, [_i, _i, _i]),
+    "lbm_pool_create": (_vp, [ctypes.c_size_t, _i]),
+    "lbm_pool_last_error": (_i, []),
+    "lbm_pool_destroy": (None, [_vp]),
+    "lbm_pool_slot_bytes": (ctypes.c_size_t, [_i, _i, _i]),
+    "lbm_pool_used_bytes": (ctypes.c_size_t, [_vp]),
+    "lbm_pool_budget_bytes": (ctypes.c_size_t, [_vp]),
+    "lbm_pool_add": (_i, [_vp, _i, _i, _d, _d]),
+    "lbm_pool_remove": (_i, [_vp, _i]),
+    "lbm_pool_init": (_i, [_vp, _i, _vp, _vp, _vp]),
+    "lbm_pool_init_device": (_i, [_vp, _i, _vp, _vp, _vp]),
+    "lbm_pool_step": (_i, [_vp, _vp, _vp, _i]),
+    "lbm_pool_sync": (_i, [_vp]),
+    "lbm_pool_moments": (_i, [_vp, _i, _vp, _vp, _vp, _vp]),
+    "lbm_pool_get_f": (_i, [_vp, _i, _vp]),
+    "lbm_pool_time": (ctypes.c_longlong, [_vp, _i]),
+    "lbm_pool_set_mode": (_i, [_vp, _i, _i]),
+    "lbm_pool_set_tile": (_i, [_vp, _i, _i, _i]),
+    "lbm_pool_get_tile": (_i, [_vp, _vp, _vp, _vp]),
+    "lbm_pool_set_stream": (_i, [_vp, _vp]),
     "lbm_set_tile": (_i, [_vp, _i, _i, _i, _i]),
     "lbm_get_tile": (_i, [_vp, _vp, _vp, _vp, _vp]),
 }

@@ -1,0 +1,193 @@
+// batch.hip -- batched forms of the variable-speed-of-sound D2Q9 step
+// (Buick & Cosgrove, Sec. 3 Eq. 5): many independent lattices of uneven
+// size, tau and c^2 stepped by one launch per step (grouped), or by one
+// persistent cooperative launch for many steps with a grid barrier between
+// steps. Every tile is processed by vstack_tile (step.h), the same code as
+// the single-lattice vertical-stack kernel, so each lattice's result is
+// bitwise identical to stepping it alone.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+#include "step.h"
+
+namespace lbm {
+
+// Batch tile t -> lattice index: the last lattice whose first tile is <= t
+// (tile_begin is a prefix sum; a uniform binary search per workgroup).
+__device__ __forceinline__ int batch_lattice(const BatchLat* __restrict__ lats, int nlat, int t)
+{
+    int lo = 0, hi = nlat - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (lats[mid].tile_begin <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <class T, bool SHIFT, int VX, int NW, bool NTS>
+__device__ __forceinline__ void batch_tile(const BatchLat* __restrict__ lats, int nlat, int t, int s,
+                                           typename CompT<T>::type (&lds)[NW][64 * VX], bool& did)
+{
+    const int l = batch_lattice(lats, nlat, t);
+    const BatchLat& L = lats[l];
+    did = s < L.nsteps;
+    if (!did) return;  // uniform per workgroup
+    const int lt = t - L.tile_begin;
+    const bool odd = ((L.t0 + s) & 1) != 0;
+    const void* src = odd ? L.tile.dst : L.tile.src;
+    void* dst = odd ? const_cast<void*>(L.tile.src) : L.tile.dst;
+    vstack_tile<T, SHIFT, VX, NW, NTS>(L.tile, src, dst, lt % L.tile.nstrips, lt / L.tile.nstrips, lds);
+}
+
+// One step s of every lattice of the batch; one workgroup per tile, tiles
+// of a lattice contiguous and spread over the XCDs in contiguous runs.
+template <class T, bool SHIFT, int VX, int NW, bool NTS>
+__global__ __launch_bounds__(64 * NW) void batch_step_kernel(const BatchLat* __restrict__ lats, int nlat, int ntiles,
+                                                             int s)
+{
+    using C = typename CompT<T>::type;
+    __shared__ C lds[NW][64 * VX];
+    const int nb = gridDim.x;  // a multiple of 8
+    const int b = blockIdx.x;
+    const int t = (b & 7) * (nb >> 3) + (b >> 3);
+    if (t >= ntiles) return;
+    bool did;
+    batch_tile<T, SHIFT, VX, NW, NTS>(lats, nlat, t, s, lds, did);
+}
+
+// Grid barrier for the persistent kernel: a counter and a generation word in
+// device memory (bar[0], bar[1]; zero at first use; bar[2] is an error flag).
+// The last workgroup to arrive resets the counter and bumps the generation;
+// the others wait for the bump. The wait is bounded: after `spin_limit`
+// polls a workgroup gives up, raises the error flag and returns false, and
+// the kernel then ends in every workgroup (no workgroup can wait forever).
+// All accesses are vector-memory atomics.
+__device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned nblocks, unsigned spin_limit)
+{
+    __shared__ int ok;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ok = 1;
+        const unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();  // this workgroup's stores before its arrival
+        const unsigned arrived = atomicAdd(&bar[0], 1u);
+        if (arrived == nblocks - 1) {
+            atomicExch(&bar[0], 0u);
+            __threadfence();
+            __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            unsigned spins = 0;
+            while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                if (++spins > spin_limit) {
+                    atomicExch(&bar[2], 1u);
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(4);
+            }
+        }
+        __threadfence();
+    }
+    __syncthreads();
+    if (__hip_atomic_load(&bar[2], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != 0) ok = 0;
+    __syncthreads();
+    return ok != 0;
+}
+
+// nsteps_max steps of the whole batch in one cooperative launch: every
+// workgroup strides over the tiles of a step, then all wait at the grid
+// barrier before the next step reads what this one wrote. Launched only
+// with a grid that is co-resident (hipLaunchCooperativeKernel checks it).
+template <class T, bool SHIFT, int VX, int NW, bool NTS>
+__global__ __launch_bounds__(64 * NW) void batch_persistent_kernel(const BatchLat* __restrict__ lats, int nlat,
+                                                                   int ntiles, int nsteps_max, unsigned* bar,
+                                                                   unsigned spin_limit)
+{
+    using C = typename CompT<T>::type;
+    __shared__ C lds[NW][64 * VX];
+    for (int s = 0; s < nsteps_max; ++s) {
+        for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+            bool did;
+            batch_tile<T, SHIFT, VX, NW, NTS>(lats, nlat, t, s, lds, did);
+            if (did) __syncthreads();  // lds is reused by the next tile
+        }
+        if (!grid_barrier(bar, gridDim.x, spin_limit)) return;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers.
+
+template <class T, bool SHIFT, int VX, int NW, bool NTS>
+static hipError_t launch_batch_t(bool persistent, const BatchLat* lats, int nlat, int ntiles, int s_or_n,
+                                 int max_grid, unsigned* bar, hipStream_t st)
+{
+    if (!persistent) {
+        const int grid = (ntiles + 7) / 8 * 8;
+        hipLaunchKernelGGL((batch_step_kernel<T, SHIFT, VX, NW, NTS>), dim3(grid), dim3(64 * NW), 0, st, lats, nlat,
+                           ntiles, s_or_n);
+        return hipGetLastError();
+    }
+    auto kern = batch_persistent_kernel<T, SHIFT, VX, NW, NTS>;
+    int dev = 0, per_cu = 0, ncu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * NW, 0);
+    if (e != hipSuccess) return e;
+    int grid = per_cu * ncu;
+    if (max_grid > 0 && grid > max_grid) grid = max_grid;
+    if (grid > ntiles) grid = ntiles;
+    if (grid < 1) return hipErrorInvalidConfiguration;
+    unsigned spin_limit = 1u << 24;  // ~1 s of polling at one poll per ~64 ns
+    void* args[] = {(void*)&lats, (void*)&nlat, (void*)&ntiles, (void*)&s_or_n, (void*)&bar, (void*)&spin_limit};
+    return hipLaunchCooperativeKernel((const void*)kern, dim3(grid), dim3(64 * NW), args, 0, st);
+}
+
+template <class T, bool SHIFT, int VX>
+static hipError_t launch_batch_nw(int nw, bool nts, bool persistent, const BatchLat* lats, int nlat, int ntiles,
+                                  int s_or_n, int max_grid, unsigned* bar, hipStream_t st)
+{
+#define LBM_B(NWV)                                                                                                   \
+    return nts ? launch_batch_t<T, SHIFT, VX, NWV, true>(persistent, lats, nlat, ntiles, s_or_n, max_grid, bar, st)  \
+               : launch_batch_t<T, SHIFT, VX, NWV, false>(persistent, lats, nlat, ntiles, s_or_n, max_grid, bar, st)
+    switch (nw) {
+    case 4: LBM_B(4);
+    case 8: LBM_B(8);
+    case 16: LBM_B(16);
+    default: return hipErrorInvalidValue;
+    }
+#undef LBM_B
+}
+
+template <class T, bool SHIFT>
+static hipError_t launch_batch_vx(int vx, int nw, bool nts, bool persistent, const BatchLat* lats, int nlat,
+                                  int ntiles, int s_or_n, int max_grid, unsigned* bar, hipStream_t st)
+{
+    switch (vx) {
+    case 1: return launch_batch_nw<T, SHIFT, 1>(nw, nts, persistent, lats, nlat, ntiles, s_or_n, max_grid, bar, st);
+    case 2: return launch_batch_nw<T, SHIFT, 2>(nw, nts, persistent, lats, nlat, ntiles, s_or_n, max_grid, bar, st);
+    case 4: return launch_batch_nw<T, SHIFT, 4>(nw, nts, persistent, lats, nlat, ntiles, s_or_n, max_grid, bar, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// Grouped (persistent = false): step s_or_n of the batch, one launch.
+// Persistent: s_or_n steps in one cooperative launch, at most max_grid
+// workgroups (<= 0: as many as are co-resident), barrier state in `bar`
+// (3 words, zero-initialised; bar[2] becomes 1 if a barrier timed out).
+hipError_t launch_batch(int dtype, int vx, int nw, bool nts, bool persistent, const BatchLat* lats, int nlat,
+                        int ntiles, int s_or_n, int max_grid, unsigned* bar, hipStream_t st)
+{
+#define LBM_BV(T, S) launch_batch_vx<T, S>(vx, nw, nts, persistent, lats, nlat, ntiles, s_or_n, max_grid, bar, st)
+    switch (dtype) {
+    case 0: return LBM_BV(double, false);
+    case 1: return LBM_BV(float, false);
+    case 2: return LBM_BV(float, true);
+    case 3: return LBM_BV(_Float16, true);
+    default: return hipErrorInvalidValue;
+    }
+#undef LBM_BV
+}
+
+}  // namespace lbm

@@ -52,4 +52,15 @@ struct StepTile {
     int rowband;  // tile order: 1 = strip groups of a chunk first
 };
 
+// One lattice of a batched launch (device array, read by every workgroup).
+// tile.src holds the buffer of even times and tile.dst the buffer of odd
+// times: at step s of the call the lattice is at time t0 + s, reads buffer
+// (t0 + s) & 1 and writes the other. Lattices with s >= nsteps sit out.
+struct BatchLat {
+    StepTile tile;
+    long long t0;    // lattice time when the call starts
+    int nsteps;      // steps this lattice takes in the call
+    int tile_begin;  // first batch tile of this lattice (prefix sum)
+};
+
 }  // namespace lbm

@@ -29,150 +29,10 @@
 // multiply-adds are written explicitly.
 #include <hip/hip_runtime.h>
 
-#include <type_traits>
-
 #include "internal.h"
+#include "step.h"
 
 namespace lbm {
-
-template <class T> struct CompT { using type = float; };
-template <> struct CompT<double> { using type = double; };
-
-// Lattice weights (Sec. 2) in compute precision.
-template <class C> __device__ __forceinline__ C wt(int i)
-{
-    return i == 0 ? C(4) / C(9) : (i < 5 ? C(1) / C(9) : C(1) / C(36));
-}
-
-__device__ __forceinline__ int wrapy(int r, int ny) { return r < 0 ? r + ny : (r >= ny ? r - ny : r); }
-
-// Stored value -> d_i = f_i - w_i in compute precision, and back.
-template <class T, bool SHIFT, class C> __device__ __forceinline__ C to_d(T v, int i)
-{
-    if constexpr (SHIFT) return (C)v;
-    else return (C)v - wt<C>(i);
-}
-template <class T, bool SHIFT, class C> __device__ __forceinline__ T from_d(C d, int i)
-{
-    if constexpr (SHIFT) return (T)d;
-    else return (T)(wt<C>(i) + d);
-}
-
-template <class T, int VX> struct Pack { T v[VX]; };
-
-// Memory is addressed as a per-plane base pointer (uniform, computed once
-// per workgroup, held in scalar registers) plus a 32-bit byte offset (row
-// offset + lane offset), which maps to SGPR-based global loads and stores;
-// the lattice is created only if those offsets fit in 32 bits. Only element
-// alignment is assumed: the windows start one element off a vector
-// boundary, and gfx950 executes such dwordx2/x3/x4 loads directly.
-template <class T, int VX> __device__ __forceinline__ Pack<T, VX> ld_vec(const char* base, unsigned byte_off)
-{
-    Pack<T, VX> r;
-    __builtin_memcpy(&r, base + (size_t)byte_off, sizeof(r));
-    return r;
-}
-
-// Registers hold the populations of two rows. FP32/FP64 storage is kept
-// as d_i = f_i - w_i in compute precision; FP16 storage is kept raw (half
-// the registers) and converted where it is used.
-template <class T, class C> using KeepT = typename std::conditional<(sizeof(T) < sizeof(C)), T, C>::type;
-
-template <class T, bool SHIFT, class C> __device__ __forceinline__ KeepT<T, C> keep_of(T v, int i)
-{
-    if constexpr (sizeof(T) < sizeof(C)) return v;
-    else return to_d<T, SHIFT, C>(v, i);
-}
-template <class T, bool SHIFT, class C> __device__ __forceinline__ C d_of(KeepT<T, C> v, int i)
-{
-    if constexpr (sizeof(T) < sizeof(C)) return to_d<T, SHIFT, C>(v, i);
-    else return v;
-}
-
-// Window gather: for the VX sites at columns x .. x+VX-1 of row r, load
-// per plane i the stored values S_i(c - e_ix, r - e_iy) for the VX + 2
-// columns c = x-1 .. x+VX, i.e. f_i of those columns (Eq. 5, left-hand
-// side). Links (Sec. 2): e_0 (0,0); e_1 (1,0); e_2 (0,1); e_3 (-1,0);
-// e_4 (0,-1); e_5 (1,1); e_6 (-1,1); e_7 (-1,-1); e_8 (1,-1).
-// pb[i] points at column -2 of row 0 of plane i; the byte offset of column
-// x - 1 - e_ix in row q is (q * rs + x + 1 - e_ix) * sizeof(T) >= 0.
-template <class T, int NV>
-__device__ __forceinline__ void gather_raw(const char* const (&pb)[9], const Geom& g, int r, int x, Pack<T, NV> (&v)[9])
-{
-    constexpr unsigned es = sizeof(T);
-    const unsigned rs = (unsigned)g.rs * es;
-    const unsigned om = (unsigned)wrapy(r - 1, g.ny) * rs;  // source row r - 1 (e_iy = +1)
-    const unsigned o0 = (unsigned)wrapy(r, g.ny) * rs;      // source row r     (e_iy =  0)
-    const unsigned op = (unsigned)wrapy(r + 1, g.ny) * rs;  // source row r + 1 (e_iy = -1)
-    const unsigned xm = (unsigned)x * es, x0 = xm + es, xp = xm + 2 * es;  // window starts for e_ix = +1, 0, -1
-    v[0] = ld_vec<T, NV>(pb[0], o0 + x0);
-    v[1] = ld_vec<T, NV>(pb[1], o0 + xm);
-    v[2] = ld_vec<T, NV>(pb[2], om + x0);
-    v[3] = ld_vec<T, NV>(pb[3], o0 + xp);
-    v[4] = ld_vec<T, NV>(pb[4], op + x0);
-    v[5] = ld_vec<T, NV>(pb[5], om + xm);
-    v[6] = ld_vec<T, NV>(pb[6], om + xp);
-    v[7] = ld_vec<T, NV>(pb[7], op + xp);
-    v[8] = ld_vec<T, NV>(pb[8], op + xm);
-}
-
-// delta rho = sum_i d_i (Eq. 3), one fixed order for every code path.
-template <class T, bool SHIFT, class C, int VX> __device__ __forceinline__ C drho_of(const KeepT<T, C> d[9][VX], int j)
-{
-    auto D = [&](int i) { return d_of<T, SHIFT, C>(d[i][j], i); };
-    return (((D(0) + D(1)) + (D(2) + D(3))) + ((D(4) + D(5)) + (D(6) + D(7)))) + D(8);
-}
-
-template <class C> struct CoefC {
-    C om1, wo0, wo1, wo2, as1, as2;
-};
-
-template <class C> __device__ __forceinline__ CoefC<C> coef_c(const Coef& k)
-{
-    return CoefC<C>{(C)k.om1, (C)k.wo0, (C)k.wo1, (C)k.wo2, (C)k.as1, (C)k.as2};
-}
-
-// Fused multiply-add in the compute precision (the only FMAs the build emits).
-__device__ __forceinline__ float fmac(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-__device__ __forceinline__ double fmac(double a, double b, double c) { return __builtin_fma(a, b, c); }
-
-template <class C> __device__ __forceinline__ C recip(C r) { return C(1) / r; }
-template <> __device__ __forceinline__ float recip<float>(float r) { return __builtin_amdgcn_rcpf(r); }
-
-// Eq. 5 right-hand side in delta form for one site.
-//   rho = 1 + drho, u = j / rho (Eq. 3)
-//   feq_i - w_i = w_i [drho + rho (3 e.u + 9/2 (e.u)^2 - 3/2 u.u)]      (Eq. 2)
-//   d*_i = d_i - (d_i - (feq_i - w_i))/tau + 3 w_i alpha (e_i . G)      (Eq. 5)
-// For a link pair (i, opp) with e_opp = -e_i, write A = drho - 3/2 rho u.u,
-// sym = A + 9/2 rho (e.u)^2, P = om w sym, Q = om w 3 rho (e.u) + 3 w alpha (e.G):
-//   d*_i = (1 - om) d_i + P + Q,  d*_opp = (1 - om) d_opp + P - Q.
-template <class T, bool SHIFT, class C, int VX>
-__device__ __forceinline__ void collide(const KeepT<T, C> dk[9][VX], int j, C drho, C gx, C gy, const CoefC<C>& k,
-                                        C o[9])
-{
-    C d[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) d[i] = d_of<T, SHIFT, C>(dk[i][j], i);
-    const C jx = ((d[1] - d[3]) + (d[5] - d[6])) + (d[8] - d[7]);
-    const C jy = ((d[2] - d[4]) + (d[5] - d[8])) + (d[6] - d[7]);
-    const C rho = C(1) + drho;
-    const C ir = recip<C>(rho);
-    const C ux = jx * ir, uy = jy * ir;
-    const C usq = fmac(ux, ux, uy * uy);
-    const C A = fmac(C(-1.5) * rho, usq, drho);
-    const C r45 = C(4.5) * rho, r3 = C(3) * rho;
-    o[0] = fmac(k.om1, d[0], k.wo0 * A);
-    auto pair = [&](int i, int io, C eu, C eg, C wo, C as) {
-        const C P = wo * fmac(r45, eu * eu, A);
-        const C Q = fmac(as, eg, wo * (r3 * eu));
-        o[i] = fmac(k.om1, d[i], P + Q);
-        o[io] = fmac(k.om1, d[io], P - Q);
-    };
-    pair(1, 3, ux, gx, k.wo1, k.as1);
-    pair(2, 4, uy, gy, k.wo1, k.as1);
-    pair(5, 7, ux + uy, gx + gy, k.wo2, k.as2);
-    pair(6, 8, uy - ux, gy - gx, k.wo2, k.as2);
-}
 
 template <class T, bool SHIFT, int VX, int NW, int PF, bool NTS>
 __global__ __launch_bounds__(64 * NW) void step_kernel(StepTile a, int ntiles)
@@ -216,14 +76,9 @@ __global__ __launch_bounds__(64 * NW) void step_kernel(StepTile a, int ntiles)
     const int ys = dir > 0 ? ylo : yhi - 1;
     const int nrow = yhi - ylo;
 
-    // per-plane bases: source at column -2, destination at column 0
     const char* sb[9];
     char* dbase[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        sb[i] = (const char*)a.src + ((long long)i * g.ps + g.off - 2) * (long long)sizeof(T);
-        dbase[i] = (char*)a.dst + ((long long)i * g.ps + g.off) * (long long)sizeof(T);
-    }
+    plane_bases<T>(a.src, a.dst, g, sb, dbase);
 
     K da[9][VX], db[9][VX];        // populations of the current and next row (own columns)
     C wa[WV], wb[WV];              // densities of the current and next row, window columns
@@ -246,7 +101,6 @@ __global__ __launch_bounds__(64 * NW) void step_kernel(StepTile a, int ntiles)
             for (int j = 0; j < VX; ++j) d[i][j] = tmp[i][j + 1];
     };
 
-    constexpr unsigned es = sizeof(T);
     auto collide_row = [&](int y, const K (&dc)[9][VX], const C (&wc)[WV], const C (&wn)[WV]) {
         Pack<T, VX> out[9];
 #pragma unroll
@@ -261,42 +115,7 @@ __global__ __launch_bounds__(64 * NW) void step_kernel(StepTile a, int ntiles)
 #pragma unroll
             for (int i = 0; i < 9; ++i) out[i].v[j] = from_d<T, SHIFT, C>(o[i], i);
         }
-        const unsigned ro = (unsigned)y * ((unsigned)g.rs * es);  // row y, column 0
-        const unsigned lo = ro + (unsigned)x * es;
-        if (nv == VX) {
-#pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                if constexpr (NTS) {
-#pragma unroll
-                    for (int j = 0; j < VX; ++j)
-                        __builtin_nontemporal_store(out[i].v[j], (T*)(dbase[i] + (size_t)(lo + j * es)));
-                } else {
-                    __builtin_memcpy(dbase[i] + (size_t)lo, &out[i], sizeof(out[i]));
-                }
-            }
-        } else {
-#pragma unroll
-            for (int i = 0; i < 9; ++i)
-#pragma unroll
-                for (int j = 0; j < VX; ++j)
-                    if (j < nv) __builtin_memcpy(dbase[i] + (size_t)(lo + j * es), &out[i].v[j], es);
-        }
-        // ghost columns: -2, -1 hold columns nx-2, nx-1; nx, nx+1 hold 0, 1
-        // (for nx = 3, column 1 is both nx-2 and 1 and has two ghosts)
-#pragma unroll
-        for (int j = 0; j < VX; ++j) {
-            const int c = x + j;
-            if (j < nv && c >= g.nx - 2) {
-#pragma unroll
-                for (int i = 0; i < 9; ++i)  // column c - nx in [-2, -1]
-                    __builtin_memcpy(dbase[i] - 2 * es + (size_t)(ro + (unsigned)(c - g.nx + 2) * es), &out[i].v[j], es);
-            }
-            if (j < nv && c <= 1) {
-#pragma unroll
-                for (int i = 0; i < 9; ++i)  // column c + nx in [nx, nx + 1]
-                    __builtin_memcpy(dbase[i] + (size_t)(ro + (unsigned)(c + g.nx) * es), &out[i].v[j], es);
-            }
-        }
+        write_row<T, VX, NTS>(dbase, g, y, x, nv, out);
     };
 
     // March. Entering row y (the k-th of the chunk): row y's populations and
@@ -339,14 +158,8 @@ __global__ __launch_bounds__(64 * NW) void step_kernel(StepTile a, int ntiles)
     if (kk < nrow) advance(kk, da, db, wa, wb, ra);
 }
 
-// Vertical-stack form of the same step. A workgroup of R + 2 waves covers
-// one column strip of 64 * VX sites and R consecutive rows y0 .. y0+R-1:
-// wave w handles row y0 - 1 + w, so waves 0 and R + 1 take the rows just
-// outside the group, whose densities the gradient needs. Every wave loads
-// its row's windows (one row, all loads issued at once), forms the window
-// densities, publishes its own columns' densities in LDS, and after one
-// barrier the R interior waves read the densities of the rows above and
-// below, relax and write. All rows of the group are in flight together and
+// Vertical-stack form of the same step (see vstack_tile in step.h). Each
+// workgroup takes one tile; all rows of a group are in flight together and
 // consecutive workgroups (row-band order) cover adjacent strips of the same
 // rows, so the set of rows being streamed at any time stays compact. Each
 // row is read (R + 2) / R times; the extra reads of the boundary rows are
@@ -355,105 +168,12 @@ template <class T, bool SHIFT, int VX, int NW, bool NTS>
 __global__ __launch_bounds__(64 * NW) void step_vstack_kernel(StepTile a, int ntiles)
 {
     using C = typename CompT<T>::type;
-    using K = KeepT<T, C>;
-    constexpr int WV = VX + 2;
-    constexpr int R = NW - 2;  // interior rows per workgroup
-    using Rw = Pack<T, WV>;
     __shared__ C lds[NW][64 * VX];
-
     const int nb = gridDim.x;  // a multiple of 8
     const int b = blockIdx.x;
     const int t = (b & 7) * (nb >> 3) + (b >> 3);  // contiguous run of tiles per XCD
     if (t >= ntiles) return;
-    const int strip = t % a.nstrips;  // row-band order: strips of a group first
-    const int grp = t / a.nstrips;
-    const Geom g = a.g;
-    const int wave = (int)(threadIdx.x >> 6), lane = threadIdx.x & 63;
-    const int y0 = grp * R;
-    const int nrows = min(R, g.ny - y0);
-    const int y = y0 - 1 + wave;  // in [-1, ny + R - 1]; rows wrap by index
-    const int x = strip * (64 * VX) + lane * VX;
-    const int nv = min(VX, g.nx - x);
-    const bool active = nv > 0 && wave <= nrows + 1;  // waves past the bottom halo idle
-
-    const char* sb[9];
-    char* dbase[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        sb[i] = (const char*)a.src + ((long long)i * g.ps + g.off - 2) * (long long)sizeof(T);
-        dbase[i] = (char*)a.dst + ((long long)i * g.ps + g.off) * (long long)sizeof(T);
-    }
-
-    K d[9][VX];
-    C w[WV];
-    if (active) {
-        Rw raw[9];
-        gather_raw<T, WV>(sb, g, y, x, raw);
-        K tmp[9][WV];
-#pragma unroll
-        for (int i = 0; i < 9; ++i)
-#pragma unroll
-            for (int j = 0; j < WV; ++j) tmp[i][j] = keep_of<T, SHIFT, C>(raw[i].v[j], i);
-#pragma unroll
-        for (int j = 0; j < WV; ++j) w[j] = drho_of<T, SHIFT, C, WV>(tmp, j);
-#pragma unroll
-        for (int i = 0; i < 9; ++i)
-#pragma unroll
-            for (int j = 0; j < VX; ++j) d[i][j] = tmp[i][j + 1];
-#pragma unroll
-        for (int j = 0; j < VX; ++j) lds[wave][lane * VX + j] = w[j + 1];
-    }
-    __syncthreads();
-    if (!active || wave == 0 || wave > nrows) return;
-
-    const CoefC<C> k = coef_c<C>(a.c);
-    constexpr unsigned es = sizeof(T);
-    Pack<T, VX> out[9];
-#pragma unroll
-    for (int j = 0; j < VX; ++j) {
-        // central differences at time t (Sec. 4)
-        const C gx = C(0.5) * (w[j + 2] - w[j]);
-        const C gy = C(0.5) * (lds[wave + 1][lane * VX + j] - lds[wave - 1][lane * VX + j]);
-        C o[9];
-        collide<T, SHIFT, C, VX>(d, j, w[j + 1], gx, gy, k, o);
-#pragma unroll
-        for (int i = 0; i < 9; ++i) out[i].v[j] = from_d<T, SHIFT, C>(o[i], i);
-    }
-    const unsigned ro = (unsigned)y * ((unsigned)g.rs * es);  // row y, column 0
-    const unsigned lo = ro + (unsigned)x * es;
-    if (nv == VX) {
-#pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            if constexpr (NTS) {
-#pragma unroll
-                for (int j = 0; j < VX; ++j)
-                    __builtin_nontemporal_store(out[i].v[j], (T*)(dbase[i] + (size_t)(lo + j * es)));
-            } else {
-                __builtin_memcpy(dbase[i] + (size_t)lo, &out[i], sizeof(out[i]));
-            }
-        }
-    } else {
-#pragma unroll
-        for (int i = 0; i < 9; ++i)
-#pragma unroll
-            for (int j = 0; j < VX; ++j)
-                if (j < nv) __builtin_memcpy(dbase[i] + (size_t)(lo + j * es), &out[i].v[j], es);
-    }
-    // ghost columns: -2, -1 hold columns nx-2, nx-1; nx, nx+1 hold 0, 1
-#pragma unroll
-    for (int j = 0; j < VX; ++j) {
-        const int c = x + j;
-        if (j < nv && c >= g.nx - 2) {
-#pragma unroll
-            for (int i = 0; i < 9; ++i)
-                __builtin_memcpy(dbase[i] - 2 * es + (size_t)(ro + (unsigned)(c - g.nx + 2) * es), &out[i].v[j], es);
-        }
-        if (j < nv && c <= 1) {
-#pragma unroll
-            for (int i = 0; i < 9; ++i)
-                __builtin_memcpy(dbase[i] + (size_t)(ro + (unsigned)(c + g.nx) * es), &out[i].v[j], es);
-        }
-    }
+    vstack_tile<T, SHIFT, VX, NW, NTS>(a, a.src, a.dst, t % a.nstrips, t / a.nstrips, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -572,25 +292,29 @@ __global__ __launch_bounds__(kRedThreads) void moments_kernel(const T* __restric
 {
     __shared__ double red[3][kRedThreads];
     const long long n = (long long)g.nx * g.ny;
-    const long long q = (long long)blockIdx.x * kRedThreads + threadIdx.x;
     double dr = 0.0, jx = 0.0, jy = 0.0;
-    if (q < n) {
+    // grid-stride over sites, fixed order per thread (the block count depends
+    // only on the lattice size, so the sums are deterministic)
+    for (long long q = (long long)blockIdx.x * kRedThreads + threadIdx.x; q < n;
+         q += (long long)gridDim.x * kRedThreads) {
         const int y = (int)(q / g.nx), x = (int)(q - (long long)y * g.nx);
         // Shifted forms store g_i = f_i - w_i; since sum_i w_i e_i = 0 the
         // momentum is sum_i g_i e_i as well, and rho = 1 + sum_i g_i.
-        double vsum = 0.0;
+        double vsum = 0.0, sx = 0.0, sy2 = 0.0;
         for (int i = 0; i < 9; ++i) {
             const int sy = wrapy(y - kEY[i], g.ny);
             const double v = (double)s[i * g.ps + (long long)sy * g.rs + g.off + x - kEX[i]];
             vsum += v;
-            jx += v * kEX[i];
-            jy += v * kEY[i];
+            sx += v * kEX[i];
+            sy2 += v * kEY[i];
         }
         const double r = SHIFT ? 1.0 + vsum : vsum;
-        dr = SHIFT ? vsum : vsum - 1.0;
+        dr += SHIFT ? vsum : vsum - 1.0;
+        jx += sx;
+        jy += sy2;
         if (rho) rho[q] = r;
-        if (ux) ux[q] = jx / r;
-        if (uy) uy[q] = jy / r;
+        if (ux) ux[q] = sx / r;
+        if (uy) uy[q] = sy2 / r;
     }
     red[0][threadIdx.x] = dr;
     red[1][threadIdx.x] = jx;
@@ -768,7 +492,8 @@ hipError_t launch_sample_f(int dtype, const void* s, const Geom& g, int n, const
 int moments_blocks(const Geom& g)
 {
     const long long n = (long long)g.nx * g.ny;
-    return (int)((n + kRedThreads - 1) / kRedThreads);
+    const long long nb = (n + kRedThreads - 1) / kRedThreads;
+    return (int)(nb < 1024 ? nb : 1024);
 }
 
 hipError_t launch_moments(int dtype, const void* s, const Geom& g, double* rho, double* ux, double* uy,

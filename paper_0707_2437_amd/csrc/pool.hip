@@ -1,0 +1,437 @@
+// pool.hip -- host side of the batched and served forms: a pool of resident
+// lattices (slots) of one storage dtype under a device-memory budget, stepped
+// together by batched launches (grouped, grouped under a captured hipGraph,
+// or one persistent cooperative launch). C ABI in include/liblbm.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "host.h"
+
+using namespace lbm;
+
+namespace {
+
+struct Slot {
+    bool used = false;
+    bool ready = false;
+    int nx = 0, ny = 0;
+    double tau = 0, c2 = 0;
+    Geom g{};
+    Coef coef{};
+    size_t bytes = 0;  // buffers + moments scratch
+    void* buf = nullptr;
+    void* b0 = nullptr;  // state at even times
+    void* b1 = nullptr;  // state at odd times
+    double* red = nullptr;
+    long long t = 0;
+};
+
+struct GraphEntry {
+    int nsteps_max = 0, nlat = 0, ntiles = 0, vx = 0, nw = 0, nts = 0;
+    const BatchLat* lats = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+}  // namespace
+
+struct lbm_pool {
+    int dtype = 0, esize = 0, device = 0;
+    size_t budget = 0, used = 0;
+    std::vector<Slot> slots;
+    hipStream_t own = nullptr, stream = nullptr;
+    int vx = 2, nw = 8, nts = 0;  // vertical-stack tile of the batched kernels
+    int mode = LBM_POOL_GROUPED;
+    int max_grid = 0;             // persistent mode: workgroup cap (0 = all co-resident)
+    BatchLat* d_lats = nullptr;   // device descriptor array
+    unsigned* d_bar = nullptr;    // grid-barrier state of the persistent kernel (3 words)
+    int cap = 0;
+    std::vector<BatchLat> h_lats;
+    std::vector<GraphEntry> graphs;
+};
+
+namespace {
+
+thread_local int g_pool_error = LBM_OK;
+
+Slot* slot_of(lbm_pool* P, int s)
+{
+    if (!P || s < 0 || s >= (int)P->slots.size() || !P->slots[s].used) return nullptr;
+    return &P->slots[s];
+}
+
+void* cur_buf(const Slot& S) { return (S.t & 1) ? S.b1 : S.b0; }
+
+void drop_graphs(lbm_pool* P)
+{
+    for (auto& g : P->graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    P->graphs.clear();
+}
+
+size_t slot_bytes(int nx, int ny, int dtype, Geom* g_out)
+{
+    const int es = esize_of(dtype);
+    const Geom g = make_geom(nx, ny, es, choose_interleaved(nx, ny, dtype));
+    if (g_out) *g_out = g;
+    return footprint(g, es) + red_doubles(g) * sizeof(double);
+}
+
+StepTile slot_tile(const lbm_pool* P, const Slot& S)
+{
+    StepTile t{};
+    t.src = S.b0;
+    t.dst = S.b1;
+    t.g = S.g;
+    t.c = S.coef;
+    t.h = P->nw - 2;
+    const int W = 64 * P->vx, R = P->nw - 2;
+    t.nstrips = (S.nx + W - 1) / W;
+    t.nchunks = (S.ny + R - 1) / R;
+    t.rowband = 1;
+    return t;
+}
+
+hipError_t ensure_cap(lbm_pool* P, int n)
+{
+    if (n <= P->cap) return hipSuccess;
+    int cap = std::max(n, std::max(16, 2 * P->cap));
+    BatchLat* d = nullptr;
+    hipError_t e = hipMalloc((void**)&d, sizeof(BatchLat) * (size_t)cap);
+    if (e != hipSuccess) return e;
+    if (P->d_lats) {
+        (void)hipStreamSynchronize(P->stream);
+        (void)hipFree(P->d_lats);
+    }
+    drop_graphs(P);  // they hold the old descriptor pointer
+    P->d_lats = d;
+    P->cap = cap;
+    return hipSuccess;
+}
+
+// Run the batch described by h_lats (already built) for nmax steps.
+hipError_t run_batch(lbm_pool* P, int nlat, int ntiles, int nmax)
+{
+    hipError_t e = ensure_cap(P, nlat);
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(P->d_lats, P->h_lats.data(), sizeof(BatchLat) * (size_t)nlat, hipMemcpyHostToDevice,
+                       P->stream);
+    if (e != hipSuccess) return e;
+    const bool nts = P->nts != 0;
+    if (P->mode == LBM_POOL_PERSISTENT)
+        return launch_batch(P->dtype, P->vx, P->nw, nts, true, P->d_lats, nlat, ntiles, nmax, P->max_grid, P->d_bar,
+                            P->stream);
+    if (P->mode == LBM_POOL_GRAPH) {
+        GraphEntry* ge = nullptr;
+        for (auto& g : P->graphs)
+            if (g.nsteps_max == nmax && g.nlat == nlat && g.ntiles == ntiles && g.vx == P->vx && g.nw == P->nw &&
+                g.nts == P->nts && g.lats == P->d_lats)
+                ge = &g;
+        if (!ge) {
+            // Capture nmax grouped launches once; replays re-read the
+            // descriptors, which are refreshed above before every replay.
+            hipGraph_t graph = nullptr;
+            e = hipStreamBeginCapture(P->stream, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return e;
+            hipError_t le = hipSuccess;
+            for (int s = 0; s < nmax && le == hipSuccess; ++s)
+                le = launch_batch(P->dtype, P->vx, P->nw, nts, false, P->d_lats, nlat, ntiles, s, 0, nullptr,
+                                  P->stream);
+            e = hipStreamEndCapture(P->stream, &graph);
+            if (le != hipSuccess) e = le;
+            hipGraphExec_t exec = nullptr;
+            if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            if (graph) (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) return e;
+            if (P->graphs.size() >= 8) {
+                (void)hipGraphExecDestroy(P->graphs.front().exec);
+                P->graphs.erase(P->graphs.begin());
+            }
+            P->graphs.push_back(GraphEntry{nmax, nlat, ntiles, P->vx, P->nw, P->nts, P->d_lats, exec});
+            ge = &P->graphs.back();
+        }
+        return hipGraphLaunch(ge->exec, P->stream);
+    }
+    for (int s = 0; s < nmax && e == hipSuccess; ++s)
+        e = launch_batch(P->dtype, P->vx, P->nw, nts, false, P->d_lats, nlat, ntiles, s, 0, nullptr, P->stream);
+    return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_pool_last_error(void) { return g_pool_error; }
+
+lbm_pool* lbm_pool_create(size_t budget_bytes, int dtype)
+{
+    if (esize_of(dtype) == 0 || budget_bytes == 0) {
+        g_pool_error = LBM_EINVAL;
+        return nullptr;
+    }
+    lbm_pool* P = new (std::nothrow) lbm_pool();
+    if (!P) {
+        g_pool_error = LBM_ENOMEM;
+        return nullptr;
+    }
+    P->dtype = dtype;
+    P->esize = esize_of(dtype);
+    P->budget = budget_bytes;
+    switch (dtype) {  // vertical-stack tiles from the single-lattice sweeps
+    case LBM_F64: P->vx = 2; P->nw = 8; P->nts = 1; break;
+    case LBM_F32: P->vx = 2; P->nw = 8; P->nts = 0; break;
+    case LBM_F32S: P->vx = 2; P->nw = 16; P->nts = 1; break;
+    default: P->vx = 4; P->nw = 8; P->nts = 0; break;
+    }
+    hipError_t e = hipGetDevice(&P->device);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&P->own, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipMalloc((void**)&P->d_bar, 4 * sizeof(unsigned));
+    if (e == hipSuccess) e = hipMemsetAsync(P->d_bar, 0, 4 * sizeof(unsigned), P->own);
+    if (e == hipSuccess) e = hipStreamSynchronize(P->own);
+    if (e != hipSuccess) {
+        g_pool_error = LBM_EDEVICE;
+        if (P->d_bar) (void)hipFree(P->d_bar);
+        if (P->own) (void)hipStreamDestroy(P->own);
+        delete P;
+        return nullptr;
+    }
+    P->stream = P->own;
+    g_pool_error = LBM_OK;
+    return P;
+}
+
+void lbm_pool_destroy(lbm_pool* P)
+{
+    if (!P) return;
+    (void)hipStreamSynchronize(P->stream);
+    drop_graphs(P);
+    for (auto& S : P->slots) {
+        if (S.buf) (void)hipFree(S.buf);
+        if (S.red) (void)hipFree(S.red);
+    }
+    if (P->d_lats) (void)hipFree(P->d_lats);
+    if (P->d_bar) (void)hipFree(P->d_bar);
+    if (P->own) (void)hipStreamDestroy(P->own);
+    delete P;
+}
+
+size_t lbm_pool_slot_bytes(int nx, int ny, int dtype)
+{
+    if (!args_ok(nx, ny, 1.0, 1.0 / 3.0, dtype)) return 0;
+    return slot_bytes(nx, ny, dtype, nullptr);
+}
+
+size_t lbm_pool_used_bytes(const lbm_pool* P) { return P ? P->used : 0; }
+size_t lbm_pool_budget_bytes(const lbm_pool* P) { return P ? P->budget : 0; }
+
+int lbm_pool_add(lbm_pool* P, int nx, int ny, double tau, double c2)
+{
+    if (!P || !args_ok(nx, ny, tau, c2, P->dtype)) return LBM_EINVAL;
+    Geom g;
+    const size_t bytes = slot_bytes(nx, ny, P->dtype, &g);
+    if (P->used + bytes > P->budget) return LBM_ENOMEM;
+    Slot S;
+    S.used = true;
+    S.nx = nx;
+    S.ny = ny;
+    S.tau = tau;
+    S.c2 = c2;
+    S.g = g;
+    S.coef = make_coef(tau, c2);
+    S.bytes = bytes;
+    const size_t fb = footprint(g, P->esize);
+    hipError_t e = hipMalloc(&S.buf, fb);
+    if (e == hipSuccess) e = hipMalloc((void**)&S.red, red_doubles(g) * sizeof(double));
+    if (e == hipSuccess) e = hipMemsetAsync(S.buf, 0, fb, P->stream);
+    if (e != hipSuccess) {
+        if (S.buf) (void)hipFree(S.buf);
+        if (S.red) (void)hipFree(S.red);
+        return e == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE;
+    }
+    S.b0 = S.buf;
+    S.b1 = (char*)S.buf + (size_t)buffer_elems(g) * P->esize;
+    P->used += bytes;
+    for (int i = 0; i < (int)P->slots.size(); ++i)
+        if (!P->slots[i].used) {
+            P->slots[i] = S;
+            return i;
+        }
+    P->slots.push_back(S);
+    return (int)P->slots.size() - 1;
+}
+
+int lbm_pool_remove(lbm_pool* P, int slot)
+{
+    Slot* S = slot_of(P, slot);
+    if (!S) return LBM_EINVAL;
+    hipError_t e = hipStreamSynchronize(P->stream);
+    if (S->buf) (void)hipFree(S->buf);
+    if (S->red) (void)hipFree(S->red);
+    P->used -= S->bytes;
+    *S = Slot();
+    return status_of(e);
+}
+
+int lbm_pool_init(lbm_pool* P, int slot, const double* rho, const double* ux, const double* uy)
+{
+    Slot* S = slot_of(P, slot);
+    if (!S) return LBM_EINVAL;
+    const size_t n = (size_t)S->nx * S->ny;
+    DevScratch d;
+    hipError_t e = d.alloc(3 * n);
+    const double* src[3] = {rho, ux, uy};
+    const double* dp[3] = {nullptr, nullptr, nullptr};
+    for (int c = 0; c < 3 && e == hipSuccess; ++c) {
+        if (!src[c]) continue;
+        e = hipMemcpyAsync(d.p + c * n, src[c], n * sizeof(double), hipMemcpyHostToDevice, P->stream);
+        dp[c] = d.p + c * n;
+    }
+    if (e == hipSuccess) e = launch_init(P->dtype, S->b0, S->g, dp[0], dp[1], dp[2], P->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(P->stream);
+    if (e != hipSuccess) return status_of(e);
+    S->t = 0;
+    S->ready = true;
+    return LBM_OK;
+}
+
+int lbm_pool_init_device(lbm_pool* P, int slot, const double* rho, const double* ux, const double* uy)
+{
+    Slot* S = slot_of(P, slot);
+    if (!S) return LBM_EINVAL;
+    hipError_t e = launch_init(P->dtype, S->b0, S->g, rho, ux, uy, P->stream);
+    if (e != hipSuccess) return status_of(e);
+    S->t = 0;
+    S->ready = true;
+    return LBM_OK;
+}
+
+int lbm_pool_step(lbm_pool* P, const int* slots, const int* nsteps, int count)
+{
+    if (!P || count < 0 || (count > 0 && (!slots || !nsteps))) return LBM_EINVAL;
+    P->h_lats.clear();
+    int ntiles = 0, nmax = 0;
+    for (int k = 0; k < count; ++k) {
+        Slot* S = slot_of(P, slots[k]);
+        if (!S || nsteps[k] < 0) return LBM_EINVAL;
+        if (!S->ready) return LBM_ESTATE;
+        for (int j = 0; j < k; ++j)
+            if (slots[j] == slots[k]) return LBM_EINVAL;  // a slot listed twice
+        if (nsteps[k] == 0) continue;
+        BatchLat b{};
+        b.tile = slot_tile(P, *S);
+        b.t0 = S->t;
+        b.nsteps = nsteps[k];
+        b.tile_begin = ntiles;
+        ntiles += b.tile.nstrips * b.tile.nchunks;
+        nmax = std::max(nmax, nsteps[k]);
+        P->h_lats.push_back(b);
+    }
+    if (P->h_lats.empty()) return LBM_OK;
+    const int nlat = (int)P->h_lats.size();
+    hipError_t e = run_batch(P, nlat, ntiles, nmax);
+    if (e != hipSuccess) return status_of(e);
+    for (int k = 0; k < count; ++k) P->slots[slots[k]].t += nsteps[k];
+    return LBM_OK;
+}
+
+int lbm_pool_sync(lbm_pool* P)
+{
+    if (!P) return LBM_EINVAL;
+    hipError_t e = hipStreamSynchronize(P->stream);
+    unsigned flag = 0;
+    if (e == hipSuccess) e = hipMemcpy(&flag, P->d_bar + 2, sizeof(flag), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return status_of(e);
+    if (flag) {
+        // a persistent launch timed out at a grid barrier: its steps are
+        // incomplete; reset the barrier state for later launches
+        unsigned zero[3] = {0, 0, 0};
+        (void)hipMemcpy(P->d_bar, zero, sizeof(zero), hipMemcpyHostToDevice);
+        return LBM_EDEVICE;
+    }
+    return LBM_OK;
+}
+
+int lbm_pool_moments(lbm_pool* P, int slot, double* rho, double* ux, double* uy, double totals[3])
+{
+    Slot* S = slot_of(P, slot);
+    if (!S) return LBM_EINVAL;
+    if (!S->ready) return LBM_ESTATE;
+    const size_t n = (size_t)S->nx * S->ny;
+    DevScratch d;
+    hipError_t e = (rho || ux || uy) ? d.alloc(3 * n) : hipSuccess;
+    double* dp[3] = {rho ? d.p : nullptr, ux ? d.p + n : nullptr, uy ? d.p + 2 * n : nullptr};
+    double* tot_dev = S->red + (size_t)3 * moments_blocks(S->g);
+    double tot[3] = {0, 0, 0};
+    if (e == hipSuccess)
+        e = launch_moments(P->dtype, cur_buf(*S), S->g, dp[0], dp[1], dp[2], S->red, tot_dev, P->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(tot, tot_dev, sizeof(tot), hipMemcpyDeviceToHost, P->stream);
+    double* host[3] = {rho, ux, uy};
+    for (int c = 0; c < 3 && e == hipSuccess; ++c)
+        if (host[c]) e = hipMemcpyAsync(host[c], dp[c], n * sizeof(double), hipMemcpyDeviceToHost, P->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(P->stream);
+    if (e != hipSuccess) return status_of(e);
+    if (totals) std::memcpy(totals, tot, sizeof(tot));
+    for (double v : tot)
+        if (!std::isfinite(v)) return LBM_ENONFINITE;
+    return LBM_OK;
+}
+
+int lbm_pool_get_f(lbm_pool* P, int slot, double* f)
+{
+    Slot* S = slot_of(P, slot);
+    if (!S || !f) return LBM_EINVAL;
+    if (!S->ready) return LBM_ESTATE;
+    const size_t n = (size_t)9 * S->nx * S->ny;
+    DevScratch d;
+    hipError_t e = d.alloc(n);
+    if (e == hipSuccess) e = launch_get_f(P->dtype, cur_buf(*S), S->g, d.p, P->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(f, d.p, n * sizeof(double), hipMemcpyDeviceToHost, P->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(P->stream);
+    return status_of(e);
+}
+
+long long lbm_pool_time(const lbm_pool* P, int slot)
+{
+    if (!P || slot < 0 || slot >= (int)P->slots.size() || !P->slots[slot].used) return -1;
+    return P->slots[slot].t;
+}
+
+int lbm_pool_set_mode(lbm_pool* P, int mode, int max_grid)
+{
+    if (!P || mode < LBM_POOL_GROUPED || mode > LBM_POOL_PERSISTENT || max_grid < 0) return LBM_EINVAL;
+    P->mode = mode;
+    P->max_grid = max_grid;
+    return LBM_OK;
+}
+
+int lbm_pool_set_tile(lbm_pool* P, int vx, int nw, int flags)
+{
+    if (!P || (flags & ~LBM_TILE_NT_STORE) || !step_shape_supported(P->dtype, vx, nw, LBM_TILE_VSTACK)) return LBM_EINVAL;
+    hipError_t e = hipStreamSynchronize(P->stream);
+    P->vx = vx;
+    P->nw = nw;
+    P->nts = (flags & LBM_TILE_NT_STORE) ? 1 : 0;
+    return status_of(e);
+}
+
+int lbm_pool_get_tile(const lbm_pool* P, int* vx, int* nw, int* flags)
+{
+    if (!P) return LBM_EINVAL;
+    if (vx) *vx = P->vx;
+    if (nw) *nw = P->nw;
+    if (flags) *flags = P->nts ? LBM_TILE_NT_STORE : 0;
+    return LBM_OK;
+}
+
+int lbm_pool_set_stream(lbm_pool* P, void* s)
+{
+    if (!P) return LBM_EINVAL;
+    hipError_t e = hipStreamSynchronize(P->stream);
+    drop_graphs(P);  // graphs were captured on the old stream
+    P->stream = s ? (hipStream_t)s : P->own;
+    return status_of(e);
+}
+
+}  // extern "C"

@@ -7,22 +7,7 @@
 #include <cstring>
 #include <new>
 
-#include "internal.h"
-#include "liblbm.h"
-
-namespace lbm {
-hipError_t launch_step(int dtype, int vx, int nw, int flags, const StepTile& t, hipStream_t st);
-bool step_shape_supported(int dtype, int vx, int nw, int flags);
-hipError_t launch_init(int dtype, void* s, const Geom& g, const double* rho, const double* ux, const double* uy,
-                       hipStream_t st);
-hipError_t launch_set_f(int dtype, void* s, const Geom& g, const double* f, hipStream_t st);
-hipError_t launch_get_f(int dtype, const void* s, const Geom& g, double* f, hipStream_t st);
-int moments_blocks(const Geom& g);
-hipError_t launch_sample_f(int dtype, const void* s, const Geom& g, int n, const int* xy, double* out,
-                           hipStream_t st);
-hipError_t launch_moments(int dtype, const void* s, const Geom& g, double* rho, double* ux, double* uy,
-                          double* partials, double* totals, hipStream_t st);
-}  // namespace lbm
+#include "host.h"
 
 using namespace lbm;
 
@@ -47,101 +32,6 @@ struct lbm_lattice {
 namespace {
 
 thread_local int g_last_error = LBM_OK;
-
-constexpr int kLineBytes = 128;
-
-int esize_of(int dtype)
-{
-    switch (dtype) {
-    case LBM_F64: return 8;
-    case LBM_F32:
-    case LBM_F32S: return 4;
-    case LBM_F16S: return 2;
-    default: return 0;
-    }
-}
-
-Geom make_geom(int nx, int ny, int esize, bool interleaved);
-long long buffer_elems(const Geom& g);
-
-// True if the kernels' 32-bit byte offsets cover the lattice in this layout:
-// a plane (plane-major) or a whole buffer (row-interleaved).
-bool offsets_fit(int nx, int ny, int dtype, bool interleaved)
-{
-    const Geom g = make_geom(nx, ny, esize_of(dtype), interleaved);
-    const long long span = interleaved ? buffer_elems(g) : g.ps;
-    return (unsigned long long)(span + g.pitch) * esize_of(dtype) < (1ULL << 32);
-}
-
-// Layout of a new lattice: row-interleaved when it fits (it streams the nine
-// plane rows of a lattice row as one contiguous block), else plane-major.
-// LBM_LAYOUT=soa forces plane-major.
-bool choose_interleaved(int nx, int ny, int dtype)
-{
-    const char* e = std::getenv("LBM_LAYOUT");
-    if (e && std::strcmp(e, "soa") == 0) return false;
-    return offsets_fit(nx, ny, dtype, true);
-}
-
-bool args_ok(int nx, int ny, double tau, double c2, int dtype)
-{
-    // nx, ny >= 3: the central differences need two distinct neighbours.
-    // tau > 1/2: positive viscosity (Eq. 4). c2 > 0: real c_e (Eq. 8).
-    if (nx < 3 || ny < 3 || !std::isfinite(tau) || !(tau > 0.5) || !std::isfinite(c2) || !(c2 > 0.0)) return false;
-    if (esize_of(dtype) == 0) return false;
-    if (nx > (1 << 28) || ny > (1 << 28)) return false;
-    return offsets_fit(nx, ny, dtype, choose_interleaved(nx, ny, dtype));
-}
-
-// Row pitch leaves one line before column 0 (ghost columns -2, -1 at its
-// end), the ghost columns nx, nx+1, and room for the widest window past the
-// last column. Plane-major layout: planes rounded to 4 KiB plus a 1 KiB
-// skew; row-interleaved layout: rows of 9 * pitch.
-Geom make_geom(int nx, int ny, int esize, bool interleaved)
-{
-    Geom g;
-    g.nx = nx;
-    g.ny = ny;
-    const int line = kLineBytes / esize;
-    g.off = line;
-    const long long need = (long long)line + nx + kMaxVX + 4;
-    g.pitch = (int)((need + line - 1) / line * line);
-    if (interleaved) {
-        g.ps = g.pitch;
-        g.rs = 9LL * g.pitch;
-    } else {
-        const long long bytes = (long long)g.pitch * ny * esize;
-        g.ps = ((bytes + 4095) / 4096 * 4096 + 1024) / esize;
-        g.rs = g.pitch;
-    }
-    return g;
-}
-
-// Elements of one population buffer (9 planes).
-long long buffer_elems(const Geom& g) { return g.rs == g.pitch ? 9 * g.ps : g.rs * g.ny; }
-
-size_t footprint(const Geom& g, int esize)
-{
-    // 2 buffers, plus one line of slack past the end.
-    return (size_t)2 * (size_t)buffer_elems(g) * esize + kLineBytes;
-}
-
-size_t red_doubles(const Geom& g) { return (size_t)3 * moments_blocks(g) + 3; }
-
-Coef make_coef(double tau, double c2)
-{
-    // Eq. 5 with alpha = 1/3 - c2 (Eq. 8), weights of Sec. 2.
-    const double om = 1.0 / tau, alpha = 1.0 / 3.0 - c2;
-    const double w0 = 4.0 / 9.0, w1 = 1.0 / 9.0, w2 = 1.0 / 36.0;
-    Coef k;
-    k.om1 = 1.0 - om;
-    k.wo0 = om * w0;
-    k.wo1 = om * w1;
-    k.wo2 = om * w2;
-    k.as1 = 3.0 * w1 * alpha;
-    k.as2 = 3.0 * w2 * alpha;
-    return k;
-}
 
 // Defaults from repeated tile sweeps on MI355X at 4096^2 (row-interleaved
 // layout): the vertical-stack form for every dtype.
@@ -172,13 +62,6 @@ void apply_tile_env(int dtype, int* vx, int* nw, int* h, int* flags)
     }
 }
 
-int status_of(hipError_t e)
-{
-    if (e == hipSuccess) return LBM_OK;
-    if (e == hipErrorOutOfMemory) return LBM_ENOMEM;
-    return LBM_EDEVICE;
-}
-
 StepTile make_tile(const lbm_lattice* L)
 {
     StepTile t;
@@ -200,19 +83,6 @@ StepTile make_tile(const lbm_lattice* L)
     t.rowband = (L->kflags & LBM_TILE_ROWBAND) ? 1 : 0;
     return t;
 }
-
-// RAII device scratch for host-array entry points.
-struct DevScratch {
-    double* p = nullptr;
-    hipError_t alloc(size_t n)
-    {
-        return hipMalloc((void**)&p, n * sizeof(double));
-    }
-    ~DevScratch()
-    {
-        if (p) (void)hipFree(p);
-    }
-};
 
 }  // namespace
 

@@ -1,0 +1,277 @@
+// step.h -- device code of the variable-speed-of-sound D2Q9 step (Buick &
+// Cosgrove, Sec. 3 Eq. 5), shared by the single-lattice and batched kernels.
+// See kernels.hip for the decomposition; internal.h for the storage layout.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "internal.h"
+
+namespace lbm {
+
+template <class T> struct CompT { using type = float; };
+template <> struct CompT<double> { using type = double; };
+
+// Lattice weights (Sec. 2) in compute precision.
+template <class C> __device__ __forceinline__ C wt(int i)
+{
+    return i == 0 ? C(4) / C(9) : (i < 5 ? C(1) / C(9) : C(1) / C(36));
+}
+
+__device__ __forceinline__ int wrapy(int r, int ny) { return r < 0 ? r + ny : (r >= ny ? r - ny : r); }
+
+// Stored value -> d_i = f_i - w_i in compute precision, and back.
+template <class T, bool SHIFT, class C> __device__ __forceinline__ C to_d(T v, int i)
+{
+    if constexpr (SHIFT) return (C)v;
+    else return (C)v - wt<C>(i);
+}
+template <class T, bool SHIFT, class C> __device__ __forceinline__ T from_d(C d, int i)
+{
+    if constexpr (SHIFT) return (T)d;
+    else return (T)(wt<C>(i) + d);
+}
+
+template <class T, int VX> struct Pack { T v[VX]; };
+
+// Memory is addressed as a per-plane base pointer (uniform, computed once
+// per workgroup, held in scalar registers) plus a 32-bit byte offset (row
+// offset + lane offset), which maps to SGPR-based global loads and stores;
+// the lattice is created only if those offsets fit in 32 bits. Only element
+// alignment is assumed: the windows start one element off a vector
+// boundary, and gfx950 executes such dwordx2/x3/x4 loads directly.
+template <class T, int VX> __device__ __forceinline__ Pack<T, VX> ld_vec(const char* base, unsigned byte_off)
+{
+    Pack<T, VX> r;
+    __builtin_memcpy(&r, base + (size_t)byte_off, sizeof(r));
+    return r;
+}
+
+// Registers hold the populations of two rows. FP32/FP64 storage is kept
+// as d_i = f_i - w_i in compute precision; FP16 storage is kept raw (half
+// the registers) and converted where it is used.
+template <class T, class C> using KeepT = typename std::conditional<(sizeof(T) < sizeof(C)), T, C>::type;
+
+template <class T, bool SHIFT, class C> __device__ __forceinline__ KeepT<T, C> keep_of(T v, int i)
+{
+    if constexpr (sizeof(T) < sizeof(C)) return v;
+    else return to_d<T, SHIFT, C>(v, i);
+}
+template <class T, bool SHIFT, class C> __device__ __forceinline__ C d_of(KeepT<T, C> v, int i)
+{
+    if constexpr (sizeof(T) < sizeof(C)) return to_d<T, SHIFT, C>(v, i);
+    else return v;
+}
+
+// Window gather: for the VX sites at columns x .. x+VX-1 of row r, load
+// per plane i the stored values S_i(c - e_ix, r - e_iy) for the VX + 2
+// columns c = x-1 .. x+VX, i.e. f_i of those columns (Eq. 5, left-hand
+// side). Links (Sec. 2): e_0 (0,0); e_1 (1,0); e_2 (0,1); e_3 (-1,0);
+// e_4 (0,-1); e_5 (1,1); e_6 (-1,1); e_7 (-1,-1); e_8 (1,-1).
+// pb[i] points at column -2 of row 0 of plane i; the byte offset of column
+// x - 1 - e_ix in row q is (q * rs + x + 1 - e_ix) * sizeof(T) >= 0.
+template <class T, int NV>
+__device__ __forceinline__ void gather_raw(const char* const (&pb)[9], const Geom& g, int r, int x, Pack<T, NV> (&v)[9])
+{
+    constexpr unsigned es = sizeof(T);
+    const unsigned rs = (unsigned)g.rs * es;
+    const unsigned om = (unsigned)wrapy(r - 1, g.ny) * rs;  // source row r - 1 (e_iy = +1)
+    const unsigned o0 = (unsigned)wrapy(r, g.ny) * rs;      // source row r     (e_iy =  0)
+    const unsigned op = (unsigned)wrapy(r + 1, g.ny) * rs;  // source row r + 1 (e_iy = -1)
+    const unsigned xm = (unsigned)x * es, x0 = xm + es, xp = xm + 2 * es;  // window starts for e_ix = +1, 0, -1
+    v[0] = ld_vec<T, NV>(pb[0], o0 + x0);
+    v[1] = ld_vec<T, NV>(pb[1], o0 + xm);
+    v[2] = ld_vec<T, NV>(pb[2], om + x0);
+    v[3] = ld_vec<T, NV>(pb[3], o0 + xp);
+    v[4] = ld_vec<T, NV>(pb[4], op + x0);
+    v[5] = ld_vec<T, NV>(pb[5], om + xm);
+    v[6] = ld_vec<T, NV>(pb[6], om + xp);
+    v[7] = ld_vec<T, NV>(pb[7], op + xp);
+    v[8] = ld_vec<T, NV>(pb[8], op + xm);
+}
+
+// delta rho = sum_i d_i (Eq. 3), one fixed order for every code path.
+template <class T, bool SHIFT, class C, int VX> __device__ __forceinline__ C drho_of(const KeepT<T, C> d[9][VX], int j)
+{
+    auto D = [&](int i) { return d_of<T, SHIFT, C>(d[i][j], i); };
+    return (((D(0) + D(1)) + (D(2) + D(3))) + ((D(4) + D(5)) + (D(6) + D(7)))) + D(8);
+}
+
+template <class C> struct CoefC {
+    C om1, wo0, wo1, wo2, as1, as2;
+};
+
+template <class C> __device__ __forceinline__ CoefC<C> coef_c(const Coef& k)
+{
+    return CoefC<C>{(C)k.om1, (C)k.wo0, (C)k.wo1, (C)k.wo2, (C)k.as1, (C)k.as2};
+}
+
+// Fused multiply-add in the compute precision (the only FMAs the build emits).
+__device__ __forceinline__ float fmac(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmac(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+template <class C> __device__ __forceinline__ C recip(C r) { return C(1) / r; }
+template <> __device__ __forceinline__ float recip<float>(float r) { return __builtin_amdgcn_rcpf(r); }
+
+// Eq. 5 right-hand side in delta form for one site.
+//   rho = 1 + drho, u = j / rho (Eq. 3)
+//   feq_i - w_i = w_i [drho + rho (3 e.u + 9/2 (e.u)^2 - 3/2 u.u)]      (Eq. 2)
+//   d*_i = d_i - (d_i - (feq_i - w_i))/tau + 3 w_i alpha (e_i . G)      (Eq. 5)
+// For a link pair (i, opp) with e_opp = -e_i, write A = drho - 3/2 rho u.u,
+// sym = A + 9/2 rho (e.u)^2, P = om w sym, Q = om w 3 rho (e.u) + 3 w alpha (e.G):
+//   d*_i = (1 - om) d_i + P + Q,  d*_opp = (1 - om) d_opp + P - Q.
+template <class T, bool SHIFT, class C, int VX>
+__device__ __forceinline__ void collide(const KeepT<T, C> dk[9][VX], int j, C drho, C gx, C gy, const CoefC<C>& k,
+                                        C o[9])
+{
+    C d[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) d[i] = d_of<T, SHIFT, C>(dk[i][j], i);
+    const C jx = ((d[1] - d[3]) + (d[5] - d[6])) + (d[8] - d[7]);
+    const C jy = ((d[2] - d[4]) + (d[5] - d[8])) + (d[6] - d[7]);
+    const C rho = C(1) + drho;
+    const C ir = recip<C>(rho);
+    const C ux = jx * ir, uy = jy * ir;
+    const C usq = fmac(ux, ux, uy * uy);
+    const C A = fmac(C(-1.5) * rho, usq, drho);
+    const C r45 = C(4.5) * rho, r3 = C(3) * rho;
+    o[0] = fmac(k.om1, d[0], k.wo0 * A);
+    auto pair = [&](int i, int io, C eu, C eg, C wo, C as) {
+        const C P = wo * fmac(r45, eu * eu, A);
+        const C Q = fmac(as, eg, wo * (r3 * eu));
+        o[i] = fmac(k.om1, d[i], P + Q);
+        o[io] = fmac(k.om1, d[io], P - Q);
+    };
+    pair(1, 3, ux, gx, k.wo1, k.as1);
+    pair(2, 4, uy, gy, k.wo1, k.as1);
+    pair(5, 7, ux + uy, gx + gy, k.wo2, k.as2);
+    pair(6, 8, uy - ux, gy - gx, k.wo2, k.as2);
+}
+
+// Write row y of the lattice: VX relaxed sites per lane (nv of them valid)
+// and, for the columns that have them, the ghost copies (-2, -1 hold columns
+// nx-2, nx-1; nx, nx+1 hold 0, 1; for nx = 3 column 1 has two ghosts).
+template <class T, int VX, bool NTS>
+__device__ __forceinline__ void write_row(char* const (&dbase)[9], const Geom& g, int y, int x, int nv,
+                                          const Pack<T, VX> (&out)[9])
+{
+    constexpr unsigned es = sizeof(T);
+    const unsigned ro = (unsigned)y * ((unsigned)g.rs * es);  // row y, column 0
+    const unsigned lo = ro + (unsigned)x * es;
+    if (nv == VX) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            if constexpr (NTS) {
+#pragma unroll
+                for (int j = 0; j < VX; ++j)
+                    __builtin_nontemporal_store(out[i].v[j], (T*)(dbase[i] + (size_t)(lo + j * es)));
+            } else {
+                __builtin_memcpy(dbase[i] + (size_t)lo, &out[i], sizeof(out[i]));
+            }
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+#pragma unroll
+            for (int j = 0; j < VX; ++j)
+                if (j < nv) __builtin_memcpy(dbase[i] + (size_t)(lo + j * es), &out[i].v[j], es);
+    }
+#pragma unroll
+    for (int j = 0; j < VX; ++j) {
+        const int c = x + j;
+        if (j < nv && c >= g.nx - 2) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i)  // column c - nx in [-2, -1]
+                __builtin_memcpy(dbase[i] - 2 * es + (size_t)(ro + (unsigned)(c - g.nx + 2) * es), &out[i].v[j], es);
+        }
+        if (j < nv && c <= 1) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i)  // column c + nx in [nx, nx + 1]
+                __builtin_memcpy(dbase[i] + (size_t)(ro + (unsigned)(c + g.nx) * es), &out[i].v[j], es);
+        }
+    }
+}
+
+// Per-plane base pointers: source at column -2, destination at column 0.
+template <class T>
+__device__ __forceinline__ void plane_bases(const void* src, void* dst, const Geom& g, const char* (&sb)[9],
+                                            char* (&dbase)[9])
+{
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        sb[i] = (const char*)src + ((long long)i * g.ps + g.off - 2) * (long long)sizeof(T);
+        dbase[i] = (char*)dst + ((long long)i * g.ps + g.off) * (long long)sizeof(T);
+    }
+}
+
+// One vertical-stack tile: strip `strip` (64 * VX columns) and row group
+// `grp` (R = NW - 2 rows) of the lattice described by `a`, with src/dst the
+// buffers of this step. A workgroup of NW waves: wave w handles row
+// y0 - 1 + w, so waves 0 and R + 1 take the rows just outside the group,
+// whose densities the gradient needs. Every wave loads its row's windows,
+// forms the window densities and publishes its own columns' densities in
+// `lds`; after one barrier the interior waves read the densities of the
+// rows above and below, relax and write. The caller must place a barrier
+// between two calls that reuse `lds`.
+template <class T, bool SHIFT, int VX, int NW, bool NTS>
+__device__ __forceinline__ void vstack_tile(const StepTile& a, const void* src, void* dst, int strip, int grp,
+                                            typename CompT<T>::type (&lds)[NW][64 * VX])
+{
+    using C = typename CompT<T>::type;
+    using K = KeepT<T, C>;
+    constexpr int WV = VX + 2;
+    constexpr int R = NW - 2;
+    using Rw = Pack<T, WV>;
+    const Geom g = a.g;
+    const int wave = (int)(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int y0 = grp * R;
+    const int nrows = min(R, g.ny - y0);
+    const int y = y0 - 1 + wave;  // in [-1, ny + R - 1]; rows wrap by index
+    const int x = strip * (64 * VX) + lane * VX;
+    const int nv = min(VX, g.nx - x);
+    const bool active = nv > 0 && wave <= nrows + 1;  // waves past the bottom halo idle
+
+    const char* sb[9];
+    char* dbase[9];
+    plane_bases<T>(src, dst, g, sb, dbase);
+
+    K d[9][VX];
+    C w[WV];
+    if (active) {
+        Rw raw[9];
+        gather_raw<T, WV>(sb, g, y, x, raw);
+        K tmp[9][WV];
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+#pragma unroll
+            for (int j = 0; j < WV; ++j) tmp[i][j] = keep_of<T, SHIFT, C>(raw[i].v[j], i);
+#pragma unroll
+        for (int j = 0; j < WV; ++j) w[j] = drho_of<T, SHIFT, C, WV>(tmp, j);
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+#pragma unroll
+            for (int j = 0; j < VX; ++j) d[i][j] = tmp[i][j + 1];
+#pragma unroll
+        for (int j = 0; j < VX; ++j) lds[wave][lane * VX + j] = w[j + 1];
+    }
+    __syncthreads();
+    if (active && wave >= 1 && wave <= nrows) {
+        const CoefC<C> k = coef_c<C>(a.c);
+        Pack<T, VX> out[9];
+#pragma unroll
+        for (int j = 0; j < VX; ++j) {
+            // central differences at time t (Sec. 4)
+            const C gx = C(0.5) * (w[j + 2] - w[j]);
+            const C gy = C(0.5) * (lds[wave + 1][lane * VX + j] - lds[wave - 1][lane * VX + j]);
+            C o[9];
+            collide<T, SHIFT, C, VX>(d, j, w[j + 1], gx, gy, k, o);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) out[i].v[j] = from_d<T, SHIFT, C>(o[i], i);
+        }
+        write_row<T, VX, NTS>(dbase, g, y, x, nv, out);
+    }
+}
+
+}  // namespace lbm

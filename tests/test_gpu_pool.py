@@ -1,0 +1,138 @@
+"""Batched form: a pool of lattices of uneven size, tau and c^2 stepped by
+batched launches (grouped, captured hipGraph, persistent cooperative) gives
+every lattice bitwise the result of stepping it alone; the pool enforces its
+memory budget; errors are reported."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import max_rel_err, smooth_random_state
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_0707_2437_amd as lbm  # noqa: E402
+
+# (nx, ny, tau, c2, steps): tiny, ragged, tall, wide, several tiles
+CASES = [(3, 3, 0.7, 0.5, 40), (130, 77, 0.6, 0.81, 40), (64, 300, 1.2, 0.04, 17), (333, 41, 0.9, 1.0 / 3.0, 0),
+         (257, 129, 0.55, 0.3, 33), (5, 200, 0.8, 0.2, 40)]
+
+
+def run_alone(nx, ny, tau, c2, steps, dtype, fields):
+    with lbm.Lattice(nx, ny, tau, c2, dtype) as L:
+        return L.init(*fields).step(steps).get_f()
+
+
+@pytest.mark.parametrize("mode", [lbm.GROUPED, lbm.GRAPH, lbm.PERSISTENT])
+@pytest.mark.parametrize("dtype", ["f64", "f32", "f16s"])
+def test_batched_equals_alone_bitwise(dtype, mode):
+    fields = [smooth_random_state(nx, ny, seed=17 * k + 1) for k, (nx, ny, *_) in enumerate(CASES)]
+    with lbm.Pool(4 << 30, dtype) as P:
+        P.set_mode(mode)
+        slots = [P.add(nx, ny, tau, c2) for (nx, ny, tau, c2, _) in CASES]
+        for s, f in zip(slots, fields):
+            P.init(s, *f)
+        P.step(slots, [c[4] for c in CASES])
+        # a second call with the same shape replays the captured graph
+        P.step(slots, [c[4] for c in CASES])
+        got = [P.get_f(s) for s in slots]
+        times = [P.time(s) for s in slots]
+    for (nx, ny, tau, c2, n), f, g, t in zip(CASES, fields, got, times):
+        assert t == 2 * n
+        assert np.array_equal(g, run_alone(nx, ny, tau, c2, 2 * n, dtype, f)), (nx, ny)
+
+
+def test_persistent_with_few_workgroups_bitwise():
+    """Persistent mode with 4 workgroups: each strides over many tiles and
+    waits at the grid barrier every step."""
+    fields = [smooth_random_state(nx, ny, seed=k) for k, (nx, ny, *_) in enumerate(CASES)]
+    with lbm.Pool(1 << 30, "f32") as P:
+        P.set_mode(lbm.PERSISTENT, max_grid=4)
+        slots = [P.add(nx, ny, tau, c2) for (nx, ny, tau, c2, _) in CASES]
+        for s, f in zip(slots, fields):
+            P.init(s, *f)
+        P.step(slots, [c[4] for c in CASES])
+        got = [P.get_f(s) for s in slots]
+    for (nx, ny, tau, c2, n), f, g in zip(CASES, fields, got):
+        assert np.array_equal(g, run_alone(nx, ny, tau, c2, n, "f32", f))
+
+
+@pytest.mark.parametrize("tile", [(1, 4, 0), (2, 16, 2), (4, 8, 0)])
+def test_pool_tile_does_not_change_results(tile):
+    fields = [smooth_random_state(nx, ny, seed=k) for k, (nx, ny, *_) in enumerate(CASES)]
+    with lbm.Pool(1 << 30, "f64") as P:
+        P.set_tile(*tile)
+        slots = [P.add(nx, ny, tau, c2) for (nx, ny, tau, c2, _) in CASES]
+        for s, f in zip(slots, fields):
+            P.init(s, *f)
+        P.step(slots, 25)
+        got = [P.get_f(s) for s in slots]
+    for (nx, ny, tau, c2, _), f, g in zip(CASES, fields, got):
+        assert np.array_equal(g, run_alone(nx, ny, tau, c2, 25, "f64", f))
+
+
+def test_pool_members_match_oracle():
+    cases = [(48, 36, 0.7, 0.5), (31, 64, 0.6, 0.9)]
+    with lbm.Pool(1 << 30, "f64") as P:
+        slots, refs = [], []
+        for k, (nx, ny, tau, c2) in enumerate(cases):
+            f = smooth_random_state(nx, ny, seed=40 + k)
+            s = P.add(nx, ny, tau, c2)
+            P.init(s, *f)
+            slots.append(s)
+            refs.append(oracle.Oracle(nx, ny, tau, c2).init(*f).step(200).get_f())
+        P.step(slots, 200)
+        for s, r in zip(slots, refs):
+            assert max_rel_err(P.get_f(s), r) <= 1e-12
+
+
+def test_budget_admission_and_slot_reuse():
+    b = lbm.Pool.slot_bytes(256, 256, "f32")
+    with lbm.Pool(3 * b, "f32") as P:
+        s = [P.add(256, 256, 0.8, 0.3) for _ in range(3)]
+        assert P.used_bytes == 3 * b
+        assert P.try_add(256, 256, 0.8, 0.3) is None  # over budget
+        with pytest.raises(lbm.LBMError) as ei:
+            P.add(256, 256, 0.8, 0.3)
+        assert ei.value.status == lbm.ENOMEM
+        P.remove(s[1])
+        assert P.used_bytes == 2 * b
+        assert P.add(256, 256, 0.8, 0.3) == s[1]  # id reused
+
+
+def test_pool_errors():
+    with lbm.Pool(1 << 28, "f32") as P:
+        s = P.add(32, 32, 0.8, 0.3)
+        with pytest.raises(lbm.LBMError) as ei:
+            P.step([s], [1])
+        assert ei.value.status == lbm.ESTATE
+        P.init(s)
+        with pytest.raises(lbm.LBMError) as ei:
+            P.step([s, s], [1, 1])
+        assert ei.value.status == lbm.EINVAL
+        with pytest.raises(lbm.LBMError) as ei:
+            P.step([s + 7], [1])
+        assert ei.value.status == lbm.EINVAL
+        with pytest.raises(lbm.LBMError) as ei:
+            P.add(2, 32, 0.8, 0.3)
+        assert ei.value.status == lbm.EINVAL
+
+
+def test_nonfinite_job_detected_and_isolated():
+    """A lattice with a NaN is reported by its totals and does not disturb
+    the other slots stepped in the same launches."""
+    with lbm.Pool(1 << 28, "f32") as P:
+        good, bad = P.add(40, 30, 0.7, 0.4), P.add(40, 30, 0.7, 0.4)
+        f = smooth_random_state(40, 30, seed=2)
+        rho_bad = f[0].copy()
+        rho_bad[5, 5] = np.nan
+        P.init(good, *f)
+        P.init(bad, rho_bad, f[1], f[2])
+        P.step([good, bad], 30)
+        assert P.totals(bad)[1] == lbm.ENONFINITE
+        assert P.totals(good)[1] == 0
+        ref = run_alone(40, 30, 0.7, 0.4, 30, "f32", f)
+        assert np.array_equal(P.get_f(good), ref)
