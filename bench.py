@@ -39,6 +39,11 @@ def parse():
     p.add_argument("--form-steps", type=int, default=300)
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     p.add_argument("--cpu-steps", type=int, default=200)
+    p.add_argument("--batch", type=int, default=256, help="lattices of the batched form (0: skip it)")
+    p.add_argument("--batch-steps", type=int, default=2000)
+    p.add_argument("--batch-mode", default="graph", choices=["grouped", "graph", "persistent"])
+    p.add_argument("--batch-persistent-steps", type=int, default=200,
+                   help="also time the persistent cooperative form for this many steps (0: skip)")
     p.add_argument("--copy-probe", action="store_true",
                    help="only run a device copy of known size (reference for HBM byte counters)")
     return p.parse_args()
@@ -133,6 +138,75 @@ def cpu_baseline(workloads, n, steps):
                       f"{sec:.1f} s on {cores} threads ({platform.processor() or platform.machine()})"}
 
 
+def measure_batched(lbm, workloads, torch, nlat, steps, mode, warmup=5, persistent_steps=0):
+    """The batching workload: nlat seeded lattices of uneven size, tau and c^2
+    (FP32) in one pool, stepped `steps` times by one call (in persistent mode
+    one cooperative launch); compared with the plain single-lattice kernel
+    stepping the same lattices one launch each."""
+    specs = workloads.batch_specs(nlat, seed=0)
+    sites = sum(s["nx"] * s["ny"] for s in specs)
+    stream = torch.cuda.Stream()
+    budget = sum(lbm.Pool.slot_bytes(s["nx"], s["ny"], "f32") for s in specs)
+    P = lbm.Pool(budget, "f32")
+    P.set_stream(stream)
+    P.set_mode({"grouped": lbm.GROUPED, "graph": lbm.GRAPH, "persistent": lbm.PERSISTENT}[mode])
+    slots = []
+    for sp in specs:
+        s = P.add(sp["nx"], sp["ny"], sp["tau"], sp["c2"])
+        P.init(s, *workloads.batch_fields(sp))
+        slots.append(s)
+    tile = P.autotune(slots, reps=3)
+    P.step(slots, warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    P.step(slots, steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    P.sync()
+    sec = e0.elapsed_time(e1) / 1e3
+    nonfinite = sum(1 for s in slots if P.totals(s)[1] != 0)
+    pers = None
+    if persistent_steps > 0 and mode != "persistent":
+        P.set_mode(lbm.PERSISTENT)
+        P.step(slots, 2)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        P.step(slots, persistent_steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        P.sync()
+        pers = sites * persistent_steps / (e0.elapsed_time(e1) / 1e3) / 1e6
+    P.close()
+    # plain kernel, one launch per lattice per step (same lattices, fewer steps)
+    psteps = max(1, steps // 10)
+    lats = []
+    for sp in specs:
+        L = lbm.Lattice(sp["nx"], sp["ny"], sp["tau"], sp["c2"], "f32")
+        L.set_stream(stream)
+        L.init(*workloads.batch_fields(sp))
+        lats.append(L)
+    for L in lats:
+        L.step(warmup)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(psteps):
+        for L in lats:
+            L.step(1)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    psec = e0.elapsed_time(e1) / 1e3
+    for L in lats:
+        L.close()
+    mlups = sites * steps / sec / 1e6
+    plain = sites * psteps / psec / 1e6
+    return {"mlups": mlups, "frac": mlups * 1e6 * BYTES_PER_SITE["f32"] / 1e9 / PEAK_HBM_GBS,
+            "lattices": nlat, "sites": sites, "steps": steps, "mode": mode, "tile": list(tile),
+            "seconds": sec, "plain_mlups": plain, "vs_plain": mlups / plain, "nonfinite_lattices": nonfinite,
+            "persistent_mlups": pers}
+
+
 def copy_probe(torch):
     """Device-to-device copy of 1 GiB, 20 times (reference kernel for the HBM
     byte counters: 1 GiB read + 1 GiB written per dispatch)."""
@@ -177,6 +251,13 @@ def main():
     for f in [s for s in a.forms.split(",") if s]:
         forms[f] = measure_form(lbm, workloads, torch, n, f, a.form_steps, a.warmup)
         print(f"# form {f}: {forms[f]['mlups']:.0f} MLUPS, {100 * forms[f]['frac']:.1f}% of HBM peak",
+              file=sys.stderr, flush=True)
+
+    if a.batch > 0:
+        forms["batched_f32"] = measure_batched(lbm, workloads, torch, a.batch, a.batch_steps, a.batch_mode,
+                                               persistent_steps=a.batch_persistent_steps)
+        print(f"# batched: {forms['batched_f32']['mlups']:.0f} MLUPS over {a.batch} lattices "
+              f"({forms['batched_f32']['vs_plain']:.2f}x the plain kernel one lattice at a time)",
               file=sys.stderr, flush=True)
 
     cpu = None if a.no_cpu else cpu_baseline(workloads, n, a.cpu_steps)

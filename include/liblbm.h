@@ -143,6 +143,16 @@ enum lbm_tile_flags {
 int lbm_set_tile(lbm_lattice* L, int vx, int nw, int h, int flags);
 int lbm_get_tile(const lbm_lattice* L, int* vx, int* nw, int* h, int* flags);
 
+/* Autotuner: time the candidate kernel shapes on this lattice (reps timed
+ * launches each, after two warm-up launches; every launch reads the current
+ * state and writes the spare buffer, so the state is unchanged) and apply the
+ * fastest. With use_cache != 0 a shape found before for the same GPU
+ * architecture, dtype and nx x ny is applied without timing. Results are
+ * remembered for the process and, if the environment variable LBM_TUNE_CACHE
+ * names a file, appended to it (one JSON object per line). Synchronous.
+ * LBM_ESTATE before init. */
+int lbm_autotune(lbm_lattice* L, int reps, int use_cache);
+
 /* ---------------------------------------------------------------------------
  * Pools: the batched and served forms. A pool holds resident lattices
  * (slots) of one dtype, each with its own nx, ny, tau and c2, under a device
@@ -206,6 +216,15 @@ int lbm_pool_set_mode(lbm_pool* P, int mode, int max_grid);
  * {4, 8, 16}, flags 0 or LBM_TILE_NT_STORE. Does not change results. */
 int lbm_pool_set_tile(lbm_pool* P, int vx, int nw, int flags);
 int lbm_pool_get_tile(const lbm_pool* P, int* vx, int* nw, int* flags);
+/* Tiles per work item of the batched kernels (1..64, default 4): a
+ * workgroup takes that many consecutive tiles of one lattice, paying the
+ * lattice lookup once. Does not change results. */
+int lbm_pool_set_items(lbm_pool* P, int tiles_per_item);
+/* Autotuner for the batched kernels (see lbm_autotune): shape, stores and
+ * tiles per item, timed on one batched launch over the listed slots; cached
+ * per architecture, dtype, and the batch's lattice count and total sites
+ * rounded up to powers of two. */
+int lbm_pool_autotune(lbm_pool* P, const int* slots, int count, int reps, int use_cache);
 /* Use an existing (non-null) HIP stream for the pool's work; NULL selects
  * the pool's own non-blocking stream (the default). Synchronises the
  * previous stream. */

@@ -59,8 +59,11 @@ SIGNATURES = {
     "lbm_pool_set_mode": (_i, [_vp, _i, _i]),
     "lbm_pool_set_tile": (_i, [_vp, _i, _i, _i]),
     "lbm_pool_get_tile": (_i, [_vp, _vp, _vp, _vp]),
+    "lbm_pool_set_items": (_i, [_vp, _i]),
     "lbm_pool_set_stream": (_i, [_vp, _vp]),
     "lbm_set_tile": (_i, [_vp, _i, _i, _i, _i]),
+    "lbm_autotune": (_i, [_vp, _i, _i]),
+    "lbm_pool_autotune": (_i, [_vp, _vp, _i, _i, _i]),
     "lbm_get_tile": (_i, [_vp, _vp, _vp, _vp, _vp]),
 }
 

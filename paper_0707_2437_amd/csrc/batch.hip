@@ -12,48 +12,43 @@
 
 namespace lbm {
 
-// Batch tile t -> lattice index: the last lattice whose first tile is <= t
-// (tile_begin is a prefix sum; a uniform binary search per workgroup).
-__device__ __forceinline__ int batch_lattice(const BatchLat* __restrict__ lats, int nlat, int t)
-{
-    int lo = 0, hi = nlat - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (lats[mid].tile_begin <= t) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
-
+// One work item: up to per_item consecutive tiles (row-band order: adjacent
+// strips of one row group, then the next group) of one lattice. The item's
+// lattice comes from a direct map, so a workgroup pays two dependent loads
+// (map, descriptor) per item instead of a search per tile. Returns whether
+// the item had work (uniform per workgroup); the caller places a barrier
+// before reusing lds.
 template <class T, bool SHIFT, int VX, int NW, bool NTS>
-__device__ __forceinline__ void batch_tile(const BatchLat* __restrict__ lats, int nlat, int t, int s,
-                                           typename CompT<T>::type (&lds)[NW][64 * VX], bool& did)
+__device__ __forceinline__ bool batch_item(const BatchLat* __restrict__ lats, const int* __restrict__ item_lat, int i,
+                                           int s, typename CompT<T>::type (&lds)[NW][64 * VX])
 {
-    const int l = batch_lattice(lats, nlat, t);
-    const BatchLat& L = lats[l];
-    did = s < L.nsteps;
-    if (!did) return;  // uniform per workgroup
-    const int lt = t - L.tile_begin;
+    const BatchLat& L = lats[item_lat[i]];
+    if (s >= L.nsteps) return false;
     const bool odd = ((L.t0 + s) & 1) != 0;
     const void* src = odd ? L.tile.dst : L.tile.src;
     void* dst = odd ? const_cast<void*>(L.tile.src) : L.tile.dst;
-    vstack_tile<T, SHIFT, VX, NW, NTS>(L.tile, src, dst, lt % L.tile.nstrips, lt / L.tile.nstrips, lds);
+    const int t0 = (i - L.item_begin) * L.per_item;
+    const int t1 = min(t0 + L.per_item, L.ntiles);
+    for (int t = t0; t < t1; ++t) {
+        if (t > t0) __syncthreads();  // lds of the previous tile is still being read
+        vstack_tile<T, SHIFT, VX, NW, NTS>(L.tile, src, dst, t % L.tile.nstrips, t / L.tile.nstrips, lds);
+    }
+    return true;
 }
 
-// One step s of every lattice of the batch; one workgroup per tile, tiles
+// One step s of every lattice of the batch; one workgroup per item, items
 // of a lattice contiguous and spread over the XCDs in contiguous runs.
 template <class T, bool SHIFT, int VX, int NW, bool NTS>
-__global__ __launch_bounds__(64 * NW) void batch_step_kernel(const BatchLat* __restrict__ lats, int nlat, int ntiles,
-                                                             int s)
+__global__ __launch_bounds__(64 * NW) void batch_step_kernel(const BatchLat* __restrict__ lats,
+                                                             const int* __restrict__ item_lat, int nitems, int s)
 {
     using C = typename CompT<T>::type;
     __shared__ C lds[NW][64 * VX];
     const int nb = gridDim.x;  // a multiple of 8
     const int b = blockIdx.x;
-    const int t = (b & 7) * (nb >> 3) + (b >> 3);
-    if (t >= ntiles) return;
-    bool did;
-    batch_tile<T, SHIFT, VX, NW, NTS>(lats, nlat, t, s, lds, did);
+    const int i = (b & 7) * (nb >> 3) + (b >> 3);
+    if (i >= nitems) return;
+    batch_item<T, SHIFT, VX, NW, NTS>(lats, item_lat, i, s, lds);
 }
 
 // Grid barrier for the persistent kernel: a counter and a generation word in
@@ -100,18 +95,15 @@ __device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned nblocks, un
 // barrier before the next step reads what this one wrote. Launched only
 // with a grid that is co-resident (hipLaunchCooperativeKernel checks it).
 template <class T, bool SHIFT, int VX, int NW, bool NTS>
-__global__ __launch_bounds__(64 * NW) void batch_persistent_kernel(const BatchLat* __restrict__ lats, int nlat,
-                                                                   int ntiles, int nsteps_max, unsigned* bar,
-                                                                   unsigned spin_limit)
+__global__ __launch_bounds__(64 * NW) void batch_persistent_kernel(const BatchLat* __restrict__ lats,
+                                                                   const int* __restrict__ item_lat, int nitems,
+                                                                   int nsteps_max, unsigned* bar, unsigned spin_limit)
 {
     using C = typename CompT<T>::type;
     __shared__ C lds[NW][64 * VX];
     for (int s = 0; s < nsteps_max; ++s) {
-        for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-            bool did;
-            batch_tile<T, SHIFT, VX, NW, NTS>(lats, nlat, t, s, lds, did);
-            if (did) __syncthreads();  // lds is reused by the next tile
-        }
+        for (int i = blockIdx.x; i < nitems; i += gridDim.x)
+            if (batch_item<T, SHIFT, VX, NW, NTS>(lats, item_lat, i, s, lds)) __syncthreads();
         if (!grid_barrier(bar, gridDim.x, spin_limit)) return;
     }
 }
@@ -120,13 +112,13 @@ __global__ __launch_bounds__(64 * NW) void batch_persistent_kernel(const BatchLa
 // Host-side launchers.
 
 template <class T, bool SHIFT, int VX, int NW, bool NTS>
-static hipError_t launch_batch_t(bool persistent, const BatchLat* lats, int nlat, int ntiles, int s_or_n,
-                                 int max_grid, unsigned* bar, hipStream_t st)
+static hipError_t launch_batch_t(bool persistent, const BatchLat* lats, const int* item_lat, int nitems,
+                                 int s_or_n, int max_grid, unsigned* bar, hipStream_t st)
 {
     if (!persistent) {
-        const int grid = (ntiles + 7) / 8 * 8;
-        hipLaunchKernelGGL((batch_step_kernel<T, SHIFT, VX, NW, NTS>), dim3(grid), dim3(64 * NW), 0, st, lats, nlat,
-                           ntiles, s_or_n);
+        const int grid = (nitems + 7) / 8 * 8;
+        hipLaunchKernelGGL((batch_step_kernel<T, SHIFT, VX, NW, NTS>), dim3(grid), dim3(64 * NW), 0, st, lats,
+                           item_lat, nitems, s_or_n);
         return hipGetLastError();
     }
     auto kern = batch_persistent_kernel<T, SHIFT, VX, NW, NTS>;
@@ -137,20 +129,20 @@ static hipError_t launch_batch_t(bool persistent, const BatchLat* lats, int nlat
     if (e != hipSuccess) return e;
     int grid = per_cu * ncu;
     if (max_grid > 0 && grid > max_grid) grid = max_grid;
-    if (grid > ntiles) grid = ntiles;
+    if (grid > nitems) grid = nitems;
     if (grid < 1) return hipErrorInvalidConfiguration;
     unsigned spin_limit = 1u << 24;  // ~1 s of polling at one poll per ~64 ns
-    void* args[] = {(void*)&lats, (void*)&nlat, (void*)&ntiles, (void*)&s_or_n, (void*)&bar, (void*)&spin_limit};
+    void* args[] = {(void*)&lats, (void*)&item_lat, (void*)&nitems, (void*)&s_or_n, (void*)&bar, (void*)&spin_limit};
     return hipLaunchCooperativeKernel((const void*)kern, dim3(grid), dim3(64 * NW), args, 0, st);
 }
 
 template <class T, bool SHIFT, int VX>
-static hipError_t launch_batch_nw(int nw, bool nts, bool persistent, const BatchLat* lats, int nlat, int ntiles,
-                                  int s_or_n, int max_grid, unsigned* bar, hipStream_t st)
+static hipError_t launch_batch_nw(int nw, bool nts, bool persistent, const BatchLat* lats, const int* item_lat,
+                                  int nitems, int s_or_n, int max_grid, unsigned* bar, hipStream_t st)
 {
 #define LBM_B(NWV)                                                                                                   \
-    return nts ? launch_batch_t<T, SHIFT, VX, NWV, true>(persistent, lats, nlat, ntiles, s_or_n, max_grid, bar, st)  \
-               : launch_batch_t<T, SHIFT, VX, NWV, false>(persistent, lats, nlat, ntiles, s_or_n, max_grid, bar, st)
+    return nts ? launch_batch_t<T, SHIFT, VX, NWV, true>(persistent, lats, item_lat, nitems, s_or_n, max_grid, bar, st)  \
+               : launch_batch_t<T, SHIFT, VX, NWV, false>(persistent, lats, item_lat, nitems, s_or_n, max_grid, bar, st)
     switch (nw) {
     case 4: LBM_B(4);
     case 8: LBM_B(8);
@@ -161,25 +153,27 @@ static hipError_t launch_batch_nw(int nw, bool nts, bool persistent, const Batch
 }
 
 template <class T, bool SHIFT>
-static hipError_t launch_batch_vx(int vx, int nw, bool nts, bool persistent, const BatchLat* lats, int nlat,
-                                  int ntiles, int s_or_n, int max_grid, unsigned* bar, hipStream_t st)
+static hipError_t launch_batch_vx(int vx, int nw, bool nts, bool persistent, const BatchLat* lats,
+                                  const int* item_lat, int nitems, int s_or_n, int max_grid, unsigned* bar,
+                                  hipStream_t st)
 {
     switch (vx) {
-    case 1: return launch_batch_nw<T, SHIFT, 1>(nw, nts, persistent, lats, nlat, ntiles, s_or_n, max_grid, bar, st);
-    case 2: return launch_batch_nw<T, SHIFT, 2>(nw, nts, persistent, lats, nlat, ntiles, s_or_n, max_grid, bar, st);
-    case 4: return launch_batch_nw<T, SHIFT, 4>(nw, nts, persistent, lats, nlat, ntiles, s_or_n, max_grid, bar, st);
+    case 1: return launch_batch_nw<T, SHIFT, 1>(nw, nts, persistent, lats, item_lat, nitems, s_or_n, max_grid, bar, st);
+    case 2: return launch_batch_nw<T, SHIFT, 2>(nw, nts, persistent, lats, item_lat, nitems, s_or_n, max_grid, bar, st);
+    case 4: return launch_batch_nw<T, SHIFT, 4>(nw, nts, persistent, lats, item_lat, nitems, s_or_n, max_grid, bar, st);
     default: return hipErrorInvalidValue;
     }
 }
 
-// Grouped (persistent = false): step s_or_n of the batch, one launch.
+// Grouped (persistent = false): step s_or_n of the batch, one launch, one
+// workgroup per item.
 // Persistent: s_or_n steps in one cooperative launch, at most max_grid
 // workgroups (<= 0: as many as are co-resident), barrier state in `bar`
 // (3 words, zero-initialised; bar[2] becomes 1 if a barrier timed out).
-hipError_t launch_batch(int dtype, int vx, int nw, bool nts, bool persistent, const BatchLat* lats, int nlat,
-                        int ntiles, int s_or_n, int max_grid, unsigned* bar, hipStream_t st)
+hipError_t launch_batch(int dtype, int vx, int nw, bool nts, bool persistent, const BatchLat* lats,
+                        const int* item_lat, int nitems, int s_or_n, int max_grid, unsigned* bar, hipStream_t st)
 {
-#define LBM_BV(T, S) launch_batch_vx<T, S>(vx, nw, nts, persistent, lats, nlat, ntiles, s_or_n, max_grid, bar, st)
+#define LBM_BV(T, S) launch_batch_vx<T, S>(vx, nw, nts, persistent, lats, item_lat, nitems, s_or_n, max_grid, bar, st)
     switch (dtype) {
     case 0: return LBM_BV(double, false);
     case 1: return LBM_BV(float, false);

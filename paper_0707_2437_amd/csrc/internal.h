@@ -56,11 +56,16 @@ struct StepTile {
 // tile.src holds the buffer of even times and tile.dst the buffer of odd
 // times: at step s of the call the lattice is at time t0 + s, reads buffer
 // (t0 + s) & 1 and writes the other. Lattices with s >= nsteps sit out.
+// The batch's work is cut into items of up to `per_item` consecutive tiles
+// of one lattice; item i belongs to lattice item_lat[i] (a device array),
+// and the lattice's items are item_begin .. item_begin + nitems - 1.
 struct BatchLat {
     StepTile tile;
     long long t0;    // lattice time when the call starts
     int nsteps;      // steps this lattice takes in the call
-    int tile_begin;  // first batch tile of this lattice (prefix sum)
+    int item_begin;  // first batch item of this lattice
+    int ntiles;      // tiles of this lattice (tile.nstrips * tile.nchunks)
+    int per_item;    // tiles per item
 };
 
 }  // namespace lbm

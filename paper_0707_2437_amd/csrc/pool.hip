@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "host.h"
+#include "tune.h"
 
 using namespace lbm;
 
@@ -30,8 +31,9 @@ struct Slot {
 };
 
 struct GraphEntry {
-    int nsteps_max = 0, nlat = 0, ntiles = 0, vx = 0, nw = 0, nts = 0;
+    int nsteps_max = 0, nitems = 0, vx = 0, nw = 0, nts = 0;
     const BatchLat* lats = nullptr;
+    const int* items = nullptr;
     hipGraphExec_t exec = nullptr;
 };
 
@@ -46,9 +48,12 @@ struct lbm_pool {
     int mode = LBM_POOL_GROUPED;
     int max_grid = 0;             // persistent mode: workgroup cap (0 = all co-resident)
     BatchLat* d_lats = nullptr;   // device descriptor array
+    int* d_items = nullptr;       // device item -> lattice map
     unsigned* d_bar = nullptr;    // grid-barrier state of the persistent kernel (3 words)
-    int cap = 0;
+    int cap = 0, item_cap = 0;
+    int per_item = 4;             // tiles per work item
     std::vector<BatchLat> h_lats;
+    std::vector<int> h_items;
     std::vector<GraphEntry> graphs;
 };
 
@@ -94,40 +99,70 @@ StepTile slot_tile(const lbm_pool* P, const Slot& S)
     return t;
 }
 
-hipError_t ensure_cap(lbm_pool* P, int n)
+hipError_t ensure_cap(lbm_pool* P, int n, int nitems)
 {
-    if (n <= P->cap) return hipSuccess;
-    int cap = std::max(n, std::max(16, 2 * P->cap));
-    BatchLat* d = nullptr;
-    hipError_t e = hipMalloc((void**)&d, sizeof(BatchLat) * (size_t)cap);
-    if (e != hipSuccess) return e;
-    if (P->d_lats) {
-        (void)hipStreamSynchronize(P->stream);
-        (void)hipFree(P->d_lats);
+    if (n > P->cap) {
+        int cap = std::max(n, std::max(16, 2 * P->cap));
+        BatchLat* d = nullptr;
+        hipError_t e = hipMalloc((void**)&d, sizeof(BatchLat) * (size_t)cap);
+        if (e != hipSuccess) return e;
+        if (P->d_lats) {
+            (void)hipStreamSynchronize(P->stream);
+            (void)hipFree(P->d_lats);
+        }
+        drop_graphs(P);  // they hold the old descriptor pointer
+        P->d_lats = d;
+        P->cap = cap;
     }
-    drop_graphs(P);  // they hold the old descriptor pointer
-    P->d_lats = d;
-    P->cap = cap;
+    if (nitems > P->item_cap) {
+        int cap = std::max(nitems, std::max(1024, 2 * P->item_cap));
+        int* d = nullptr;
+        hipError_t e = hipMalloc((void**)&d, sizeof(int) * (size_t)cap);
+        if (e != hipSuccess) return e;
+        if (P->d_items) {
+            (void)hipStreamSynchronize(P->stream);
+            (void)hipFree(P->d_items);
+        }
+        drop_graphs(P);
+        P->d_items = d;
+        P->item_cap = cap;
+    }
     return hipSuccess;
 }
 
-// Run the batch described by h_lats (already built) for nmax steps.
-hipError_t run_batch(lbm_pool* P, int nlat, int ntiles, int nmax)
+// Append lattice descriptor b (tile already set) and its work items.
+void add_lattice(lbm_pool* P, BatchLat b)
 {
-    hipError_t e = ensure_cap(P, nlat);
+    b.ntiles = b.tile.nstrips * b.tile.nchunks;
+    b.per_item = P->per_item;
+    b.item_begin = (int)P->h_items.size();
+    const int nitems = (b.ntiles + b.per_item - 1) / b.per_item;
+    const int l = (int)P->h_lats.size();
+    for (int k = 0; k < nitems; ++k) P->h_items.push_back(l);
+    P->h_lats.push_back(b);
+}
+
+// Run the batch described by h_lats / h_items (already built) for nmax steps.
+hipError_t run_batch(lbm_pool* P, int nmax)
+{
+    const int nlat = (int)P->h_lats.size(), nitems = (int)P->h_items.size();
+    hipError_t e = ensure_cap(P, nlat, nitems);
     if (e != hipSuccess) return e;
     e = hipMemcpyAsync(P->d_lats, P->h_lats.data(), sizeof(BatchLat) * (size_t)nlat, hipMemcpyHostToDevice,
                        P->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(P->d_items, P->h_items.data(), sizeof(int) * (size_t)nitems, hipMemcpyHostToDevice,
+                           P->stream);
     if (e != hipSuccess) return e;
     const bool nts = P->nts != 0;
     if (P->mode == LBM_POOL_PERSISTENT)
-        return launch_batch(P->dtype, P->vx, P->nw, nts, true, P->d_lats, nlat, ntiles, nmax, P->max_grid, P->d_bar,
-                            P->stream);
+        return launch_batch(P->dtype, P->vx, P->nw, nts, true, P->d_lats, P->d_items, nitems, nmax, P->max_grid,
+                            P->d_bar, P->stream);
     if (P->mode == LBM_POOL_GRAPH) {
         GraphEntry* ge = nullptr;
         for (auto& g : P->graphs)
-            if (g.nsteps_max == nmax && g.nlat == nlat && g.ntiles == ntiles && g.vx == P->vx && g.nw == P->nw &&
-                g.nts == P->nts && g.lats == P->d_lats)
+            if (g.nsteps_max == nmax && g.nitems == nitems && g.vx == P->vx && g.nw == P->nw && g.nts == P->nts &&
+                g.lats == P->d_lats && g.items == P->d_items)
                 ge = &g;
         if (!ge) {
             // Capture nmax grouped launches once; replays re-read the
@@ -137,7 +172,7 @@ hipError_t run_batch(lbm_pool* P, int nlat, int ntiles, int nmax)
             if (e != hipSuccess) return e;
             hipError_t le = hipSuccess;
             for (int s = 0; s < nmax && le == hipSuccess; ++s)
-                le = launch_batch(P->dtype, P->vx, P->nw, nts, false, P->d_lats, nlat, ntiles, s, 0, nullptr,
+                le = launch_batch(P->dtype, P->vx, P->nw, nts, false, P->d_lats, P->d_items, nitems, s, 0, nullptr,
                                   P->stream);
             e = hipStreamEndCapture(P->stream, &graph);
             if (le != hipSuccess) e = le;
@@ -149,13 +184,13 @@ hipError_t run_batch(lbm_pool* P, int nlat, int ntiles, int nmax)
                 (void)hipGraphExecDestroy(P->graphs.front().exec);
                 P->graphs.erase(P->graphs.begin());
             }
-            P->graphs.push_back(GraphEntry{nmax, nlat, ntiles, P->vx, P->nw, P->nts, P->d_lats, exec});
+            P->graphs.push_back(GraphEntry{nmax, nitems, P->vx, P->nw, P->nts, P->d_lats, P->d_items, exec});
             ge = &P->graphs.back();
         }
         return hipGraphLaunch(ge->exec, P->stream);
     }
     for (int s = 0; s < nmax && e == hipSuccess; ++s)
-        e = launch_batch(P->dtype, P->vx, P->nw, nts, false, P->d_lats, nlat, ntiles, s, 0, nullptr, P->stream);
+        e = launch_batch(P->dtype, P->vx, P->nw, nts, false, P->d_lats, P->d_items, nitems, s, 0, nullptr, P->stream);
     return e;
 }
 
@@ -212,6 +247,7 @@ void lbm_pool_destroy(lbm_pool* P)
         if (S.red) (void)hipFree(S.red);
     }
     if (P->d_lats) (void)hipFree(P->d_lats);
+    if (P->d_items) (void)hipFree(P->d_items);
     if (P->d_bar) (void)hipFree(P->d_bar);
     if (P->own) (void)hipStreamDestroy(P->own);
     delete P;
@@ -311,7 +347,8 @@ int lbm_pool_step(lbm_pool* P, const int* slots, const int* nsteps, int count)
 {
     if (!P || count < 0 || (count > 0 && (!slots || !nsteps))) return LBM_EINVAL;
     P->h_lats.clear();
-    int ntiles = 0, nmax = 0;
+    P->h_items.clear();
+    int nmax = 0;
     for (int k = 0; k < count; ++k) {
         Slot* S = slot_of(P, slots[k]);
         if (!S || nsteps[k] < 0) return LBM_EINVAL;
@@ -323,14 +360,11 @@ int lbm_pool_step(lbm_pool* P, const int* slots, const int* nsteps, int count)
         b.tile = slot_tile(P, *S);
         b.t0 = S->t;
         b.nsteps = nsteps[k];
-        b.tile_begin = ntiles;
-        ntiles += b.tile.nstrips * b.tile.nchunks;
+        add_lattice(P, b);
         nmax = std::max(nmax, nsteps[k]);
-        P->h_lats.push_back(b);
     }
     if (P->h_lats.empty()) return LBM_OK;
-    const int nlat = (int)P->h_lats.size();
-    hipError_t e = run_batch(P, nlat, ntiles, nmax);
+    hipError_t e = run_batch(P, nmax);
     if (e != hipSuccess) return status_of(e);
     for (int k = 0; k < count; ++k) P->slots[slots[k]].t += nsteps[k];
     return LBM_OK;
@@ -414,6 +448,72 @@ int lbm_pool_set_tile(lbm_pool* P, int vx, int nw, int flags)
     P->nw = nw;
     P->nts = (flags & LBM_TILE_NT_STORE) ? 1 : 0;
     return status_of(e);
+}
+
+int lbm_pool_autotune(lbm_pool* P, const int* slots, int count, int reps, int use_cache)
+{
+    if (!P || reps < 1 || count < 1 || !slots) return LBM_EINVAL;
+    long long sites = 0;
+    for (int k = 0; k < count; ++k) {
+        Slot* S = slot_of(P, slots[k]);
+        if (!S) return LBM_EINVAL;
+        if (!S->ready) return LBM_ESTATE;
+        sites += (long long)S->nx * S->ny;
+    }
+    // key: the batch's lattice count and total sites, rounded to powers of 2
+    int lc = 0, ls = 0;
+    while ((1 << lc) < count) ++lc;
+    while ((1LL << ls) < sites) ++ls;
+    char key[160];
+    std::snprintf(key, sizeof(key), "%s|pool|%d|n2^%d|s2^%d", device_arch().c_str(), P->dtype, lc, ls);
+    TileCand c{};
+    if (use_cache && tune_cache_get(key, &c)) return lbm_pool_set_tile(P, c.vx, c.nw, c.flags);
+    const std::vector<TileCand> cands = pool_candidates(P->dtype);
+    // one batched launch at step 0 of a 1-step call: reads each slot's
+    // current buffer and writes the other, without advancing any slot
+    auto launch = [&](const TileCand& k) -> hipError_t {
+        const int ovx = P->vx, onw = P->nw, opi = P->per_item;
+        P->vx = k.vx;
+        P->nw = k.nw;
+        P->per_item = k.h;
+        P->h_lats.clear();
+        P->h_items.clear();
+        for (int j = 0; j < count; ++j) {
+            BatchLat b{};
+            b.tile = slot_tile(P, P->slots[slots[j]]);
+            b.t0 = P->slots[slots[j]].t;
+            b.nsteps = 1;
+            add_lattice(P, b);
+        }
+        P->vx = ovx;
+        P->nw = onw;
+        P->per_item = opi;
+        const int nitems = (int)P->h_items.size();
+        hipError_t le = ensure_cap(P, count, nitems);
+        if (le == hipSuccess)
+            le = hipMemcpyAsync(P->d_lats, P->h_lats.data(), sizeof(BatchLat) * (size_t)count, hipMemcpyHostToDevice,
+                                P->stream);
+        if (le == hipSuccess)
+            le = hipMemcpyAsync(P->d_items, P->h_items.data(), sizeof(int) * (size_t)nitems, hipMemcpyHostToDevice,
+                                P->stream);
+        if (le == hipSuccess)
+            le = launch_batch(P->dtype, k.vx, k.nw, (k.flags & LBM_TILE_NT_STORE) != 0, false, P->d_lats,
+                              P->d_items, nitems, 0, 0, nullptr, P->stream);
+        return le;
+    };
+    float us = 0;
+    const int best = time_candidates(cands, reps, P->stream, launch, &us);
+    if (best < 0) return LBM_EDEVICE;
+    tune_cache_put(key, cands[best], us);
+    P->per_item = cands[best].h;
+    return lbm_pool_set_tile(P, cands[best].vx, cands[best].nw, cands[best].flags);
+}
+
+int lbm_pool_set_items(lbm_pool* P, int tiles_per_item)
+{
+    if (!P || tiles_per_item < 1 || tiles_per_item > 64) return LBM_EINVAL;
+    P->per_item = tiles_per_item;
+    return LBM_OK;
 }
 
 int lbm_pool_get_tile(const lbm_pool* P, int* vx, int* nw, int* flags)

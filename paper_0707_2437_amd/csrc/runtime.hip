@@ -8,6 +8,7 @@
 #include <new>
 
 #include "host.h"
+#include "tune.h"
 
 using namespace lbm;
 
@@ -199,6 +200,31 @@ int lbm_set_tile(lbm_lattice* L, int vx, int nw, int h, int flags)
     L->h = h;
     L->kflags = flags;
     return LBM_OK;
+}
+
+int lbm_autotune(lbm_lattice* L, int reps, int use_cache)
+{
+    if (!L || reps < 1) return LBM_EINVAL;
+    if (!L->ready) return LBM_ESTATE;
+    char key[160];
+    std::snprintf(key, sizeof(key), "%s|lattice|%d|%dx%d", device_arch().c_str(), L->dtype, L->nx, L->ny);
+    TileCand c{};
+    if (use_cache && tune_cache_get(key, &c)) return lbm_set_tile(L, c.vx, c.nw, c.h, c.flags);
+    const std::vector<TileCand> cands = lattice_candidates(L->dtype);
+    // read cur, write nxt, no swap: the state does not change
+    auto launch = [&](const TileCand& k) -> hipError_t {
+        lbm_lattice tmp = *L;
+        tmp.vx = k.vx;
+        tmp.nw = k.nw;
+        tmp.h = k.h;
+        tmp.kflags = k.flags;
+        return launch_step(L->dtype, k.vx, k.nw, k.flags, make_tile(&tmp), L->stream);
+    };
+    float us = 0;
+    const int best = time_candidates(cands, reps, L->stream, launch, &us);
+    if (best < 0) return LBM_EDEVICE;
+    tune_cache_put(key, cands[best], us);
+    return lbm_set_tile(L, cands[best].vx, cands[best].nw, cands[best].h, cands[best].flags);
 }
 
 int lbm_get_tile(const lbm_lattice* L, int* vx, int* nw, int* h, int* flags)

@@ -174,6 +174,11 @@ class Lattice:
         _check(self._L.lbm_set_tile(self._h, int(vx), int(nw), int(h), int(flags)), "lbm_set_tile")
         return self
 
+    def autotune(self, reps=5, use_cache=True):
+        """Time the candidate kernel shapes on this lattice and keep the fastest."""
+        _check(self._L.lbm_autotune(self._h, int(reps), int(bool(use_cache))), "lbm_autotune")
+        return self.get_tile()
+
     def get_tile(self):
         v, w, h, f = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         _check(self._L.lbm_get_tile(self._h, ctypes.byref(v), ctypes.byref(w), ctypes.byref(h), ctypes.byref(f)),

@@ -124,6 +124,16 @@ class Pool:
     def set_tile(self, vx, nw, flags=0):
         _check(self._L.lbm_pool_set_tile(self._h, int(vx), int(nw), int(flags)), "lbm_pool_set_tile")
 
+    def autotune(self, slots, reps=3, use_cache=True):
+        """Time the batched kernels' tile shapes on one launch over `slots` and keep the fastest."""
+        slots = np.ascontiguousarray(slots, dtype=np.int32)
+        _check(self._L.lbm_pool_autotune(self._h, _hptr(slots), len(slots), int(reps), int(bool(use_cache))),
+               "lbm_pool_autotune")
+        return self.get_tile()
+
+    def set_items(self, tiles_per_item):
+        _check(self._L.lbm_pool_set_items(self._h, int(tiles_per_item)), "lbm_pool_set_items")
+
     def get_tile(self):
         v, w, f = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         _check(self._L.lbm_pool_get_tile(self._h, ctypes.byref(v), ctypes.byref(w), ctypes.byref(f)),

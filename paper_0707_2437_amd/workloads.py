@@ -47,3 +47,23 @@ def gaussian_pulse_fields(nx, ny, amp, sigma=None):
     x, y = grid(nx, ny)
     r2 = (x - nx / 2.0) ** 2 + (y - ny / 2.0) ** 2
     return 1.0 + amp * np.exp(-r2 / (2.0 * sigma * sigma)), None, None
+
+
+def batch_specs(n=256, seed=0, lo=64, hi=1024):
+    """The batching workload: n independent periodic lattices with
+    nx, ny ~ U{lo..hi}, tau ~ U[0.55, 1.5], c^2 ~ U[0.04, 0.6] (inside the
+    linearly stable range for tau >= 0.55) and a centred Gaussian density
+    pulse of amplitude ~ U[0.01, 0.1] (width min(nx, ny)/16) at rest.
+    Returns a list of dicts (nx, ny, tau, c2, amp)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        out.append({"nx": int(rng.integers(lo, hi + 1)), "ny": int(rng.integers(lo, hi + 1)),
+                    "tau": float(rng.uniform(0.55, 1.5)), "c2": float(rng.uniform(0.04, 0.6)),
+                    "amp": float(rng.uniform(0.01, 0.1))})
+    return out
+
+
+def batch_fields(spec):
+    """Initial fields of one lattice of batch_specs()."""
+    return gaussian_pulse_fields(spec["nx"], spec["ny"], spec["amp"])

@@ -60,11 +60,12 @@ def test_persistent_with_few_workgroups_bitwise():
         assert np.array_equal(g, run_alone(nx, ny, tau, c2, n, "f32", f))
 
 
-@pytest.mark.parametrize("tile", [(1, 4, 0), (2, 16, 2), (4, 8, 0)])
-def test_pool_tile_does_not_change_results(tile):
+@pytest.mark.parametrize("tile,per_item", [((1, 4, 0), 1), ((2, 16, 2), 3), ((4, 8, 0), 8), ((2, 8, 2), 64)])
+def test_pool_tile_does_not_change_results(tile, per_item):
     fields = [smooth_random_state(nx, ny, seed=k) for k, (nx, ny, *_) in enumerate(CASES)]
     with lbm.Pool(1 << 30, "f64") as P:
         P.set_tile(*tile)
+        P.set_items(per_item)
         slots = [P.add(nx, ny, tau, c2) for (nx, ny, tau, c2, _) in CASES]
         for s, f in zip(slots, fields):
             P.init(s, *f)
