@@ -5,7 +5,9 @@ Workload (one "step"): one time step of each of five periodic 4096 x 4096
 lattices, tau = 0.6, c^2 in {0.04, 0.2, 1/3, 0.5, 0.81} (c_e = 0.2 ... 0.9),
 each initialised with a plane sound wave of amplitude 1e-3 plus seeded
 uniform density noise +-1e-4. Headline: FP32 storage and arithmetic. The
-same sweep in FP64 is reported under "forms".
+same sweep in FP64 is reported under "forms", beside the batched form (256
+seeded lattices of uneven size, tau and c^2 in one pool) and the served form
+(a continuous-batching server fed Poisson job arrivals for a short window).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 
@@ -44,6 +46,10 @@ def parse():
     p.add_argument("--batch-mode", default="graph", choices=["grouped", "graph", "persistent"])
     p.add_argument("--batch-persistent-steps", type=int, default=200,
                    help="also time the persistent cooperative form for this many steps (0: skip)")
+    p.add_argument("--serve-seconds", type=float, default=30.0,
+                   help="window of the served form (Poisson jobs at --serve-rate; 0: skip it)")
+    p.add_argument("--serve-rate", type=float, default=50.0)
+    p.add_argument("--serve-budget-gb", type=float, default=200.0)
     p.add_argument("--copy-probe", action="store_true",
                    help="only run a device copy of known size (reference for HBM byte counters)")
     return p.parse_args()
@@ -207,6 +213,20 @@ def measure_batched(lbm, workloads, torch, nlat, steps, mode, warmup=5, persiste
             "persistent_mlups": pers}
 
 
+def measure_served(serve, seconds, rate, budget_gb):
+    """The serving workload: Poisson job arrivals (sides 128..2048, 500..20000
+    steps, FP32) into a continuous-batching server with a device-memory
+    budget, for `seconds` of wall time."""
+    jobs = serve.job_stream(rate, seconds, seed=0)
+    srv = serve.Server(int(budget_gb * 1e9), "f32", tick_steps=100)
+    st = srv.run(jobs, seconds)
+    srv.close()
+    st["offered_mlups"] = serve.offered_mlups(jobs, seconds)
+    st["rate_per_s"] = rate
+    st["budget_gb"] = budget_gb
+    return st
+
+
 def copy_probe(torch):
     """Device-to-device copy of 1 GiB, 20 times (reference kernel for the HBM
     byte counters: 1 GiB read + 1 GiB written per dispatch)."""
@@ -259,6 +279,13 @@ def main():
         print(f"# batched: {forms['batched_f32']['mlups']:.0f} MLUPS over {a.batch} lattices "
               f"({forms['batched_f32']['vs_plain']:.2f}x the plain kernel one lattice at a time)",
               file=sys.stderr, flush=True)
+
+    if a.serve_seconds > 0:
+        from paper_0707_2437_amd import serve
+        forms["served_f32"] = measure_served(serve, a.serve_seconds, a.serve_rate, a.serve_budget_gb)
+        sv = forms["served_f32"]
+        print(f"# served: {sv['mlups']:.0f} MLUPS, {sv['jobs_completed']} jobs done, latency p50 "
+              f"{sv['latency_p50_s']} s p99 {sv['latency_p99_s']} s", file=sys.stderr, flush=True)
 
     cpu = None if a.no_cpu else cpu_baseline(workloads, n, a.cpu_steps)
     sweep = list(workloads.C2_SWEEP)
