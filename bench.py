@@ -46,6 +46,8 @@ def parse():
     p.add_argument("--batch-mode", default="graph", choices=["grouped", "graph", "persistent"])
     p.add_argument("--batch-persistent-steps", type=int, default=200,
                    help="also time the persistent cooperative form for this many steps (0: skip)")
+    p.add_argument("--precision-steps", type=int, default=300,
+                   help="steps of the precision workload (8192^2 shear wave, shifted FP32 / FP16; 0: skip)")
     p.add_argument("--serve-seconds", type=float, default=30.0,
                    help="window of the served form (Poisson jobs at --serve-rate; 0: skip it)")
     p.add_argument("--serve-rate", type=float, default=50.0)
@@ -213,6 +215,27 @@ def measure_batched(lbm, workloads, torch, nlat, steps, mode, warmup=5, persiste
             "persistent_mlups": pers}
 
 
+def measure_precision(lbm, workloads, torch, steps, warmup=5, n=8192):
+    """The precision workload: a periodic 8192^2 shear wave (tau = 0.7,
+    c^2 = 0.25) in the shifted FP32 and FP16 storage forms."""
+    out = {}
+    stream = torch.cuda.Stream()
+    for dtype in ("f32s", "f16s"):
+        _, ux, _ = workloads.shear_wave_fields(n, n, amp=0.01)
+        L = lbm.Lattice(n, n, 0.7, 0.25, dtype)
+        L.set_stream(stream)
+        L.init(None, ux, None)
+        del ux
+        sec, _ = time_sweep(torch, [L], steps, warmup, stream)
+        tile = L.get_tile()
+        L.close()
+        mlups = n * n * steps / sec / 1e6
+        gbs = BYTES_PER_SITE[dtype] * n * n * steps / sec / 1e9
+        out[dtype] = {"mlups": mlups, "achieved_GBs": gbs, "frac": gbs / PEAK_HBM_GBS, "steps": steps,
+                      "kernel": kernel_name(tile, dtype), "lattice": [n, n]}
+    return out
+
+
 def measure_served(serve, seconds, rate, budget_gb):
     """The serving workload: Poisson job arrivals (sides 128..2048, 500..20000
     steps, FP32) into a continuous-batching server with a device-memory
@@ -272,6 +295,12 @@ def main():
         forms[f] = measure_form(lbm, workloads, torch, n, f, a.form_steps, a.warmup)
         print(f"# form {f}: {forms[f]['mlups']:.0f} MLUPS, {100 * forms[f]['frac']:.1f}% of HBM peak",
               file=sys.stderr, flush=True)
+
+    if a.precision_steps > 0:
+        for k, v in measure_precision(lbm, workloads, torch, a.precision_steps).items():
+            forms[f"precision_{k}"] = v
+            print(f"# precision {k}: {v['mlups']:.0f} MLUPS, {100 * v['frac']:.1f}% of HBM peak",
+                  file=sys.stderr, flush=True)
 
     if a.batch > 0:
         forms["batched_f32"] = measure_batched(lbm, workloads, torch, a.batch, a.batch_steps, a.batch_mode,

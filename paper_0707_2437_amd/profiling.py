@@ -22,12 +22,16 @@ import statistics
 import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCE = os.path.join(PKG, "csrc", "kernels.hip")
+KERNEL_SOURCES = [os.path.join(PKG, "csrc", n) for n in ("kernels.hip", "step.h", "internal.h", "batch.hip")]
 
 
 def kernel_source_sha():
-    with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    """SHA-256 over the device sources of the step kernels."""
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def stats_summary(path, top=12):
