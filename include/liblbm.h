@@ -127,11 +127,13 @@ long long lbm_time(const lbm_lattice* L);
 size_t lbm_footprint_bytes(int nx, int ny, int dtype);
 
 /* Step kernel shape. vx = sites per lane along x (1, 2 or 4); flags =
- * LBM_TILE_* bits. March form (default): nw = 64-lane waves per workgroup
- * (1 or 4), each owning its own column strip of 64 * vx sites and marching
- * h >= 1 rows. Vertical-stack form (LBM_TILE_VSTACK): nw = 4, 8 or 16 waves
- * per workgroup covering one strip and nw - 2 rows (h is ignored).
- * Results do not depend on the shape (bitwise). LBM_EINVAL for an
+ * LBM_TILE_* bits. March form: nw = 64-lane waves per workgroup (1 or 4),
+ * each owning its own column strip of 64 * vx sites and marching h >= 1
+ * rows. Vertical-stack form (LBM_TILE_VSTACK): nw = 4, 8 or 16 waves per
+ * workgroup covering one strip and nw - 2 rows (h is ignored). Default:
+ * vertical stack with non-temporal stores; vx = 2 and nw = 16 for LBM_F32
+ * and LBM_F32S, vx = 2 and nw = 8 for LBM_F64, vx = 4 and nw = 8 for
+ * LBM_F16S. Results do not depend on the shape (bitwise). LBM_EINVAL for an
  * unsupported shape. lbm_get_tile: any pointer may be NULL. */
 enum lbm_tile_flags {
     LBM_TILE_PREFETCH = 1, /* issue the next row's loads before relaxing the current row */
@@ -213,10 +215,11 @@ long long lbm_pool_time(const lbm_pool* P, int slot);
  * workgroups of the cooperative launch (0: as many as are co-resident). */
 int lbm_pool_set_mode(lbm_pool* P, int mode, int max_grid);
 /* Vertical-stack tile of the batched kernels: vx in {1, 2, 4}, nw in
- * {4, 8, 16}, flags 0 or LBM_TILE_NT_STORE. Does not change results. */
+ * {4, 8, 16}, flags 0 or LBM_TILE_NT_STORE (default: vx 2, nw 16,
+ * non-temporal stores). Does not change results. */
 int lbm_pool_set_tile(lbm_pool* P, int vx, int nw, int flags);
 int lbm_pool_get_tile(const lbm_pool* P, int* vx, int* nw, int* flags);
-/* Tiles per work item of the batched kernels (1..64, default 4): a
+/* Tiles per work item of the batched kernels (1..64, default 1): a
  * workgroup takes that many consecutive tiles of one lattice, paying the
  * lattice lookup once. Does not change results. */
 int lbm_pool_set_items(lbm_pool* P, int tiles_per_item);

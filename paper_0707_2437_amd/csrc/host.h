@@ -109,7 +109,8 @@ inline size_t red_doubles(const Geom& g) { return (size_t)3 * moments_blocks(g) 
 
 inline Coef make_coef(double tau, double c2)
 {
-    // Eq. 5 with alpha = 1/3 - c2 (Eq. 8), weights of Sec. 2.
+    // Eq. 5 with alpha = 1/3 - c2 (Eq. 8), weights of Sec. 2; the 1/2 of the
+    // central differences is folded into as1, as2.
     const double om = 1.0 / tau, alpha = 1.0 / 3.0 - c2;
     const double w0 = 4.0 / 9.0, w1 = 1.0 / 9.0, w2 = 1.0 / 36.0;
     Coef k;
@@ -117,8 +118,14 @@ inline Coef make_coef(double tau, double c2)
     k.wo0 = om * w0;
     k.wo1 = om * w1;
     k.wo2 = om * w2;
-    k.as1 = 3.0 * w1 * alpha;
-    k.as2 = 3.0 * w2 * alpha;
+    k.as1 = 1.5 * w1 * alpha;
+    k.as2 = 1.5 * w2 * alpha;
+    k.om1f = (float)k.om1;
+    k.wo0f = (float)k.wo0;
+    k.wo1f = (float)k.wo1;
+    k.wo2f = (float)k.wo2;
+    k.as1f = (float)k.as1;
+    k.as2f = (float)k.as2;
     return k;
 }
 

@@ -35,9 +35,14 @@ struct Geom {
 // kernels (d_i = f_i - w_i):
 //   d*_0 = om1 d_0 + wo0 A
 //   d*_i = om1 d_i + P + Q,  d*_opp = om1 d_opp + P - Q        (pairs)
-// with om = 1/tau, om1 = 1 - om, wo_k = om w_k, as_k = 3 w_k alpha.
+// with om = 1/tau, om1 = 1 - om, wo_k = om w_k, and as_k = 3 w_k alpha / 2:
+// the source term 3 w_k alpha (e_i . grad rho) is applied to the undivided
+// central differences rho(x + 1) - rho(x - 1), so the 1/2 of the central
+// difference sits in the coefficient (an exact power-of-two scaling). The
+// FP32-compute kernels take the same values rounded once to FP32.
 struct Coef {
     double om1, wo0, wo1, wo2, as1, as2;
+    float om1f, wo0f, wo1f, wo2f, as1f, as2f;
 };
 
 // One lattice as seen by a step launch.

@@ -63,7 +63,7 @@ __global__ __launch_bounds__(64 * NW) void step_kernel(StepTile a, int ntiles)
         group = t / a.nchunks;
         chunk = t - group * a.nchunks;
     }
-    const int strip = group * NW + (int)(threadIdx.x >> 6);
+    const int strip = group * NW + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     const Geom g = a.g;
     const int x = strip * (64 * VX) + lane * VX;
@@ -107,9 +107,10 @@ __global__ __launch_bounds__(64 * NW) void step_kernel(StepTile a, int ntiles)
         for (int j = 0; j < VX; ++j) {
             // central differences at time t (Sec. 4); y +- 1 are the march's
             // next / previous rows in the order of the march direction
-            const C gx = C(0.5) * (wc[j + 2] - wc[j]);
+            // (undivided: the 1/2 is in the source coefficient)
+            const C gx = wc[j + 2] - wc[j];
             const C up = wn[j + 1], dw = rprev[j];
-            const C gy = dir > 0 ? C(0.5) * (up - dw) : C(0.5) * (dw - up);
+            const C gy = dir > 0 ? up - dw : dw - up;
             C o[9];
             collide<T, SHIFT, C, VX>(dc, j, wc[j + 1], gx, gy, k, o);
 #pragma unroll
@@ -165,7 +166,8 @@ __global__ __launch_bounds__(64 * NW) void step_kernel(StepTile a, int ntiles)
 // row is read (R + 2) / R times; the extra reads of the boundary rows are
 // served by L2 when the neighbouring group is resident on the same XCD.
 template <class T, bool SHIFT, int VX, int NW, bool NTS>
-__global__ __launch_bounds__(64 * NW) void step_vstack_kernel(StepTile a, int ntiles)
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(MinWaves<T>::value, 8))) void step_vstack_kernel(
+    StepTile a, int ntiles)
 {
     using C = typename CompT<T>::type;
     __shared__ C lds[NW][64 * VX];

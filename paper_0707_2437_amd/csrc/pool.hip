@@ -44,14 +44,14 @@ struct lbm_pool {
     size_t budget = 0, used = 0;
     std::vector<Slot> slots;
     hipStream_t own = nullptr, stream = nullptr;
-    int vx = 2, nw = 8, nts = 0;  // vertical-stack tile of the batched kernels
+    int vx = 2, nw = 16, nts = 1; // vertical-stack tile of the batched kernels
     int mode = LBM_POOL_GROUPED;
     int max_grid = 0;             // persistent mode: workgroup cap (0 = all co-resident)
     BatchLat* d_lats = nullptr;   // device descriptor array
     int* d_items = nullptr;       // device item -> lattice map
     unsigned* d_bar = nullptr;    // grid-barrier state of the persistent kernel (3 words)
     int cap = 0, item_cap = 0;
-    int per_item = 4;             // tiles per work item
+    int per_item = 1;             // tiles per work item
     std::vector<BatchLat> h_lats;
     std::vector<int> h_items;
     std::vector<GraphEntry> graphs;

@@ -43,9 +43,9 @@ TileDefault default_tile(int dtype)
 {
     switch (dtype) {
     case LBM_F64: return {2, 8, 8, LBM_TILE_VSTACK | LBM_TILE_NT_STORE};
-    case LBM_F32: return {2, 8, 8, LBM_TILE_VSTACK};
+    case LBM_F32: return {2, 16, 8, LBM_TILE_VSTACK | LBM_TILE_NT_STORE};
     case LBM_F32S: return {2, 16, 8, LBM_TILE_VSTACK | LBM_TILE_NT_STORE};
-    default: return {4, 8, 8, LBM_TILE_VSTACK};
+    default: return {4, 8, 8, LBM_TILE_VSTACK | LBM_TILE_NT_STORE};
     }
 }
 

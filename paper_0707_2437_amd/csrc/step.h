@@ -14,6 +14,12 @@ namespace lbm {
 template <class T> struct CompT { using type = float; };
 template <> struct CompT<double> { using type = double; };
 
+// Minimum waves per SIMD the vertical-stack kernels are compiled for. The
+// FP16 form converts every loaded value and is bound by how many tiles are
+// in flight per CU; asking for 7 waves caps it at 72 VGPRs (no spills).
+template <class T> struct MinWaves { static constexpr int value = 1; };
+template <> struct MinWaves<_Float16> { static constexpr int value = 7; };
+
 // Lattice weights (Sec. 2) in compute precision.
 template <class C> __device__ __forceinline__ C wt(int i)
 {
@@ -30,6 +36,14 @@ template <class T, bool SHIFT, class C> __device__ __forceinline__ C to_d(T v, i
 }
 template <class T, bool SHIFT, class C> __device__ __forceinline__ T from_d(C d, int i)
 {
+    if constexpr (sizeof(T) < sizeof(C)) {
+        // The relaxed value is rounded to FP32 and then to the storage type.
+        // Hide it from instruction selection, which would otherwise fuse the
+        // last FMA and the conversion into one mixed-precision FMA (a single
+        // rounding) in some kernels and not in others, and the kernels would
+        // no longer agree bit for bit.
+        asm("" : "+v"(d));
+    }
     if constexpr (SHIFT) return (T)d;
     else return (T)(wt<C>(i) + d);
 }
@@ -76,20 +90,23 @@ template <class T, int NV>
 __device__ __forceinline__ void gather_raw(const char* const (&pb)[9], const Geom& g, int r, int x, Pack<T, NV> (&v)[9])
 {
     constexpr unsigned es = sizeof(T);
-    const unsigned rs = (unsigned)g.rs * es;
-    const unsigned om = (unsigned)wrapy(r - 1, g.ny) * rs;  // source row r - 1 (e_iy = +1)
-    const unsigned o0 = (unsigned)wrapy(r, g.ny) * rs;      // source row r     (e_iy =  0)
-    const unsigned op = (unsigned)wrapy(r + 1, g.ny) * rs;  // source row r + 1 (e_iy = -1)
+    // r is uniform over the wave in every caller: the row offsets are
+    // scalar and are added to the scalar plane bases, leaving one per-lane
+    // 32-bit column offset (the +-1 column shifts become immediates).
+    const size_t rs = (size_t)g.rs * es;
+    const size_t om = (size_t)wrapy(r - 1, g.ny) * rs;  // source row r - 1 (e_iy = +1)
+    const size_t o0 = (size_t)wrapy(r, g.ny) * rs;      // source row r     (e_iy =  0)
+    const size_t op = (size_t)wrapy(r + 1, g.ny) * rs;  // source row r + 1 (e_iy = -1)
     const unsigned xm = (unsigned)x * es, x0 = xm + es, xp = xm + 2 * es;  // window starts for e_ix = +1, 0, -1
-    v[0] = ld_vec<T, NV>(pb[0], o0 + x0);
-    v[1] = ld_vec<T, NV>(pb[1], o0 + xm);
-    v[2] = ld_vec<T, NV>(pb[2], om + x0);
-    v[3] = ld_vec<T, NV>(pb[3], o0 + xp);
-    v[4] = ld_vec<T, NV>(pb[4], op + x0);
-    v[5] = ld_vec<T, NV>(pb[5], om + xm);
-    v[6] = ld_vec<T, NV>(pb[6], om + xp);
-    v[7] = ld_vec<T, NV>(pb[7], op + xp);
-    v[8] = ld_vec<T, NV>(pb[8], op + xm);
+    v[0] = ld_vec<T, NV>(pb[0] + o0, x0);
+    v[1] = ld_vec<T, NV>(pb[1] + o0, xm);
+    v[2] = ld_vec<T, NV>(pb[2] + om, x0);
+    v[3] = ld_vec<T, NV>(pb[3] + o0, xp);
+    v[4] = ld_vec<T, NV>(pb[4] + op, x0);
+    v[5] = ld_vec<T, NV>(pb[5] + om, xm);
+    v[6] = ld_vec<T, NV>(pb[6] + om, xp);
+    v[7] = ld_vec<T, NV>(pb[7] + op, xp);
+    v[8] = ld_vec<T, NV>(pb[8] + op, xm);
 }
 
 // delta rho = sum_i d_i (Eq. 3), one fixed order for every code path.
@@ -105,7 +122,8 @@ template <class C> struct CoefC {
 
 template <class C> __device__ __forceinline__ CoefC<C> coef_c(const Coef& k)
 {
-    return CoefC<C>{(C)k.om1, (C)k.wo0, (C)k.wo1, (C)k.wo2, (C)k.as1, (C)k.as2};
+    if constexpr (sizeof(C) == sizeof(float)) return CoefC<C>{k.om1f, k.wo0f, k.wo1f, k.wo2f, k.as1f, k.as2f};
+    else return CoefC<C>{k.om1, k.wo0, k.wo1, k.wo2, k.as1, k.as2};
 }
 
 // Fused multiply-add in the compute precision (the only FMAs the build emits).
@@ -119,8 +137,11 @@ template <> __device__ __forceinline__ float recip<float>(float r) { return __bu
 //   rho = 1 + drho, u = j / rho (Eq. 3)
 //   feq_i - w_i = w_i [drho + rho (3 e.u + 9/2 (e.u)^2 - 3/2 u.u)]      (Eq. 2)
 //   d*_i = d_i - (d_i - (feq_i - w_i))/tau + 3 w_i alpha (e_i . G)      (Eq. 5)
+// G is the central-difference gradient (Sec. 4); the caller passes D = 2 G
+// (the undivided differences rho(x+1) - rho(x-1), rho(y+1) - rho(y-1)) and
+// k.as = 3 w alpha / 2, which gives the same products exactly.
 // For a link pair (i, opp) with e_opp = -e_i, write A = drho - 3/2 rho u.u,
-// sym = A + 9/2 rho (e.u)^2, P = om w sym, Q = om w 3 rho (e.u) + 3 w alpha (e.G):
+// sym = A + 9/2 rho (e.u)^2, P = om w sym, Q = om w 3 rho (e.u) + as (e.D):
 //   d*_i = (1 - om) d_i + P + Q,  d*_opp = (1 - om) d_opp + P - Q.
 template <class T, bool SHIFT, class C, int VX>
 __device__ __forceinline__ void collide(const KeepT<T, C> dk[9][VX], int j, C drho, C gx, C gy, const CoefC<C>& k,
@@ -158,17 +179,18 @@ __device__ __forceinline__ void write_row(char* const (&dbase)[9], const Geom& g
                                           const Pack<T, VX> (&out)[9])
 {
     constexpr unsigned es = sizeof(T);
-    const unsigned ro = (unsigned)y * ((unsigned)g.rs * es);  // row y, column 0
-    const unsigned lo = ro + (unsigned)x * es;
+    const size_t ro = (size_t)y * ((size_t)g.rs * es);  // row y, column 0 (uniform: added to the scalar bases)
+    const unsigned lo = (unsigned)x * es;
     if (nv == VX) {
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
+            char* rb = dbase[i] + ro;
             if constexpr (NTS) {
 #pragma unroll
                 for (int j = 0; j < VX; ++j)
-                    __builtin_nontemporal_store(out[i].v[j], (T*)(dbase[i] + (size_t)(lo + j * es)));
+                    __builtin_nontemporal_store(out[i].v[j], (T*)(rb + (size_t)(lo + j * es)));
             } else {
-                __builtin_memcpy(dbase[i] + (size_t)lo, &out[i], sizeof(out[i]));
+                __builtin_memcpy(rb + (size_t)lo, &out[i], sizeof(out[i]));
             }
         }
     } else {
@@ -176,7 +198,7 @@ __device__ __forceinline__ void write_row(char* const (&dbase)[9], const Geom& g
         for (int i = 0; i < 9; ++i)
 #pragma unroll
             for (int j = 0; j < VX; ++j)
-                if (j < nv) __builtin_memcpy(dbase[i] + (size_t)(lo + j * es), &out[i].v[j], es);
+                if (j < nv) __builtin_memcpy(dbase[i] + ro + (size_t)(lo + j * es), &out[i].v[j], es);
     }
 #pragma unroll
     for (int j = 0; j < VX; ++j) {
@@ -184,12 +206,12 @@ __device__ __forceinline__ void write_row(char* const (&dbase)[9], const Geom& g
         if (j < nv && c >= g.nx - 2) {
 #pragma unroll
             for (int i = 0; i < 9; ++i)  // column c - nx in [-2, -1]
-                __builtin_memcpy(dbase[i] - 2 * es + (size_t)(ro + (unsigned)(c - g.nx + 2) * es), &out[i].v[j], es);
+                __builtin_memcpy(dbase[i] + ro - 2 * es + (size_t)((unsigned)(c - g.nx + 2) * es), &out[i].v[j], es);
         }
         if (j < nv && c <= 1) {
 #pragma unroll
             for (int i = 0; i < 9; ++i)  // column c + nx in [nx, nx + 1]
-                __builtin_memcpy(dbase[i] + (size_t)(ro + (unsigned)(c + g.nx) * es), &out[i].v[j], es);
+                __builtin_memcpy(dbase[i] + ro + (size_t)((unsigned)(c + g.nx) * es), &out[i].v[j], es);
         }
     }
 }
@@ -225,7 +247,7 @@ __device__ __forceinline__ void vstack_tile(const StepTile& a, const void* src, 
     constexpr int R = NW - 2;
     using Rw = Pack<T, WV>;
     const Geom g = a.g;
-    const int wave = (int)(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
     const int y0 = grp * R;
     const int nrows = min(R, g.ny - y0);
     const int y = y0 - 1 + wave;  // in [-1, ny + R - 1]; rows wrap by index
@@ -262,9 +284,9 @@ __device__ __forceinline__ void vstack_tile(const StepTile& a, const void* src, 
         Pack<T, VX> out[9];
 #pragma unroll
         for (int j = 0; j < VX; ++j) {
-            // central differences at time t (Sec. 4)
-            const C gx = C(0.5) * (w[j + 2] - w[j]);
-            const C gy = C(0.5) * (lds[wave + 1][lane * VX + j] - lds[wave - 1][lane * VX + j]);
+            // undivided central differences at time t (Sec. 4)
+            const C gx = w[j + 2] - w[j];
+            const C gy = lds[wave + 1][lane * VX + j] - lds[wave - 1][lane * VX + j];
             C o[9];
             collide<T, SHIFT, C, VX>(d, j, w[j + 1], gx, gy, k, o);
 #pragma unroll

@@ -112,7 +112,7 @@ std::vector<TileCand> pool_candidates(int dtype)
     for (int vx : {1, 2, 4})
         for (int nw : {4, 8, 16})
             for (int nts = 0; nts < 2; ++nts)
-                for (int per : {2, 4, 8}) v.push_back({vx, nw, per, nts ? LBM_TILE_NT_STORE : 0});
+                for (int per : {1, 2, 4}) v.push_back({vx, nw, per, nts ? LBM_TILE_NT_STORE : 0});
     (void)dtype;
     return v;
 }
