@@ -131,10 +131,10 @@ size_t lbm_footprint_bytes(int nx, int ny, int dtype);
  * each owning its own column strip of 64 * vx sites and marching h >= 1
  * rows. Vertical-stack form (LBM_TILE_VSTACK): nw = 4, 8 or 16 waves per
  * workgroup covering one strip and nw - 2 rows (h is ignored). Default:
- * vertical stack with non-temporal stores; vx = 2 and nw = 16 for LBM_F32
- * and LBM_F32S, vx = 2 and nw = 8 for LBM_F64, vx = 4 and nw = 8 for
- * LBM_F16S. Results do not depend on the shape (bitwise). LBM_EINVAL for an
- * unsupported shape. lbm_get_tile: any pointer may be NULL. */
+ * vertical stack with non-temporal stores; vx = 2 and nw = 8 for LBM_F64,
+ * LBM_F32 and LBM_F32S, vx = 4 and nw = 16 for LBM_F16S. Results do not
+ * depend on the shape (bitwise). LBM_EINVAL for an unsupported shape.
+ * lbm_get_tile: any pointer may be NULL. */
 enum lbm_tile_flags {
     LBM_TILE_PREFETCH = 1, /* issue the next row's loads before relaxing the current row */
     LBM_TILE_NT_STORE = 2, /* non-temporal (streaming) stores                              */
@@ -215,16 +215,17 @@ long long lbm_pool_time(const lbm_pool* P, int slot);
  * workgroups of the cooperative launch (0: as many as are co-resident). */
 int lbm_pool_set_mode(lbm_pool* P, int mode, int max_grid);
 /* Vertical-stack tile of the batched kernels: vx in {1, 2, 4}, nw in
- * {4, 8, 16}, flags 0 or LBM_TILE_NT_STORE (default: vx 2, nw 16,
- * non-temporal stores). Does not change results. */
+ * {4, 8, 16}, flags 0 or LBM_TILE_NT_STORE (default: non-temporal stores,
+ * vx 2 and nw 8, or vx 4 and nw 8 for LBM_F16S). Does not change results. */
 int lbm_pool_set_tile(lbm_pool* P, int vx, int nw, int flags);
 int lbm_pool_get_tile(const lbm_pool* P, int* vx, int* nw, int* flags);
 /* Tiles per work item of the batched kernels (1..64, default 1): a
  * workgroup takes that many consecutive tiles of one lattice, paying the
  * lattice lookup once. Does not change results. */
 int lbm_pool_set_items(lbm_pool* P, int tiles_per_item);
-/* Autotuner for the batched kernels (see lbm_autotune): shape, stores and
- * tiles per item, timed on one batched launch over the listed slots; cached
+/* Autotuner for the batched kernels (see lbm_autotune): shape, stores,
+ * tiles per item and the order in which items are dealt to the GPU's
+ * chiplets, timed on one batched launch over the listed slots; cached
  * per architecture, dtype, and the batch's lattice count and total sites
  * rounded up to powers of two. */
 int lbm_pool_autotune(lbm_pool* P, const int* slots, int count, int reps, int use_cache);

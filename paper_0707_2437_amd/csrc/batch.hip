@@ -37,16 +37,16 @@ __device__ __forceinline__ bool batch_item(const BatchLat* __restrict__ lats, co
 }
 
 // One step s of every lattice of the batch; one workgroup per item, items
-// of a lattice contiguous and spread over the XCDs in contiguous runs.
+// of a lattice contiguous, dealt to the XCDs in chunks of ch items
+// (xcd_tile; the grid is a multiple of 8 ch, or of 8 for ch <= 0).
 template <class T, bool SHIFT, int VX, int NW, bool NTS>
 __global__ __launch_bounds__(64 * NW) void batch_step_kernel(const BatchLat* __restrict__ lats,
-                                                             const int* __restrict__ item_lat, int nitems, int s)
+                                                             const int* __restrict__ item_lat, int nitems, int s,
+                                                             int ch)
 {
     using C = typename CompT<T>::type;
     __shared__ C lds[NW][64 * VX];
-    const int nb = gridDim.x;  // a multiple of 8
-    const int b = blockIdx.x;
-    const int i = (b & 7) * (nb >> 3) + (b >> 3);
+    const int i = xcd_tile(blockIdx.x, gridDim.x, ch);
     if (i >= nitems) return;
     batch_item<T, SHIFT, VX, NW, NTS>(lats, item_lat, i, s, lds);
 }
@@ -113,12 +113,13 @@ __global__ __launch_bounds__(64 * NW) void batch_persistent_kernel(const BatchLa
 
 template <class T, bool SHIFT, int VX, int NW, bool NTS>
 static hipError_t launch_batch_t(bool persistent, const BatchLat* lats, const int* item_lat, int nitems,
-                                 int s_or_n, int max_grid, unsigned* bar, hipStream_t st)
+                                 int s_or_n, int max_grid, int ch, unsigned* bar, hipStream_t st)
 {
     if (!persistent) {
-        const int grid = (nitems + 7) / 8 * 8;
+        const int q = ch > 0 ? 8 * ch : 8;
+        const int grid = (nitems + q - 1) / q * q;
         hipLaunchKernelGGL((batch_step_kernel<T, SHIFT, VX, NW, NTS>), dim3(grid), dim3(64 * NW), 0, st, lats,
-                           item_lat, nitems, s_or_n);
+                           item_lat, nitems, s_or_n, ch);
         return hipGetLastError();
     }
     auto kern = batch_persistent_kernel<T, SHIFT, VX, NW, NTS>;
@@ -138,11 +139,13 @@ static hipError_t launch_batch_t(bool persistent, const BatchLat* lats, const in
 
 template <class T, bool SHIFT, int VX>
 static hipError_t launch_batch_nw(int nw, bool nts, bool persistent, const BatchLat* lats, const int* item_lat,
-                                  int nitems, int s_or_n, int max_grid, unsigned* bar, hipStream_t st)
+                                  int nitems, int s_or_n, int max_grid, int ch, unsigned* bar, hipStream_t st)
 {
-#define LBM_B(NWV)                                                                                                   \
-    return nts ? launch_batch_t<T, SHIFT, VX, NWV, true>(persistent, lats, item_lat, nitems, s_or_n, max_grid, bar, st)  \
-               : launch_batch_t<T, SHIFT, VX, NWV, false>(persistent, lats, item_lat, nitems, s_or_n, max_grid, bar, st)
+#define LBM_B(NWV)                                                                                                 \
+    return nts ? launch_batch_t<T, SHIFT, VX, NWV, true>(persistent, lats, item_lat, nitems, s_or_n, max_grid, ch, \
+                                                         bar, st)                                                    \
+               : launch_batch_t<T, SHIFT, VX, NWV, false>(persistent, lats, item_lat, nitems, s_or_n, max_grid, ch, \
+                                                          bar, st)
     switch (nw) {
     case 4: LBM_B(4);
     case 8: LBM_B(8);
@@ -154,26 +157,30 @@ static hipError_t launch_batch_nw(int nw, bool nts, bool persistent, const Batch
 
 template <class T, bool SHIFT>
 static hipError_t launch_batch_vx(int vx, int nw, bool nts, bool persistent, const BatchLat* lats,
-                                  const int* item_lat, int nitems, int s_or_n, int max_grid, unsigned* bar,
+                                  const int* item_lat, int nitems, int s_or_n, int max_grid, int ch, unsigned* bar,
                                   hipStream_t st)
 {
+#define LBM_BN(VXV) launch_batch_nw<T, SHIFT, VXV>(nw, nts, persistent, lats, item_lat, nitems, s_or_n, max_grid, ch, bar, st)
     switch (vx) {
-    case 1: return launch_batch_nw<T, SHIFT, 1>(nw, nts, persistent, lats, item_lat, nitems, s_or_n, max_grid, bar, st);
-    case 2: return launch_batch_nw<T, SHIFT, 2>(nw, nts, persistent, lats, item_lat, nitems, s_or_n, max_grid, bar, st);
-    case 4: return launch_batch_nw<T, SHIFT, 4>(nw, nts, persistent, lats, item_lat, nitems, s_or_n, max_grid, bar, st);
+    case 1: return LBM_BN(1);
+    case 2: return LBM_BN(2);
+    case 4: return LBM_BN(4);
     default: return hipErrorInvalidValue;
     }
+#undef LBM_BN
 }
 
 // Grouped (persistent = false): step s_or_n of the batch, one launch, one
-// workgroup per item.
+// workgroup per item, items dealt to the XCDs in chunks of ch items (<= 0:
+// one contiguous run per XCD).
 // Persistent: s_or_n steps in one cooperative launch, at most max_grid
 // workgroups (<= 0: as many as are co-resident), barrier state in `bar`
 // (3 words, zero-initialised; bar[2] becomes 1 if a barrier timed out).
 hipError_t launch_batch(int dtype, int vx, int nw, bool nts, bool persistent, const BatchLat* lats,
-                        const int* item_lat, int nitems, int s_or_n, int max_grid, unsigned* bar, hipStream_t st)
+                        const int* item_lat, int nitems, int s_or_n, int max_grid, int ch, unsigned* bar,
+                        hipStream_t st)
 {
-#define LBM_BV(T, S) launch_batch_vx<T, S>(vx, nw, nts, persistent, lats, item_lat, nitems, s_or_n, max_grid, bar, st)
+#define LBM_BV(T, S) launch_batch_vx<T, S>(vx, nw, nts, persistent, lats, item_lat, nitems, s_or_n, max_grid, ch, bar, st)
     switch (dtype) {
     case 0: return LBM_BV(double, false);
     case 1: return LBM_BV(float, false);

@@ -24,7 +24,8 @@ hipError_t launch_sample_f(int dtype, const void* s, const Geom& g, int n, const
 hipError_t launch_moments(int dtype, const void* s, const Geom& g, double* rho, double* ux, double* uy,
                           double* partials, double* totals, hipStream_t st);
 hipError_t launch_batch(int dtype, int vx, int nw, bool nts, bool persistent, const BatchLat* lats,
-                        const int* item_lat, int nitems, int s_or_n, int max_grid, unsigned* bar, hipStream_t st);
+                        const int* item_lat, int nitems, int s_or_n, int max_grid, int ch, unsigned* bar,
+                        hipStream_t st);
 
 
 constexpr int kLineBytes = 128;
@@ -127,6 +128,19 @@ inline Coef make_coef(double tau, double c2)
     k.as1f = (float)k.as1;
     k.as2f = (float)k.as2;
     return k;
+}
+
+// Tiles per XCD chunk of the vertical-stack kernels (see xcd_tile): whole
+// row groups of a lattice, at least 16 tiles. LBM_XCD_CHUNK=<n> overrides
+// it for experiments (0: one contiguous run of tiles per XCD).
+inline int xcd_chunk_tiles(int nstrips)
+{
+    if (const char* e = std::getenv("LBM_XCD_CHUNK")) {
+        const int v = std::atoi(e);
+        if (v >= 0 && v <= 4096) return v;
+    }
+    const int groups = (16 + nstrips - 1) / nstrips;
+    return groups * nstrips;
 }
 
 inline int status_of(hipError_t e)

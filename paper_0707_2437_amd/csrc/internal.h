@@ -55,6 +55,7 @@ struct StepTile {
     int nstrips;  // column strip groups (one per workgroup)
     int nchunks;  // row chunks
     int rowband;  // tile order: 1 = strip groups of a chunk first
+    int xcd_chunk;  // vertical-stack tile order over the 8 XCDs (see xcd_tile in step.h)
 };
 
 // One lattice of a batched launch (device array, read by every workgroup).

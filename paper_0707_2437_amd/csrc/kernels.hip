@@ -161,19 +161,17 @@ __global__ __launch_bounds__(64 * NW) void step_kernel(StepTile a, int ntiles)
 
 // Vertical-stack form of the same step (see vstack_tile in step.h). Each
 // workgroup takes one tile; all rows of a group are in flight together and
-// consecutive workgroups (row-band order) cover adjacent strips of the same
-// rows, so the set of rows being streamed at any time stays compact. Each
-// row is read (R + 2) / R times; the extra reads of the boundary rows are
-// served by L2 when the neighbouring group is resident on the same XCD.
+// tiles run over the strips of a row group first, dealt to the XCDs in
+// chunks (xcd_tile), so the set of rows being streamed at any time stays
+// one compact band. Each row is read (R + 2) / R times; the extra reads of
+// the boundary rows are served by the caches.
 template <class T, bool SHIFT, int VX, int NW, bool NTS>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(MinWaves<T>::value, 8))) void step_vstack_kernel(
     StepTile a, int ntiles)
 {
     using C = typename CompT<T>::type;
     __shared__ C lds[NW][64 * VX];
-    const int nb = gridDim.x;  // a multiple of 8
-    const int b = blockIdx.x;
-    const int t = (b & 7) * (nb >> 3) + (b >> 3);  // contiguous run of tiles per XCD
+    const int t = xcd_tile(blockIdx.x, gridDim.x, a.xcd_chunk);
     if (t >= ntiles) return;
     vstack_tile<T, SHIFT, VX, NW, NTS>(a, a.src, a.dst, t % a.nstrips, t / a.nstrips, lds);
 }
@@ -385,7 +383,8 @@ template <class T, bool SHIFT, int VX, int NW>
 static hipError_t launch_vstack_t(int flags, const StepTile& t, hipStream_t st)
 {
     const int ntiles = t.nstrips * t.nchunks;  // strips x row groups of NW - 2 rows
-    const int grid = (ntiles + 7) / 8 * 8;
+    const int q = t.xcd_chunk > 0 ? 8 * t.xcd_chunk : 8;
+    const int grid = (ntiles + q - 1) / q * q;
     if (flags & 2)
         hipLaunchKernelGGL((step_vstack_kernel<T, SHIFT, VX, NW, true>), dim3(grid), dim3(64 * NW), 0, st, t, ntiles);
     else

@@ -31,7 +31,7 @@ struct Slot {
 };
 
 struct GraphEntry {
-    int nsteps_max = 0, nitems = 0, vx = 0, nw = 0, nts = 0;
+    int nsteps_max = 0, nitems = 0, vx = 0, nw = 0, nts = 0, ch = 0;
     const BatchLat* lats = nullptr;
     const int* items = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -52,6 +52,7 @@ struct lbm_pool {
     unsigned* d_bar = nullptr;    // grid-barrier state of the persistent kernel (3 words)
     int cap = 0, item_cap = 0;
     int per_item = 1;             // tiles per work item
+    int xcd_chunk = 8;            // items per XCD chunk of the grouped launches (see xcd_tile)
     std::vector<BatchLat> h_lats;
     std::vector<int> h_items;
     std::vector<GraphEntry> graphs;
@@ -156,13 +157,13 @@ hipError_t run_batch(lbm_pool* P, int nmax)
     if (e != hipSuccess) return e;
     const bool nts = P->nts != 0;
     if (P->mode == LBM_POOL_PERSISTENT)
-        return launch_batch(P->dtype, P->vx, P->nw, nts, true, P->d_lats, P->d_items, nitems, nmax, P->max_grid,
+        return launch_batch(P->dtype, P->vx, P->nw, nts, true, P->d_lats, P->d_items, nitems, nmax, P->max_grid, 0,
                             P->d_bar, P->stream);
     if (P->mode == LBM_POOL_GRAPH) {
         GraphEntry* ge = nullptr;
         for (auto& g : P->graphs)
             if (g.nsteps_max == nmax && g.nitems == nitems && g.vx == P->vx && g.nw == P->nw && g.nts == P->nts &&
-                g.lats == P->d_lats && g.items == P->d_items)
+                g.ch == P->xcd_chunk && g.lats == P->d_lats && g.items == P->d_items)
                 ge = &g;
         if (!ge) {
             // Capture nmax grouped launches once; replays re-read the
@@ -172,8 +173,8 @@ hipError_t run_batch(lbm_pool* P, int nmax)
             if (e != hipSuccess) return e;
             hipError_t le = hipSuccess;
             for (int s = 0; s < nmax && le == hipSuccess; ++s)
-                le = launch_batch(P->dtype, P->vx, P->nw, nts, false, P->d_lats, P->d_items, nitems, s, 0, nullptr,
-                                  P->stream);
+                le = launch_batch(P->dtype, P->vx, P->nw, nts, false, P->d_lats, P->d_items, nitems, s, 0,
+                                  P->xcd_chunk, nullptr, P->stream);
             e = hipStreamEndCapture(P->stream, &graph);
             if (le != hipSuccess) e = le;
             hipGraphExec_t exec = nullptr;
@@ -184,13 +185,15 @@ hipError_t run_batch(lbm_pool* P, int nmax)
                 (void)hipGraphExecDestroy(P->graphs.front().exec);
                 P->graphs.erase(P->graphs.begin());
             }
-            P->graphs.push_back(GraphEntry{nmax, nitems, P->vx, P->nw, P->nts, P->d_lats, P->d_items, exec});
+            P->graphs.push_back(
+                GraphEntry{nmax, nitems, P->vx, P->nw, P->nts, P->xcd_chunk, P->d_lats, P->d_items, exec});
             ge = &P->graphs.back();
         }
         return hipGraphLaunch(ge->exec, P->stream);
     }
     for (int s = 0; s < nmax && e == hipSuccess; ++s)
-        e = launch_batch(P->dtype, P->vx, P->nw, nts, false, P->d_lats, P->d_items, nitems, s, 0, nullptr, P->stream);
+        e = launch_batch(P->dtype, P->vx, P->nw, nts, false, P->d_lats, P->d_items, nitems, s, 0, P->xcd_chunk,
+                         nullptr, P->stream);
     return e;
 }
 
@@ -214,11 +217,15 @@ lbm_pool* lbm_pool_create(size_t budget_bytes, int dtype)
     P->dtype = dtype;
     P->esize = esize_of(dtype);
     P->budget = budget_bytes;
-    switch (dtype) {  // vertical-stack tiles from the single-lattice sweeps
+    switch (dtype) {  // vertical-stack tiles from the batched sweeps
     case LBM_F64: P->vx = 2; P->nw = 8; P->nts = 1; break;
-    case LBM_F32: P->vx = 2; P->nw = 8; P->nts = 0; break;
-    case LBM_F32S: P->vx = 2; P->nw = 16; P->nts = 1; break;
-    default: P->vx = 4; P->nw = 8; P->nts = 0; break;
+    case LBM_F32: P->vx = 2; P->nw = 8; P->nts = 1; break;
+    case LBM_F32S: P->vx = 2; P->nw = 8; P->nts = 1; break;
+    default: P->vx = 4; P->nw = 8; P->nts = 1; break;
+    }
+    if (const char* ev = std::getenv("LBM_XCD_CHUNK")) {  // experiments: items per XCD chunk
+        const int v = std::atoi(ev);
+        if (v >= 0 && v <= 4096) P->xcd_chunk = v;
     }
     hipError_t e = hipGetDevice(&P->device);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&P->own, hipStreamNonBlocking);
@@ -467,7 +474,11 @@ int lbm_pool_autotune(lbm_pool* P, const int* slots, int count, int reps, int us
     char key[160];
     std::snprintf(key, sizeof(key), "%s|pool|%d|n2^%d|s2^%d", device_arch().c_str(), P->dtype, lc, ls);
     TileCand c{};
-    if (use_cache && tune_cache_get(key, &c)) return lbm_pool_set_tile(P, c.vx, c.nw, c.flags);
+    if (use_cache && tune_cache_get(key, &c)) {
+        P->per_item = c.h;
+        P->xcd_chunk = c.ch;
+        return lbm_pool_set_tile(P, c.vx, c.nw, c.flags);
+    }
     const std::vector<TileCand> cands = pool_candidates(P->dtype);
     // one batched launch at step 0 of a 1-step call: reads each slot's
     // current buffer and writes the other, without advancing any slot
@@ -498,7 +509,7 @@ int lbm_pool_autotune(lbm_pool* P, const int* slots, int count, int reps, int us
                                 P->stream);
         if (le == hipSuccess)
             le = launch_batch(P->dtype, k.vx, k.nw, (k.flags & LBM_TILE_NT_STORE) != 0, false, P->d_lats,
-                              P->d_items, nitems, 0, 0, nullptr, P->stream);
+                              P->d_items, nitems, 0, 0, k.ch, nullptr, P->stream);
         return le;
     };
     float us = 0;
@@ -506,6 +517,7 @@ int lbm_pool_autotune(lbm_pool* P, const int* slots, int count, int reps, int us
     if (best < 0) return LBM_EDEVICE;
     tune_cache_put(key, cands[best], us);
     P->per_item = cands[best].h;
+    P->xcd_chunk = cands[best].ch;
     return lbm_pool_set_tile(P, cands[best].vx, cands[best].nw, cands[best].flags);
 }
 

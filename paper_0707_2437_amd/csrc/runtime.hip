@@ -43,9 +43,9 @@ TileDefault default_tile(int dtype)
 {
     switch (dtype) {
     case LBM_F64: return {2, 8, 8, LBM_TILE_VSTACK | LBM_TILE_NT_STORE};
-    case LBM_F32: return {2, 16, 8, LBM_TILE_VSTACK | LBM_TILE_NT_STORE};
-    case LBM_F32S: return {2, 16, 8, LBM_TILE_VSTACK | LBM_TILE_NT_STORE};
-    default: return {4, 8, 8, LBM_TILE_VSTACK | LBM_TILE_NT_STORE};
+    case LBM_F32: return {2, 8, 8, LBM_TILE_VSTACK | LBM_TILE_NT_STORE};
+    case LBM_F32S: return {2, 8, 8, LBM_TILE_VSTACK | LBM_TILE_NT_STORE};
+    default: return {4, 16, 8, LBM_TILE_VSTACK | LBM_TILE_NT_STORE};
     }
 }
 
@@ -71,11 +71,13 @@ StepTile make_tile(const lbm_lattice* L)
     t.g = L->g;
     t.c = L->coef;
     t.h = L->h;
+    t.xcd_chunk = 0;
     if (L->kflags & LBM_TILE_VSTACK) {
         // one strip of 64 * vx columns and nw - 2 rows per workgroup
         const int W = 64 * L->vx, R = L->nw - 2;
         t.nstrips = (L->nx + W - 1) / W;
         t.nchunks = (L->ny + R - 1) / R;
+        t.xcd_chunk = xcd_chunk_tiles(t.nstrips);
     } else {
         const int W = 64 * L->nw * L->vx;  // columns of the NW strips of one workgroup
         t.nstrips = (L->nx + W - 1) / W;

@@ -63,6 +63,13 @@ template <class T, int VX> __device__ __forceinline__ Pack<T, VX> ld_vec(const c
     return r;
 }
 
+// Fused multiply-add in the compute precision (the only FMAs the build emits).
+__device__ __forceinline__ float fmac(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmac(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+template <class C> __device__ __forceinline__ C recip(C r) { return C(1) / r; }
+template <> __device__ __forceinline__ float recip<float>(float r) { return __builtin_amdgcn_rcpf(r); }
+
 // Registers hold the populations of two rows. FP32/FP64 storage is kept
 // as d_i = f_i - w_i in compute precision; FP16 storage is kept raw (half
 // the registers) and converted where it is used.
@@ -86,8 +93,10 @@ template <class T, bool SHIFT, class C> __device__ __forceinline__ C d_of(KeepT<
 // e_4 (0,-1); e_5 (1,1); e_6 (-1,1); e_7 (-1,-1); e_8 (1,-1).
 // pb[i] points at column -2 of row 0 of plane i; the byte offset of column
 // x - 1 - e_ix in row q is (q * rs + x + 1 - e_ix) * sizeof(T) >= 0.
-template <class T, int NV>
-__device__ __forceinline__ void gather_raw(const char* const (&pb)[9], const Geom& g, int r, int x, Pack<T, NV> (&v)[9])
+// LT / NL: the register type and count the windows are loaded as (the FP16
+// kernels load their windows as packed 32-bit words, NL = ceil(NV / 2)).
+template <class T, int NV, class LT = T, int NL = NV>
+__device__ __forceinline__ void gather_raw(const char* const (&pb)[9], const Geom& g, int r, int x, Pack<LT, NL> (&v)[9])
 {
     constexpr unsigned es = sizeof(T);
     // r is uniform over the wave in every caller: the row offsets are
@@ -98,22 +107,48 @@ __device__ __forceinline__ void gather_raw(const char* const (&pb)[9], const Geo
     const size_t o0 = (size_t)wrapy(r, g.ny) * rs;      // source row r     (e_iy =  0)
     const size_t op = (size_t)wrapy(r + 1, g.ny) * rs;  // source row r + 1 (e_iy = -1)
     const unsigned xm = (unsigned)x * es, x0 = xm + es, xp = xm + 2 * es;  // window starts for e_ix = +1, 0, -1
-    v[0] = ld_vec<T, NV>(pb[0] + o0, x0);
-    v[1] = ld_vec<T, NV>(pb[1] + o0, xm);
-    v[2] = ld_vec<T, NV>(pb[2] + om, x0);
-    v[3] = ld_vec<T, NV>(pb[3] + o0, xp);
-    v[4] = ld_vec<T, NV>(pb[4] + op, x0);
-    v[5] = ld_vec<T, NV>(pb[5] + om, xm);
-    v[6] = ld_vec<T, NV>(pb[6] + om, xp);
-    v[7] = ld_vec<T, NV>(pb[7] + op, xp);
-    v[8] = ld_vec<T, NV>(pb[8] + op, xm);
+    v[0] = ld_vec<LT, NL>(pb[0] + o0, x0);
+    v[1] = ld_vec<LT, NL>(pb[1] + o0, xm);
+    v[2] = ld_vec<LT, NL>(pb[2] + om, x0);
+    v[3] = ld_vec<LT, NL>(pb[3] + o0, xp);
+    v[4] = ld_vec<LT, NL>(pb[4] + op, x0);
+    v[5] = ld_vec<LT, NL>(pb[5] + om, xm);
+    v[6] = ld_vec<LT, NL>(pb[6] + om, xp);
+    v[7] = ld_vec<LT, NL>(pb[7] + op, xp);
+    v[8] = ld_vec<LT, NL>(pb[8] + op, xm);
+}
+
+// A column of nine populations d_i (one site) as seen by the arithmetic
+// below. ColF holds them in compute precision; ColH (FP16 storage) reads
+// them from packed halves with mixed-precision FMAs, which convert an FP16
+// operand exactly, so both give the same bits. Operations: add(a, b) =
+// d_a + d_b, sub(a, b) = d_a - d_b, plus(a, s) = s + d_a, fma(m, a, c) =
+// m d_a + c, each rounded once.
+template <class C> struct ColF {
+    C d[9];
+    __device__ __forceinline__ C add(int a, int b) const { return d[a] + d[b]; }
+    __device__ __forceinline__ C sub(int a, int b) const { return d[a] - d[b]; }
+    __device__ __forceinline__ C plus(int a, C s) const { return s + d[a]; }
+    __device__ __forceinline__ C fma(C m, int a, C c) const { return fmac(m, d[a], c); }
+};
+
+template <class T, bool SHIFT, class C, int VX> __device__ __forceinline__ ColF<C> col_of(const KeepT<T, C> d[9][VX], int j)
+{
+    ColF<C> v;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) v.d[i] = d_of<T, SHIFT, C>(d[i][j], i);
+    return v;
 }
 
 // delta rho = sum_i d_i (Eq. 3), one fixed order for every code path.
+template <class V> __device__ __forceinline__ auto drho_col(const V& v)
+{
+    return v.plus(8, (v.add(0, 1) + v.add(2, 3)) + (v.add(4, 5) + v.add(6, 7)));
+}
+
 template <class T, bool SHIFT, class C, int VX> __device__ __forceinline__ C drho_of(const KeepT<T, C> d[9][VX], int j)
 {
-    auto D = [&](int i) { return d_of<T, SHIFT, C>(d[i][j], i); };
-    return (((D(0) + D(1)) + (D(2) + D(3))) + ((D(4) + D(5)) + (D(6) + D(7)))) + D(8);
+    return drho_col(col_of<T, SHIFT, C, VX>(d, j));
 }
 
 template <class C> struct CoefC {
@@ -126,13 +161,6 @@ template <class C> __device__ __forceinline__ CoefC<C> coef_c(const Coef& k)
     else return CoefC<C>{k.om1, k.wo0, k.wo1, k.wo2, k.as1, k.as2};
 }
 
-// Fused multiply-add in the compute precision (the only FMAs the build emits).
-__device__ __forceinline__ float fmac(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-__device__ __forceinline__ double fmac(double a, double b, double c) { return __builtin_fma(a, b, c); }
-
-template <class C> __device__ __forceinline__ C recip(C r) { return C(1) / r; }
-template <> __device__ __forceinline__ float recip<float>(float r) { return __builtin_amdgcn_rcpf(r); }
-
 // Eq. 5 right-hand side in delta form for one site.
 //   rho = 1 + drho, u = j / rho (Eq. 3)
 //   feq_i - w_i = w_i [drho + rho (3 e.u + 9/2 (e.u)^2 - 3/2 u.u)]      (Eq. 2)
@@ -143,32 +171,105 @@ template <> __device__ __forceinline__ float recip<float>(float r) { return __bu
 // For a link pair (i, opp) with e_opp = -e_i, write A = drho - 3/2 rho u.u,
 // sym = A + 9/2 rho (e.u)^2, P = om w sym, Q = om w 3 rho (e.u) + as (e.D):
 //   d*_i = (1 - om) d_i + P + Q,  d*_opp = (1 - om) d_opp + P - Q.
-template <class T, bool SHIFT, class C, int VX>
-__device__ __forceinline__ void collide(const KeepT<T, C> dk[9][VX], int j, C drho, C gx, C gy, const CoefC<C>& k,
-                                        C o[9])
+template <class V, class C>
+__device__ __forceinline__ void collide_col(const V& v, C drho, C gx, C gy, const CoefC<C>& k, C o[9])
 {
-    C d[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) d[i] = d_of<T, SHIFT, C>(dk[i][j], i);
-    const C jx = ((d[1] - d[3]) + (d[5] - d[6])) + (d[8] - d[7]);
-    const C jy = ((d[2] - d[4]) + (d[5] - d[8])) + (d[6] - d[7]);
+    const C jx = (v.sub(1, 3) + v.sub(5, 6)) + v.sub(8, 7);
+    const C jy = (v.sub(2, 4) + v.sub(5, 8)) + v.sub(6, 7);
     const C rho = C(1) + drho;
     const C ir = recip<C>(rho);
     const C ux = jx * ir, uy = jy * ir;
     const C usq = fmac(ux, ux, uy * uy);
     const C A = fmac(C(-1.5) * rho, usq, drho);
     const C r45 = C(4.5) * rho, r3 = C(3) * rho;
-    o[0] = fmac(k.om1, d[0], k.wo0 * A);
+    o[0] = v.fma(k.om1, 0, k.wo0 * A);
     auto pair = [&](int i, int io, C eu, C eg, C wo, C as) {
         const C P = wo * fmac(r45, eu * eu, A);
         const C Q = fmac(as, eg, wo * (r3 * eu));
-        o[i] = fmac(k.om1, d[i], P + Q);
-        o[io] = fmac(k.om1, d[io], P - Q);
+        o[i] = v.fma(k.om1, i, P + Q);
+        o[io] = v.fma(k.om1, io, P - Q);
     };
     pair(1, 3, ux, gx, k.wo1, k.as1);
     pair(2, 4, uy, gy, k.wo1, k.as1);
     pair(5, 7, ux + uy, gx + gy, k.wo2, k.as2);
     pair(6, 8, uy - ux, gy - gx, k.wo2, k.as2);
+}
+
+template <class T, bool SHIFT, class C, int VX>
+__device__ __forceinline__ void collide(const KeepT<T, C> dk[9][VX], int j, C drho, C gx, C gy, const CoefC<C>& k,
+                                        C o[9])
+{
+    collide_col(col_of<T, SHIFT, C, VX>(dk, j), drho, gx, gy, k, o);
+}
+
+// ---------------------------------------------------------------------------
+// FP16 storage (shifted form): the nine populations of a window column sit
+// in the same half (H) of nine packed registers; v_fma_mix_f32 reads that
+// half as an FP16 operand (exactly converted) next to FP32 operands, so the
+// FP32 arithmetic needs no separate conversion instructions.
+template <int H> struct ColH {
+    unsigned w[9];
+    __device__ __forceinline__ float add(int a, int b) const
+    {
+        float r;
+        if constexpr (H == 0) asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel_hi:[1,0,1]" : "=v"(r) : "v"(w[a]), "v"(w[b]));
+        else asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[1,0,1] op_sel_hi:[1,0,1]" : "=v"(r) : "v"(w[a]), "v"(w[b]));
+        return r;
+    }
+    __device__ __forceinline__ float sub(int a, int b) const
+    {
+        float r;
+        if constexpr (H == 0)
+            asm("v_fma_mix_f32 %0, %1, 1.0, -%2 op_sel_hi:[1,0,1]" : "=v"(r) : "v"(w[a]), "v"(w[b]));
+        else
+            asm("v_fma_mix_f32 %0, %1, 1.0, -%2 op_sel:[1,0,1] op_sel_hi:[1,0,1]" : "=v"(r) : "v"(w[a]), "v"(w[b]));
+        return r;
+    }
+    __device__ __forceinline__ float plus(int a, float s) const
+    {
+        float r;
+        if constexpr (H == 0) asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(r) : "v"(w[a]), "v"(s));
+        else asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(r) : "v"(w[a]), "v"(s));
+        return r;
+    }
+    __device__ __forceinline__ float fma(float m, int a, float c) const
+    {
+        float r;
+        if constexpr (H == 0) asm("v_fma_mix_f32 %0, %1, %2, %3 op_sel_hi:[0,1,0]" : "=v"(r) : "v"(m), "v"(w[a]), "v"(c));
+        else asm("v_fma_mix_f32 %0, %1, %2, %3 op_sel:[0,1,0] op_sel_hi:[0,1,0]" : "=v"(r) : "v"(m), "v"(w[a]), "v"(c));
+        return r;
+    }
+};
+
+// Window column J of nine FP16 windows held as packed words.
+template <int J, int NWD> __device__ __forceinline__ ColH<J & 1> col_h(const unsigned (&u)[9][NWD])
+{
+    ColH<J & 1> v;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) v.w[i] = u[i][J >> 1];
+    return v;
+}
+
+// Two FP32 values rounded to FP16 (round to nearest even), packed low/high.
+__device__ __forceinline__ unsigned pack_h2(float lo, float hi)
+{
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+    f2 v = {lo, hi};
+    asm("" : "+v"(v));  // keep the conversion separate from the FMAs that produced v
+    const h2 r = __builtin_convertvector(v, h2);
+    unsigned u;
+    __builtin_memcpy(&u, &r, sizeof(u));
+    return u;
+}
+
+// Compile-time loop: f(std::integral_constant<int, I>) for I = B .. E - 1.
+template <int B, int E, class F> __device__ __forceinline__ void static_for(F&& f)
+{
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
 }
 
 // Write row y of the lattice: VX relaxed sites per lane (nv of them valid)
@@ -216,6 +317,21 @@ __device__ __forceinline__ void write_row(char* const (&dbase)[9], const Geom& g
     }
 }
 
+// Tile of workgroup b in a grid of nb workgroups. Consecutive workgroups are
+// dispatched round-robin to the 8 XCDs (b & 7); j = b >> 3 counts one XCD's
+// workgroups in dispatch order. With ch > 0 the tiles are dealt to the XCDs
+// in chunks of ch consecutive tiles (about one row group each): the 8 XCDs
+// work on 8 adjacent chunks at a time, so the rows being streamed form one
+// compact band (DRAM page locality); the rows shared by adjacent chunks are
+// re-read through the shared last-level cache. The grid is a multiple of
+// 8 ch. With ch <= 0 each XCD takes one contiguous run of nb / 8 tiles.
+__device__ __forceinline__ int xcd_tile(int b, int nb, int ch)
+{
+    if (ch <= 0) return (b & 7) * (nb >> 3) + (b >> 3);
+    const int j = b >> 3;
+    return (j / ch) * (8 * ch) + (b & 7) * ch + (j % ch);
+}
+
 // Per-plane base pointers: source at column -2, destination at column 0.
 template <class T>
 __device__ __forceinline__ void plane_bases(const void* src, void* dst, const Geom& g, const char* (&sb)[9],
@@ -237,10 +353,87 @@ __device__ __forceinline__ void plane_bases(const void* src, void* dst, const Ge
 // `lds`; after one barrier the interior waves read the densities of the
 // rows above and below, relax and write. The caller must place a barrier
 // between two calls that reuse `lds`.
+// vstack_tile for FP16 storage (shifted form): the same tile, rows,
+// summation orders and roundings, with the populations kept as the packed
+// halves they were loaded as (see ColH) and the results rounded to FP16 two
+// at a time.
+template <int VX, int NW, bool NTS>
+__device__ __forceinline__ void vstack_tile_h(const StepTile& a, const void* src, void* dst, int strip, int grp,
+                                              float (&lds)[NW][64 * VX])
+{
+    using T = _Float16;
+    constexpr int WV = VX + 2;
+    constexpr int NWD = (WV + 1) / 2;  // packed words per window
+    constexpr int R = NW - 2;
+    const Geom g = a.g;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
+    const int y0 = grp * R;
+    const int nrows = min(R, g.ny - y0);
+    const int y = y0 - 1 + wave;
+    const int x = strip * (64 * VX) + lane * VX;
+    const int nv = min(VX, g.nx - x);
+    const bool active = nv > 0 && wave <= nrows + 1;
+
+    const char* sb[9];
+    char* dbase[9];
+    plane_bases<T>(src, dst, g, sb, dbase);
+
+    unsigned u[9][NWD];
+    float w[WV];
+    if (active) {
+        // An odd-length window (VX = 1) loads one half past its end: column
+        // x + 2 <= nx + 1, a ghost column, inside the row.
+        Pack<unsigned, NWD> raw[9];
+        gather_raw<T, WV, unsigned, NWD>(sb, g, y, x, raw);
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+#pragma unroll
+            for (int q = 0; q < NWD; ++q) u[i][q] = raw[i].v[q];
+        static_for<0, WV>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            w[j] = drho_col(col_h<j>(u));
+        });
+#pragma unroll
+        for (int j = 0; j < VX; ++j) lds[wave][lane * VX + j] = w[j + 1];
+    }
+    __syncthreads();
+    if (active && wave >= 1 && wave <= nrows) {
+        const CoefC<float> k = coef_c<float>(a.c);
+        float o[VX][9];
+        static_for<0, VX>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            // undivided central differences at time t (Sec. 4)
+            const float gx = w[j + 2] - w[j];
+            const float gy = lds[wave + 1][lane * VX + j] - lds[wave - 1][lane * VX + j];
+            collide_col(col_h<j + 1>(u), w[j + 1], gx, gy, k, o[j]);
+        });
+        Pack<T, VX> out[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            if constexpr (VX == 1) {
+                float v = o[0][i];
+                asm("" : "+v"(v));
+                out[i].v[0] = (T)v;
+            } else {
+                unsigned pk[VX / 2];
+#pragma unroll
+                for (int j = 0; j < VX; j += 2) pk[j / 2] = pack_h2(o[j][i], o[j + 1][i]);
+                __builtin_memcpy(&out[i], pk, sizeof(out[i]));
+            }
+        }
+        write_row<T, VX, NTS>(dbase, g, y, x, nv, out);
+    }
+}
+
 template <class T, bool SHIFT, int VX, int NW, bool NTS>
 __device__ __forceinline__ void vstack_tile(const StepTile& a, const void* src, void* dst, int strip, int grp,
                                             typename CompT<T>::type (&lds)[NW][64 * VX])
 {
+    if constexpr (std::is_same<T, _Float16>::value) {
+        static_assert(SHIFT, "FP16 storage is the shifted form");
+        vstack_tile_h<VX, NW, NTS>(a, src, dst, strip, grp, lds);
+        return;
+    } else {
     using C = typename CompT<T>::type;
     using K = KeepT<T, C>;
     constexpr int WV = VX + 2;
@@ -293,6 +486,7 @@ __device__ __forceinline__ void vstack_tile(const StepTile& a, const void* src, 
             for (int i = 0; i < 9; ++i) out[i].v[j] = from_d<T, SHIFT, C>(o[i], i);
         }
         write_row<T, VX, NTS>(dbase, g, y, x, nv, out);
+    }
     }
 }
 

@@ -9,8 +9,11 @@
 
 namespace lbm {
 
+// A candidate shape: vx, nw, flags as in lbm_set_tile; h = rows per
+// workgroup (march form) or tiles per work item (batched kernels); ch =
+// items per XCD chunk of the batched kernels (0 for single lattices).
 struct TileCand {
-    int vx, nw, h, flags;
+    int vx, nw, h, flags, ch;
 };
 
 std::string device_arch();

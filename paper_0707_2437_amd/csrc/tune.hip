@@ -42,8 +42,10 @@ void load_cache_locked()
         char key[256];
         TileCand c{};
         float us = 0;
-        if (std::sscanf(line, "{\"key\": \"%255[^\"]\", \"vx\": %d, \"nw\": %d, \"h\": %d, \"flags\": %d, \"us\": %f}",
-                        key, &c.vx, &c.nw, &c.h, &c.flags, &us) == 6)
+        if (std::sscanf(line,
+                        "{\"key\": \"%255[^\"]\", \"vx\": %d, \"nw\": %d, \"h\": %d, \"flags\": %d, \"ch\": %d, "
+                        "\"us\": %f}",
+                        key, &c.vx, &c.nw, &c.h, &c.flags, &c.ch, &us) == 7)
             g_cache[key] = c;
     }
     std::fclose(f);
@@ -78,8 +80,10 @@ void tune_cache_put(const std::string& key, const TileCand& c, float us)
     g_cache[key] = c;
     if (const char* p = cache_path()) {
         if (FILE* f = std::fopen(p, "a")) {
-            std::fprintf(f, "{\"key\": \"%s\", \"vx\": %d, \"nw\": %d, \"h\": %d, \"flags\": %d, \"us\": %.3f}\n",
-                         key.c_str(), c.vx, c.nw, c.h, c.flags, us);
+            std::fprintf(f,
+                         "{\"key\": \"%s\", \"vx\": %d, \"nw\": %d, \"h\": %d, \"flags\": %d, \"ch\": %d, "
+                         "\"us\": %.3f}\n",
+                         key.c_str(), c.vx, c.nw, c.h, c.flags, c.ch, us);
             std::fclose(f);
         }
     }
@@ -93,26 +97,27 @@ std::vector<TileCand> lattice_candidates(int dtype)
     for (int vx : vxs)
         for (int nw : nws)
             for (int nts = 0; nts < 2; ++nts)
-                v.push_back({vx, nw, 8, LBM_TILE_VSTACK | (nts ? LBM_TILE_NT_STORE : 0)});
+                v.push_back({vx, nw, 8, LBM_TILE_VSTACK | (nts ? LBM_TILE_NT_STORE : 0), 0});
     // march form: prefetched, row-band order
     for (int vx : {1, 2})
         for (int h : {4, 8})
             for (int f : {LBM_TILE_PREFETCH2 | LBM_TILE_NT_STORE | LBM_TILE_ROWBAND,
                           LBM_TILE_PREFETCH | LBM_TILE_NT_STORE | LBM_TILE_ROWBAND})
-                v.push_back({vx, 4, h, f});
+                v.push_back({vx, 4, h, f, 0});
     (void)dtype;
     return v;
 }
 
-// Batched kernels: vertical-stack shape, non-temporal stores, and the tiles
-// per work item (carried in the h field).
+// Batched kernels: vertical-stack shape, non-temporal stores, the tiles per
+// work item (carried in the h field) and the items per XCD chunk.
 std::vector<TileCand> pool_candidates(int dtype)
 {
     std::vector<TileCand> v;
     for (int vx : {1, 2, 4})
         for (int nw : {4, 8, 16})
             for (int nts = 0; nts < 2; ++nts)
-                for (int per : {1, 2, 4}) v.push_back({vx, nw, per, nts ? LBM_TILE_NT_STORE : 0});
+                for (int per : {1, 2})
+                    for (int ch : {8, 32}) v.push_back({vx, nw, per, nts ? LBM_TILE_NT_STORE : 0, ch});
     (void)dtype;
     return v;
 }
