@@ -3,6 +3,10 @@
     # per-kernel time summary from `rocprofv3 --kernel-trace --stats -f csv`
     python -m paper_0707_2437_amd.profiling stats <..._kernel_stats.csv>
 
+    # the same from the dispatch trace, split by launch grid (one kernel
+    # stepping lattices of different sizes shows one line per grid)
+    python -m paper_0707_2437_amd.profiling trace <..._kernel_trace.csv> [--kernel REGEX]
+
     # HBM traffic of one kernel from two `--pmc FETCH_SIZE` / `--pmc WRITE_SIZE`
     # runs, scaled by the same counters on a device copy of known size
     python -m paper_0707_2437_amd.profiling traffic --kernel REGEX \\
@@ -40,6 +44,26 @@ def stats_summary(path, top=12):
     for r in rows[:top]:
         lines.append(f"{r['Name'][:90]:<90} {int(r['Calls']):>6} {float(r['AverageNs']) / 1e3:>10.2f} "
                      f"{float(r['MinNs']) / 1e3:>10.2f} {float(r['MaxNs']) / 1e3:>10.2f} {float(r['Percentage']):>7.2f}")
+    return "\n".join(lines)
+
+
+def trace_summary(path, kernel_regex=None, top=20):
+    """Dispatches grouped by (kernel, grid size): count and duration stats."""
+    rx = re.compile(kernel_regex) if kernel_regex else None
+    groups = {}
+    for r in csv.DictReader(open(path)):
+        name = r["Kernel_Name"]
+        if rx and not rx.search(name):
+            continue
+        grid = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+        wg = int(r["Workgroup_Size_X"]) * int(r["Workgroup_Size_Y"]) * int(r["Workgroup_Size_Z"])
+        dur = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        groups.setdefault((name, grid // max(wg, 1)), []).append(dur)
+    tot = sum(sum(v) for v in groups.values()) or 1.0
+    lines = [f"{'kernel':<80} {'workgroups':>10} {'calls':>6} {'avg_us':>10} {'min_us':>10} {'max_us':>10} {'share%':>7}"]
+    for (name, nwg), v in sorted(groups.items(), key=lambda kv: -sum(kv[1]))[:top]:
+        lines.append(f"{name[:80]:<80} {nwg:>10} {len(v):>6} {statistics.fmean(v):>10.2f} {min(v):>10.2f} "
+                     f"{max(v):>10.2f} {100 * sum(v) / tot:>7.2f}")
     return "\n".join(lines)
 
 
@@ -83,6 +107,9 @@ def main(argv=None):
     sub = p.add_subparsers(dest="cmd", required=True)
     s = sub.add_parser("stats")
     s.add_argument("csv")
+    tr = sub.add_parser("trace")
+    tr.add_argument("csv")
+    tr.add_argument("--kernel", default=None)
     t = sub.add_parser("traffic")
     t.add_argument("--kernel", required=True, help="regex selecting the kernel's dispatches")
     t.add_argument("--name", required=True, help="kernel name as the benchmark reports it")
@@ -93,6 +120,8 @@ def main(argv=None):
     a = p.parse_args(argv)
     if a.cmd == "stats":
         print(stats_summary(a.csv))
+    elif a.cmd == "trace":
+        print(trace_summary(a.csv, a.kernel))
     else:
         rec = traffic_record(a.kernel, a.fetch, a.write, a.copy_fetch, a.copy_write, a.copy_bytes,
                              a.algorithmic_bytes)
