@@ -73,10 +73,11 @@ inline bool args_ok(int nx, int ny, double tau, double c2, int dtype)
     return offsets_fit(nx, ny, dtype, choose_interleaved(nx, ny, dtype));
 }
 
-// Row pitch leaves one line before column 0 (ghost columns -2, -1 at its
-// end), the ghost columns nx, nx+1, and room for the widest window past the
-// last column. Plane-major layout: planes rounded to 4 KiB plus a 1 KiB
-// skew; row-interleaved layout: rows of 9 * pitch.
+// Row pitch leaves one line before column 0 and room past column nx - 1 for
+// the widest window (the gather reads up to two columns before the row and
+// up to kMaxVX + 2 after it; those padding elements are never used).
+// Plane-major layout: planes rounded to 4 KiB plus a 1 KiB skew;
+// row-interleaved layout: rows of 9 * pitch.
 inline Geom make_geom(int nx, int ny, int esize, bool interleaved)
 {
     Geom g;

@@ -7,11 +7,11 @@
 // writes S'_i(x) aligned into the other buffer (A/B).
 //
 // Layout: element (x, y) of plane i sits at
-//   i * ps + y * rs + off + x,   x in [-2, nx + 1]
-// Columns -2, -1 are ghost copies of columns nx-2, nx-1 and columns nx,
-// nx+1 are copies of 0, 1 (written by the step that writes those columns),
-// so the +-1-shifted windows of the gather need no wrap test. `off` is one
-// 128-byte line, so x = 0 is line-aligned. Two layouts are supported:
+//   i * ps + y * rs + off + x,   x in [0, nx)
+// `off` is one 128-byte line, so x = 0 is line-aligned; the row is padded
+// on both sides (the +-1-shifted windows of the gather read a little past
+// the row ends and replace those elements by the periodic image, see
+// gather_raw). Two layouts are supported:
 // plane-major (ps = plane size, rs = pitch) and row-interleaved (ps = pitch,
 // rs = 9 * pitch: the nine plane rows of a lattice row are contiguous).
 // Rows wrap in y by index.

@@ -228,8 +228,9 @@ __device__ __forceinline__ RowIdx row_idx(const Geom& g, int w)
     return r;
 }
 
-// S_i(x, y) = feq_i(rho, u at (x + e_i, y + e_i)) for x in [-2, nx + 1]:
-// the pulled gather of the first step then sees f_i(x, 0) = feq_i(x).
+// S_i(x, y) = feq_i(rho, u at (x + e_i, y + e_i)) for x in [-2, nx + 1] (the
+// ghost columns included): the pulled gather of the first step then sees
+// f_i(x, 0) = feq_i(x).
 template <class T, bool SHIFT>
 __global__ void init_kernel(T* __restrict__ s, Geom g, const double* __restrict__ rho, const double* __restrict__ ux,
                             const double* __restrict__ uy)
@@ -263,9 +264,8 @@ template <class T, bool SHIFT> __global__ void get_f_kernel(const T* __restrict_
     const RowIdx ri = row_idx(g, g.nx);
     if (!ri.ok) return;
     const int i = ri.i, y = ri.y, xx = ri.col;
-    const int sy = wrapy(y - kEY[i], g.ny);
-    f[((long long)i * g.ny + y) * g.nx + xx] =
-        load_f64<T, SHIFT>(s[i * g.ps + (long long)sy * g.rs + g.off + xx - kEX[i]], i);
+    const int sy = wrapy(y - kEY[i], g.ny), sx = wrapx2(xx - kEX[i], g.nx);
+    f[((long long)i * g.ny + y) * g.nx + xx] = load_f64<T, SHIFT>(s[i * g.ps + (long long)sy * g.rs + g.off + sx], i);
 }
 
 // f_i at n listed sites into out[n][9].
@@ -277,8 +277,8 @@ __global__ void sample_f_kernel(const T* __restrict__ s, Geom g, int n, const in
     if (q >= 9 * n) return;
     const int k = q / 9, i = q - 9 * k;
     const int x = xy[2 * k], y = xy[2 * k + 1];
-    const int sy = wrapy(y - kEY[i], g.ny);
-    out[q] = load_f64<T, SHIFT>(s[i * g.ps + (long long)sy * g.rs + g.off + x - kEX[i]], i);
+    const int sy = wrapy(y - kEY[i], g.ny), sx = wrapx2(x - kEX[i], g.nx);
+    out[q] = load_f64<T, SHIFT>(s[i * g.ps + (long long)sy * g.rs + g.off + sx], i);
 }
 
 // Moments (Eq. 3) of f(x, t) in FP64, optional fields, and per-block
@@ -302,8 +302,8 @@ __global__ __launch_bounds__(kRedThreads) void moments_kernel(const T* __restric
         // momentum is sum_i g_i e_i as well, and rho = 1 + sum_i g_i.
         double vsum = 0.0, sx = 0.0, sy2 = 0.0;
         for (int i = 0; i < 9; ++i) {
-            const int sy = wrapy(y - kEY[i], g.ny);
-            const double v = (double)s[i * g.ps + (long long)sy * g.rs + g.off + x - kEX[i]];
+            const int cy = wrapy(y - kEY[i], g.ny), cx = wrapx2(x - kEX[i], g.nx);
+            const double v = (double)s[i * g.ps + (long long)cy * g.rs + g.off + cx];
             vsum += v;
             sx += v * kEX[i];
             sy2 += v * kEY[i];

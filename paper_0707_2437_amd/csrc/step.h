@@ -20,6 +20,17 @@ template <> struct CompT<double> { using type = double; };
 template <class T> struct MinWaves { static constexpr int value = 1; };
 template <> struct MinWaves<_Float16> { static constexpr int value = 7; };
 
+// Periodicity in x. FP16 storage keeps ghost copies of the two edge columns
+// on each side of every row (columns -2, -1 hold nx-2, nx-1 and nx, nx+1
+// hold 0, 1), written by the step that writes those columns, so its windows
+// need no wrap. The other storage types write no copies (they would be
+// scattered partial-line stores); their loads take the wrapped elements from
+// the periodic image instead (patch_edges), in a separate copy of the code
+// run only by the strips at the lattice's edges. For FP16 the patch costs
+// more than the copies (its 2-byte elements share registers).
+template <class T> struct GhostCols { static constexpr bool value = false; };
+template <> struct GhostCols<_Float16> { static constexpr bool value = true; };
+
 // Lattice weights (Sec. 2) in compute precision.
 template <class C> __device__ __forceinline__ C wt(int i)
 {
@@ -48,6 +59,15 @@ template <class T, bool SHIFT, class C> __device__ __forceinline__ T from_d(C d,
     else return (T)(wt<C>(i) + d);
 }
 
+// Compile-time loop: f(std::integral_constant<int, I>) for I = B .. E - 1.
+template <int B, int E, class F> __device__ __forceinline__ void static_for(F&& f)
+{
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
 template <class T, int VX> struct Pack { T v[VX]; };
 
 // Memory is addressed as a per-plane base pointer (uniform, computed once
@@ -56,11 +76,92 @@ template <class T, int VX> struct Pack { T v[VX]; };
 // the lattice is created only if those offsets fit in 32 bits. Only element
 // alignment is assumed: the windows start one element off a vector
 // boundary, and gfx950 executes such dwordx2/x3/x4 loads directly.
-template <class T, int VX> __device__ __forceinline__ Pack<T, VX> ld_vec(const char* base, unsigned byte_off)
+//
+// The population buffers are device (global) memory, and every access goes
+// through a global-address-space pointer: pointers that come from a
+// descriptor array rather than a kernel argument (the batched kernels) are
+// otherwise generic to the compiler, which then emits flat accesses with
+// 64-bit per-lane addresses.
+// Aggregates are moved as 1-4 dword vectors (a struct copy through such a
+// pointer would be lowered to a generic-space copy); A is the alignment the
+// address is known to have (the element size).
+#define LBM_GLOBAL __attribute__((address_space(1)))
+template <int N, int A> struct DWords;
+#define LBM_DWORDS(A)                                                                                     \
+    template <> struct DWords<1, A> { typedef unsigned __attribute__((aligned(A))) type; };               \
+    template <> struct DWords<2, A> { typedef unsigned __attribute__((ext_vector_type(2), aligned(A))) type; }; \
+    template <> struct DWords<3, A> { typedef unsigned __attribute__((ext_vector_type(3), aligned(A))) type; }; \
+    template <> struct DWords<4, A> { typedef unsigned __attribute__((ext_vector_type(4), aligned(A))) type; };
+LBM_DWORDS(2)
+LBM_DWORDS(4)
+LBM_DWORDS(8)
+#undef LBM_DWORDS
+
+template <class V, int A = alignof(V)> __device__ __forceinline__ V ld_g(const char* p)
 {
-    Pack<T, VX> r;
-    __builtin_memcpy(&r, base + (size_t)byte_off, sizeof(r));
+    V r;
+    if constexpr (sizeof(V) % 4 == 0) {
+        constexpr int W = sizeof(V) / 4;
+        unsigned w[W];
+        static_for<0, (W + 3) / 4>([&](auto cc) {
+            constexpr int k = 4 * decltype(cc)::value, n = W - k < 4 ? W - k : 4;
+            using D = typename DWords<n, A>::type;
+            const D d = *(const LBM_GLOBAL D*)(p + 4 * k);
+            __builtin_memcpy(&w[k], &d, 4 * n);
+        });
+        __builtin_memcpy(&r, w, sizeof(V));
+    } else {  // e.g. three FP16 values: element by element
+        static_assert(sizeof(V) % sizeof(unsigned short) == 0, "2-byte elements");
+        unsigned short h[sizeof(V) / 2];
+#pragma unroll
+        for (int k = 0; k < (int)(sizeof(V) / 2); ++k) h[k] = *(const LBM_GLOBAL unsigned short*)(p + 2 * k);
+        __builtin_memcpy(&r, h, sizeof(V));
+    }
     return r;
+}
+
+// Non-temporal (streaming) store of a whole aggregate as dword vectors, one
+// store instruction per vector.
+template <class V, int A = alignof(V)> __device__ __forceinline__ void st_g_nt(char* p, const V& v)
+{
+    static_assert(sizeof(V) % 4 == 0, "whole dwords");
+    constexpr int W = sizeof(V) / 4;
+    unsigned w[W];
+    __builtin_memcpy(w, &v, sizeof(V));
+    static_for<0, (W + 3) / 4>([&](auto cc) {
+        constexpr int k = 4 * decltype(cc)::value, n = W - k < 4 ? W - k : 4;
+        using D = typename DWords<n, A>::type;
+        D d;
+        __builtin_memcpy(&d, &w[k], 4 * n);
+        __builtin_nontemporal_store(d, (LBM_GLOBAL D*)(p + 4 * k));
+    });
+}
+
+template <class V, int A = alignof(V)> __device__ __forceinline__ void st_g(char* p, const V& v)
+{
+    if constexpr (sizeof(V) % 4 == 0) {
+        constexpr int W = sizeof(V) / 4;
+        unsigned w[W];
+        __builtin_memcpy(w, &v, sizeof(V));
+        static_for<0, (W + 3) / 4>([&](auto cc) {
+            constexpr int k = 4 * decltype(cc)::value, n = W - k < 4 ? W - k : 4;
+            using D = typename DWords<n, A>::type;
+            D d;
+            __builtin_memcpy(&d, &w[k], 4 * n);
+            *(LBM_GLOBAL D*)(p + 4 * k) = d;
+        });
+    } else {
+        unsigned short h[sizeof(V) / 2];
+        __builtin_memcpy(h, &v, sizeof(V));
+#pragma unroll
+        for (int k = 0; k < (int)(sizeof(V) / 2); ++k) *(LBM_GLOBAL unsigned short*)(p + 2 * k) = h[k];
+    }
+}
+
+// A: the alignment of the address (the storage element size, at most 4).
+template <class T, int VX, int A> __device__ __forceinline__ Pack<T, VX> ld_vec(const char* base, unsigned byte_off)
+{
+    return ld_g<Pack<T, VX>, A>(base + (size_t)byte_off);
 }
 
 // Fused multiply-add in the compute precision (the only FMAs the build emits).
@@ -93,9 +194,49 @@ template <class T, bool SHIFT, class C> __device__ __forceinline__ C d_of(KeepT<
 // e_4 (0,-1); e_5 (1,1); e_6 (-1,1); e_7 (-1,-1); e_8 (1,-1).
 // pb[i] points at column -2 of row 0 of plane i; the byte offset of column
 // x - 1 - e_ix in row q is (q * rs + x + 1 - e_ix) * sizeof(T) >= 0.
+// Near the lattice's left and right edges the windows reach source columns
+// -2 .. -1 and nx .. nx+1: ghost copies for FP16 storage, else padding whose
+// elements are then taken from the periodic image (Sec. 4: periodic in x;
+// see GhostCols).
+template <class LT> __device__ __forceinline__ void set_elem(LT* w, int j, LT v) { w[j] = v; }
+
+// FP16 windows loaded as packed words: element j is half j & 1 of word j / 2.
+__device__ __forceinline__ void set_elem_h(unsigned* w, int j, unsigned short v)
+{
+    const int q = j >> 1;
+    w[q] = (j & 1) ? ((w[q] & 0xffffu) | ((unsigned)v << 16)) : ((w[q] & 0xffff0000u) | (unsigned)v);
+}
+
+// Every element whose source column lies outside [0, nx) is re-loaded from
+// its periodic image by the lanes concerned (a few per edge wave). Which
+// elements can wrap is fixed at compile time: on the left edge those with
+// d = j - 1 - e_ix <= -1, on the right edge those with d >= 1.
+template <class T, int NV, class LT, int NL>
+__device__ __forceinline__ void patch_edges(const char* const (&rb)[9], const Geom& g, int x, Pack<LT, NL> (&v)[9])
+{
+    constexpr int ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    constexpr unsigned es = sizeof(T);
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+            const int d = j - 1 - ex[i];  // source column s = x + d
+            int sw = -1;
+            if (d <= -1 && x + d < 0) sw = x + d + g.nx;                     // left edge: from nx + s
+            if (d >= 1 && x + d >= g.nx) sw = min(x + d - g.nx, g.nx - 1);  // right edge: from s - nx
+            if ((d <= -1 || d >= 1) && sw >= 0) {
+                const char* a = rb[i] + (size_t)((unsigned)(sw + 2) * es);
+                if constexpr (sizeof(LT) == sizeof(T)) set_elem<LT>(v[i].v, j, ld_g<T>(a));
+                else set_elem_h(v[i].v, j, ld_g<unsigned short>(a));
+            }
+        }
+}
+
 // LT / NL: the register type and count the windows are loaded as (the FP16
 // kernels load their windows as packed 32-bit words, NL = ceil(NV / 2)).
-template <class T, int NV, class LT = T, int NL = NV>
+// EDGE = false: the caller knows that no lane of the wave is within reach
+// of a lattice edge (x >= 2 and x + NV <= nx), and no patch code is emitted.
+template <class T, int NV, class LT = T, int NL = NV, bool EDGE = !GhostCols<T>::value>
 __device__ __forceinline__ void gather_raw(const char* const (&pb)[9], const Geom& g, int r, int x, Pack<LT, NL> (&v)[9])
 {
     constexpr unsigned es = sizeof(T);
@@ -106,16 +247,23 @@ __device__ __forceinline__ void gather_raw(const char* const (&pb)[9], const Geo
     const size_t om = (size_t)wrapy(r - 1, g.ny) * rs;  // source row r - 1 (e_iy = +1)
     const size_t o0 = (size_t)wrapy(r, g.ny) * rs;      // source row r     (e_iy =  0)
     const size_t op = (size_t)wrapy(r + 1, g.ny) * rs;  // source row r + 1 (e_iy = -1)
+    const char* const rb[9] = {pb[0] + o0, pb[1] + o0, pb[2] + om, pb[3] + o0, pb[4] + op,
+                               pb[5] + om, pb[6] + om, pb[7] + op, pb[8] + op};
     const unsigned xm = (unsigned)x * es, x0 = xm + es, xp = xm + 2 * es;  // window starts for e_ix = +1, 0, -1
-    v[0] = ld_vec<LT, NL>(pb[0] + o0, x0);
-    v[1] = ld_vec<LT, NL>(pb[1] + o0, xm);
-    v[2] = ld_vec<LT, NL>(pb[2] + om, x0);
-    v[3] = ld_vec<LT, NL>(pb[3] + o0, xp);
-    v[4] = ld_vec<LT, NL>(pb[4] + op, x0);
-    v[5] = ld_vec<LT, NL>(pb[5] + om, xm);
-    v[6] = ld_vec<LT, NL>(pb[6] + om, xp);
-    v[7] = ld_vec<LT, NL>(pb[7] + op, xp);
-    v[8] = ld_vec<LT, NL>(pb[8] + op, xm);
+    constexpr int A = es < 4 ? (int)es : 4;
+    v[0] = ld_vec<LT, NL, A>(rb[0], x0);
+    v[1] = ld_vec<LT, NL, A>(rb[1], xm);
+    v[2] = ld_vec<LT, NL, A>(rb[2], x0);
+    v[3] = ld_vec<LT, NL, A>(rb[3], xp);
+    v[4] = ld_vec<LT, NL, A>(rb[4], x0);
+    v[5] = ld_vec<LT, NL, A>(rb[5], xm);
+    v[6] = ld_vec<LT, NL, A>(rb[6], xp);
+    v[7] = ld_vec<LT, NL, A>(rb[7], xp);
+    v[8] = ld_vec<LT, NL, A>(rb[8], xm);
+    if constexpr (EDGE) {
+        static_assert(!GhostCols<T>::value, "ghost columns make the patch unnecessary");
+        if (x < 2 || x + NV > g.nx) patch_edges<T, NV, LT, NL>(rb, g, x, v);
+    }
 }
 
 // A column of nine populations d_i (one site) as seen by the arithmetic
@@ -263,18 +411,10 @@ __device__ __forceinline__ unsigned pack_h2(float lo, float hi)
     return u;
 }
 
-// Compile-time loop: f(std::integral_constant<int, I>) for I = B .. E - 1.
-template <int B, int E, class F> __device__ __forceinline__ void static_for(F&& f)
-{
-    if constexpr (B < E) {
-        f(std::integral_constant<int, B>{});
-        static_for<B + 1, E>(f);
-    }
-}
 
 // Write row y of the lattice: VX relaxed sites per lane (nv of them valid)
-// and, for the columns that have them, the ghost copies (-2, -1 hold columns
-// nx-2, nx-1; nx, nx+1 hold 0, 1; for nx = 3 column 1 has two ghosts).
+// and, with ghost columns (GhostCols), the copies of the edge columns (-2, -1
+// hold nx-2, nx-1; nx, nx+1 hold 0, 1; for nx = 3 column 1 has two ghosts).
 template <class T, int VX, bool NTS>
 __device__ __forceinline__ void write_row(char* const (&dbase)[9], const Geom& g, int y, int x, int nv,
                                           const Pack<T, VX> (&out)[9])
@@ -287,11 +427,21 @@ __device__ __forceinline__ void write_row(char* const (&dbase)[9], const Geom& g
         for (int i = 0; i < 9; ++i) {
             char* rb = dbase[i] + ro;
             if constexpr (NTS) {
+                // One non-temporal vector store per plane. Which source form
+                // gets that from the compiler was found by reading the
+                // generated code: element-wise through a generic pointer for
+                // FP32 (a dword-vector store lost its non-temporal bit), a
+                // dword-vector store for FP64 and FP16 (element-wise ones were
+                // split into partial stores).
+                if constexpr (sizeof(T) == 4 || sizeof(out[i]) % 4 != 0) {
 #pragma unroll
-                for (int j = 0; j < VX; ++j)
-                    __builtin_nontemporal_store(out[i].v[j], (T*)(rb + (size_t)(lo + j * es)));
+                    for (int j = 0; j < VX; ++j)
+                        __builtin_nontemporal_store(out[i].v[j], (T*)(rb + (size_t)(lo + j * es)));
+                } else {
+                    st_g_nt<Pack<T, VX>, (sizeof(out[i]) < 8 ? (int)sizeof(out[i]) : 8)>(rb + (size_t)lo, out[i]);
+                }
             } else {
-                __builtin_memcpy(rb + (size_t)lo, &out[i], sizeof(out[i]));
+                st_g<Pack<T, VX>>(rb + (size_t)lo, out[i]);
             }
         }
     } else {
@@ -299,20 +449,22 @@ __device__ __forceinline__ void write_row(char* const (&dbase)[9], const Geom& g
         for (int i = 0; i < 9; ++i)
 #pragma unroll
             for (int j = 0; j < VX; ++j)
-                if (j < nv) __builtin_memcpy(dbase[i] + ro + (size_t)(lo + j * es), &out[i].v[j], es);
+                if (j < nv) st_g<T>(dbase[i] + ro + (size_t)(lo + j * es), out[i].v[j]);
     }
+    if constexpr (GhostCols<T>::value) {
 #pragma unroll
-    for (int j = 0; j < VX; ++j) {
-        const int c = x + j;
-        if (j < nv && c >= g.nx - 2) {
+        for (int j = 0; j < VX; ++j) {
+            const int c = x + j;
+            if (j < nv && c >= g.nx - 2) {
 #pragma unroll
-            for (int i = 0; i < 9; ++i)  // column c - nx in [-2, -1]
-                __builtin_memcpy(dbase[i] + ro - 2 * es + (size_t)((unsigned)(c - g.nx + 2) * es), &out[i].v[j], es);
-        }
-        if (j < nv && c <= 1) {
+                for (int i = 0; i < 9; ++i)  // column c - nx in [-2, -1]
+                    st_g<T>(dbase[i] + ro - 2 * es + (size_t)((unsigned)(c - g.nx + 2) * es), out[i].v[j]);
+            }
+            if (j < nv && c <= 1) {
 #pragma unroll
-            for (int i = 0; i < 9; ++i)  // column c + nx in [nx, nx + 1]
-                __builtin_memcpy(dbase[i] + ro + (size_t)((unsigned)(c + g.nx) * es), &out[i].v[j], es);
+                for (int i = 0; i < 9; ++i)  // column c + nx in [nx, nx + 1]
+                    st_g<T>(dbase[i] + ro + (size_t)((unsigned)(c + g.nx) * es), out[i].v[j]);
+            }
         }
     }
 }
@@ -344,20 +496,11 @@ __device__ __forceinline__ void plane_bases(const void* src, void* dst, const Ge
     }
 }
 
-// One vertical-stack tile: strip `strip` (64 * VX columns) and row group
-// `grp` (R = NW - 2 rows) of the lattice described by `a`, with src/dst the
-// buffers of this step. A workgroup of NW waves: wave w handles row
-// y0 - 1 + w, so waves 0 and R + 1 take the rows just outside the group,
-// whose densities the gradient needs. Every wave loads its row's windows,
-// forms the window densities and publishes its own columns' densities in
-// `lds`; after one barrier the interior waves read the densities of the
-// rows above and below, relax and write. The caller must place a barrier
-// between two calls that reuse `lds`.
 // vstack_tile for FP16 storage (shifted form): the same tile, rows,
 // summation orders and roundings, with the populations kept as the packed
 // halves they were loaded as (see ColH) and the results rounded to FP16 two
 // at a time.
-template <int VX, int NW, bool NTS>
+template <int VX, int NW, bool NTS, bool EDGE>
 __device__ __forceinline__ void vstack_tile_h(const StepTile& a, const void* src, void* dst, int strip, int grp,
                                               float (&lds)[NW][64 * VX])
 {
@@ -381,10 +524,10 @@ __device__ __forceinline__ void vstack_tile_h(const StepTile& a, const void* src
     unsigned u[9][NWD];
     float w[WV];
     if (active) {
-        // An odd-length window (VX = 1) loads one half past its end: column
-        // x + 2 <= nx + 1, a ghost column, inside the row.
+        // An odd-length window (VX = 1) loads one half past its end (at most
+        // column nx + 2, row padding).
         Pack<unsigned, NWD> raw[9];
-        gather_raw<T, WV, unsigned, NWD>(sb, g, y, x, raw);
+        gather_raw<T, WV, unsigned, NWD, EDGE>(sb, g, y, x, raw);
 #pragma unroll
         for (int i = 0; i < 9; ++i)
 #pragma unroll
@@ -425,15 +568,10 @@ __device__ __forceinline__ void vstack_tile_h(const StepTile& a, const void* src
     }
 }
 
-template <class T, bool SHIFT, int VX, int NW, bool NTS>
-__device__ __forceinline__ void vstack_tile(const StepTile& a, const void* src, void* dst, int strip, int grp,
-                                            typename CompT<T>::type (&lds)[NW][64 * VX])
+template <class T, bool SHIFT, int VX, int NW, bool NTS, bool EDGE>
+__device__ __forceinline__ void vstack_tile_f(const StepTile& a, const void* src, void* dst, int strip, int grp,
+                                              typename CompT<T>::type (&lds)[NW][64 * VX])
 {
-    if constexpr (std::is_same<T, _Float16>::value) {
-        static_assert(SHIFT, "FP16 storage is the shifted form");
-        vstack_tile_h<VX, NW, NTS>(a, src, dst, strip, grp, lds);
-        return;
-    } else {
     using C = typename CompT<T>::type;
     using K = KeepT<T, C>;
     constexpr int WV = VX + 2;
@@ -456,7 +594,7 @@ __device__ __forceinline__ void vstack_tile(const StepTile& a, const void* src, 
     C w[WV];
     if (active) {
         Rw raw[9];
-        gather_raw<T, WV>(sb, g, y, x, raw);
+        gather_raw<T, WV, T, WV, EDGE>(sb, g, y, x, raw);
         K tmp[9][WV];
 #pragma unroll
         for (int i = 0; i < 9; ++i)
@@ -487,6 +625,34 @@ __device__ __forceinline__ void vstack_tile(const StepTile& a, const void* src, 
         }
         write_row<T, VX, NTS>(dbase, g, y, x, nv, out);
     }
+}
+
+// One vertical-stack tile: strip `strip` (64 * VX columns) and row group
+// `grp` (R = NW - 2 rows) of the lattice described by `a`, with src/dst the
+// buffers of this step. A workgroup of NW waves: wave w handles row
+// y0 - 1 + w, so waves 0 and R + 1 take the rows just outside the group,
+// whose densities the gradient needs. Every wave loads its row's windows,
+// forms the window densities and publishes its own columns' densities in
+// `lds`; after one barrier the interior waves read the densities of the
+// rows above and below, relax and write. The caller must place a barrier
+// between two calls that reuse `lds`.
+// Without ghost columns (see GhostCols), strips whose windows can reach past
+// a lattice edge (the first, and those within two columns of the right edge)
+// take a separate copy of the code with the edge patches; the others issue
+// their loads and start the arithmetic as the loads land, with no patch code
+// in between. The branch is uniform over the workgroup.
+template <class T, bool SHIFT, int VX, int NW, bool NTS>
+__device__ __forceinline__ void vstack_tile(const StepTile& a, const void* src, void* dst, int strip, int grp,
+                                            typename CompT<T>::type (&lds)[NW][64 * VX])
+{
+    if constexpr (std::is_same<T, _Float16>::value) {
+        static_assert(SHIFT, "FP16 storage is the shifted form");
+        static_assert(GhostCols<T>::value, "FP16 rows carry ghost columns");
+        vstack_tile_h<VX, NW, NTS, false>(a, src, dst, strip, grp, lds);
+    } else {
+        const bool edge = strip == 0 || (strip + 1) * (64 * VX) + 2 > a.g.nx;
+        if (edge) vstack_tile_f<T, SHIFT, VX, NW, NTS, true>(a, src, dst, strip, grp, lds);
+        else vstack_tile_f<T, SHIFT, VX, NW, NTS, false>(a, src, dst, strip, grp, lds);
     }
 }
 
