@@ -82,6 +82,24 @@ def test_results_bitwise_independent_of_tile(dtype):
     assert max_rel_err(outs[0], fr) <= TILE_TOL[dtype]
 
 
+# Widths around the window and strip sizes (64 lanes x 1, 2, 4 sites): the
+# periodic wrap in x at both lattice edges, lanes with a partial window,
+# one-strip and several-strip rows.
+EDGE_WIDTHS = [3, 4, 6, 7, 63, 64, 65, 127, 128, 129, 130, 255, 258, 513]
+EDGE_TILES = [(1, 8, 0, 18), (2, 8, 0, 18), (4, 8, 0, 16), (2, 16, 0, 18), (1, 1, 1, 0), (2, 4, 8, 15)]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "f32s", "f16s"])
+def test_x_edges_every_width_and_shape(dtype):
+    for nx in EDGE_WIDTHS:
+        fields = smooth_random_state(nx, 9, seed=nx)
+        outs = [run_gpu(nx, 9, 0.65, 0.3, dtype, 25, fields, tile=t)[0] for t in EDGE_TILES]
+        for t, o in zip(EDGE_TILES[1:], outs[1:]):
+            assert np.array_equal(o, outs[0]), (nx, t)
+        fr, _ = run_ref(nx, 9, 0.65, 0.3, 25, fields)
+        assert max_rel_err(outs[0], fr) <= TILE_TOL[dtype], nx
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32", "f32s", "f16s"])
 def test_rest_state_and_determinism(dtype):
     with lbm.Lattice(33, 19, 0.6, 0.9, dtype) as L:
