@@ -4,6 +4,8 @@ TEST INFRASTRUCTURE. Only the tests, the smoke check and the benchmark's
 CPU-baseline leg load this package. The product library never does, and the
 two share no code.
 """
-from .lbmref import Oracle, lattice, alpha, equilibrium, source, load, set_threads, get_threads
+from .lbmref import (Oracle, lattice, alpha, equilibrium, equilibrium_c2, source, load, set_threads, get_threads,
+                     MODEL_FORCING, MODEL_EQUILIBRIUM)
 
-__all__ = ["Oracle", "lattice", "alpha", "equilibrium", "source", "load", "set_threads", "get_threads"]
+__all__ = ["Oracle", "lattice", "alpha", "equilibrium", "equilibrium_c2", "source", "load", "set_threads", "get_threads",
+           "MODEL_FORCING", "MODEL_EQUILIBRIUM"]

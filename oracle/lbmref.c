@@ -21,6 +21,8 @@ struct lbmref {
     int nx, ny;
     double tau;     /* relaxation time, Eq. 1                              */
     double alpha;   /* forcing amplitude, Eq. 5; alpha = 1/3 - c_e^2       */
+    double c2;      /* c_e^2 as requested                                  */
+    int model;      /* enum lbmref_model                                   */
     long long t;    /* completed steps                                     */
     int ready;      /* set by init / set_f                                 */
     double* f;      /* f_i(x, t), [9][ny][nx]                              */
@@ -95,7 +97,45 @@ void lbmref_source(double alpha, double gx, double gy, double s[9])
         s[i] = 3.0 * w[i] * alpha * (gx * e[2 * i] + gy * e[2 * i + 1]);
 }
 
+/* Altered equilibrium (the equilibrium route of Sec. 3 on D2Q9): the
+ * moving populations carry 3 c^2 in place of the 1 of Eq. 2 and the rest
+ * population takes what is left of rho. */
+void lbmref_equilibrium_c2(double c2, double rho, double ux, double uy, double feq[9])
+{
+    const int* e = E;
+    const double* w = W;
+    double usq = ux * ux + uy * uy;
+    double moving = 0.0;
+    for (int i = 1; i < 9; ++i) {
+        double eu = e[2 * i] * ux + e[2 * i + 1] * uy;
+        feq[i] = w[i] * rho * (3.0 * c2 + 3.0 * eu + 4.5 * eu * eu - 1.5 * usq);
+        moving += feq[i];
+    }
+    feq[0] = rho - moving;
+}
+
 static int wrap(int a, int n) { return ((a % n) + n) % n; }
+
+int lbmref_set_model(lbmref* L, int model)
+{
+    if (!L) return LBMREF_EINVAL;
+    if (model == LBMREF_MODEL_FORCING) {
+        L->model = model;
+        return LBMREF_OK;
+    }
+    if (model == LBMREF_MODEL_EQUILIBRIUM && L->c2 < 0.6) {
+        L->model = model;
+        return LBMREF_OK;
+    }
+    return LBMREF_EINVAL;
+}
+
+/* The equilibrium of the lattice's model. */
+static void model_equilibrium(const lbmref* L, double rho, double ux, double uy, double feq[9])
+{
+    if (L->model == LBMREF_MODEL_EQUILIBRIUM) lbmref_equilibrium_c2(L->c2, rho, ux, uy, feq);
+    else lbmref_equilibrium(rho, ux, uy, feq);
+}
 
 lbmref* lbmref_create(int nx, int ny, double tau, double c2)
 {
@@ -117,6 +157,8 @@ lbmref* lbmref_create(int nx, int ny, double tau, double c2)
     L->ny = ny;
     L->tau = tau;
     L->alpha = lbmref_alpha(c2);
+    L->c2 = c2;
+    L->model = LBMREF_MODEL_FORCING;
     L->f = (double*)calloc(9 * n, sizeof(double));
     L->fnew = (double*)calloc(9 * n, sizeof(double));
     L->R = (double*)calloc(n, sizeof(double));
@@ -149,7 +191,7 @@ int lbmref_init(lbmref* L, const double* rho, const double* ux, const double* uy
     size_t n = (size_t)nx * ny;
     for (size_t s = 0; s < n; ++s) {
         double feq[9];
-        lbmref_equilibrium(rho ? rho[s] : 1.0, ux ? ux[s] : 0.0, uy ? uy[s] : 0.0, feq);
+        model_equilibrium(L, rho ? rho[s] : 1.0, ux ? ux[s] : 0.0, uy ? uy[s] : 0.0, feq);
         for (int i = 0; i < 9; ++i) L->f[i * n + s] = feq[i];
     }
     L->t = 0;
@@ -181,7 +223,8 @@ static void compute_moments(lbmref* L)
     }
 }
 
-/* One time step of Eq. 5. */
+/* One time step of Eq. 5 (or of the equilibrium model: relaxation to
+ * lbmref_equilibrium_c2, no source term). */
 static void step_once(lbmref* L)
 {
     const int* e = E;
@@ -201,8 +244,9 @@ static void step_once(lbmref* L)
             double gy = (L->R[(size_t)wrap(y + 1, ny) * nx + x] -
                          L->R[(size_t)wrap(y - 1, ny) * nx + x]) / 2.0;
             double feq[9], src[9];
-            lbmref_equilibrium(L->R[s], L->UX[s], L->UY[s], feq);
-            lbmref_source(L->alpha, gx, gy, src);
+            model_equilibrium(L, L->R[s], L->UX[s], L->UY[s], feq);
+            /* the equilibrium model has no source term */
+            lbmref_source(L->model == LBMREF_MODEL_EQUILIBRIUM ? 0.0 : L->alpha, gx, gy, src);
             for (int i = 0; i < 9; ++i) {
                 /* Right-hand side of Eq. 5 added to f_i(x, t) ... */
                 double fi = L->f[i * n + s];

@@ -51,6 +51,19 @@ void lbmref_equilibrium(double rho, double ux, double uy, double feq[9]);
 /* Source term of Eq. 5: s[i] = 3 w_i alpha (e_ix gx + e_iy gy). */
 void lbmref_source(double alpha, double gx, double gy, double s[9]);
 
+/* The other route to a free speed of sound that the paper discusses (Sec. 3,
+ * opening): alter the equilibrium, i.e. the share of rest and moving
+ * particles, instead of adding a force. On D2Q9 with sound speed c:
+ *   feq[i] = w_i rho [3 c^2 + 3 e_i.u + 9/2 (e_i.u)^2 - 3/2 u.u]   (i != 0)
+ *   feq[0] = rho - sum_{i != 0} feq[i]
+ * whose moments are rho, rho u and c^2 rho I + rho u u; c^2 = 1/3 gives
+ * Eq. 2. Used by LBMREF_MODEL_EQUILIBRIUM. */
+void lbmref_equilibrium_c2(double c2, double rho, double ux, double uy, double feq[9]);
+
+/* Which model a lattice steps (lbmref_set_model): the paper's Eq. 5
+ * (default), or relaxation to lbmref_equilibrium_c2 with no source term. */
+enum lbmref_model { LBMREF_MODEL_FORCING = 0, LBMREF_MODEL_EQUILIBRIUM = 1 };
+
 /* Create a periodic nx x ny lattice. nx, ny >= 3; tau > 1/2 (Eq. 4 gives
  * nu > 0); c2 > 0 (Eq. 8). Returns NULL and sets lbmref_last_error() on
  * failure. */
@@ -58,7 +71,12 @@ lbmref* lbmref_create(int nx, int ny, double tau, double c2);
 int lbmref_last_error(void);
 void lbmref_destroy(lbmref* L);
 
-/* f_i(x, 0) = feq_i(rho(x), u(x)). NULL rho means rho = 1, NULL ux / uy
+/* Select the model (enum lbmref_model) before init; LBMREF_EINVAL for an
+ * unknown model, or for the equilibrium model with c2 >= 3/5 (its rest
+ * population feq[0] = rho (1 - 5 c^2 / 3) would not be positive). */
+int lbmref_set_model(lbmref* L, int model);
+
+/* f_i(x, 0) = feq_i(rho(x), u(x)) of the lattice's model. NULL rho means rho = 1, NULL ux / uy
  * mean 0. Arrays have nx*ny entries. Sets t = 0. */
 int lbmref_init(lbmref* L, const double* rho, const double* ux, const double* uy);
 

@@ -40,6 +40,10 @@ def load(path=None):
     lib.lbmref_equilibrium.argtypes = [ctypes.c_double] * 3 + [_dp]
     lib.lbmref_equilibrium.restype = None
     lib.lbmref_source.argtypes = [ctypes.c_double] * 3 + [_dp]
+    lib.lbmref_equilibrium_c2.argtypes = [ctypes.c_double] * 4 + [_dp]
+    lib.lbmref_equilibrium_c2.restype = None
+    lib.lbmref_set_model.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    lib.lbmref_set_model.restype = ctypes.c_int
     lib.lbmref_source.restype = None
     lib.lbmref_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double]
     lib.lbmref_create.restype = ctypes.c_void_p
@@ -86,6 +90,16 @@ def equilibrium(rho, ux, uy, lib=None):
     return out
 
 
+def equilibrium_c2(c2, rho, ux, uy, lib=None):
+    """The altered equilibrium of the equilibrium model (lbmref.h)."""
+    out = np.zeros(9)
+    (lib or load()).lbmref_equilibrium_c2(float(c2), float(rho), float(ux), float(uy), _ptr(out))
+    return out
+
+
+MODEL_FORCING, MODEL_EQUILIBRIUM = 0, 1
+
+
 def source(alpha_, gx, gy, lib=None):
     out = np.zeros(9)
     (lib or load()).lbmref_source(float(alpha_), float(gx), float(gy), _ptr(out))
@@ -109,13 +123,15 @@ class OracleError(RuntimeError):
 class Oracle:
     """One periodic lattice stepped by the FP64 oracle."""
 
-    def __init__(self, nx, ny, tau, c2, lib_path=None):
+    def __init__(self, nx, ny, tau, c2, lib_path=None, model=MODEL_FORCING):
         self.lib = load(lib_path)
         self.nx, self.ny, self.tau, self.c2 = int(nx), int(ny), float(tau), float(c2)
         h = self.lib.lbmref_create(self.nx, self.ny, self.tau, self.c2)
         if not h:
             raise OracleError(self.lib.lbmref_last_error(), "lbmref_create")
         self._h = ctypes.c_void_p(h)
+        if model != MODEL_FORCING:
+            self._check(self.lib.lbmref_set_model(self._h, int(model)), "lbmref_set_model")
 
     def close(self):
         if getattr(self, "_h", None):

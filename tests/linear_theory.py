@@ -1,5 +1,11 @@
 """Linear (von Neumann) theory of the scheme, used to pin the oracle.
 
+Two models: the paper's forcing model (Eq. 5, model=0) below, and the
+altered-equilibrium model (model=1) of the oracle's lbmref_equilibrium_c2,
+whose linearised equilibrium is feq_i ~ w_i (3 c^2 drho + 3 e_i.j) for
+i != 0 and feq_0 ~ (1 - 5 c^2 / 3) drho (what is left of drho), with no
+source term.
+
 Written from the paper's equations independently of the oracle: around rest
 (rho = 1, u = 0) a perturbation delta f_i(x) = a_i exp(i k.x) obeys
   a(t+1) = M(k) a(t),
@@ -18,21 +24,32 @@ E = np.array([[0, 0], [1, 0], [0, 1], [-1, 0], [0, -1],
 W = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
 
 
-def matrix(kx, ky, tau, c2):
-    alpha = 1.0 / 3.0 - c2
-    J = W[:, None] * (1.0 + 3.0 * (E @ E.T))
-    A = 3.0 * W[:, None] * alpha * 1j * (E[:, 0] * np.sin(kx) + E[:, 1] * np.sin(ky))[:, None] * np.ones((1, 9))
+def matrix(kx, ky, tau, c2, model=0):
+    if model == 1:
+        J = W[:, None] * (3.0 * c2 + 3.0 * (E @ E.T))
+        J[0, :] = 1.0 - 5.0 * c2 / 3.0
+        A = np.zeros((9, 9), dtype=complex)
+    else:
+        alpha = 1.0 / 3.0 - c2
+        J = W[:, None] * (1.0 + 3.0 * (E @ E.T))
+        A = 3.0 * W[:, None] * alpha * 1j * (E[:, 0] * np.sin(kx) + E[:, 1] * np.sin(ky))[:, None] * np.ones((1, 9))
     C = np.eye(9) - (np.eye(9) - J) / tau + A
     S = np.diag(np.exp(-1j * (E[:, 0] * kx + E[:, 1] * ky)))
     return S @ C
 
 
-def evolve_fields(amp_rho, kx, ky, nx, ny, tau, c2, t, amp_u=(0.0, 0.0)):
+def evolve_fields(amp_rho, kx, ky, nx, ny, tau, c2, t, amp_u=(0.0, 0.0), model=0):
     """Linear prediction of (drho, jx, jy) on an nx x ny grid after t steps for
     the initial state f = feq(1 + amp_rho sin(k.x), u = amp_u sin(k.x))."""
     # sin(k.x) = (exp(ik.x) - exp(-ik.x)) / (2i); feq linearised: w_i(drho + 3 e_i.u)
-    a0 = W * (amp_rho + 3.0 * (E[:, 0] * amp_u[0] + E[:, 1] * amp_u[1])) / 2j
-    M = matrix(kx, ky, tau, c2)
+    ej = E[:, 0] * amp_u[0] + E[:, 1] * amp_u[1]
+    if model == 1:
+        a0 = W * (3.0 * c2 * amp_rho + 3.0 * ej)
+        a0[0] = (1.0 - 5.0 * c2 / 3.0) * amp_rho
+        a0 = a0 / 2j
+    else:
+        a0 = W * (amp_rho + 3.0 * ej) / 2j
+    M = matrix(kx, ky, tau, c2, model)
     a = np.linalg.matrix_power(M, t) @ a0
     y, x = np.mgrid[0:ny, 0:nx]
     ph = np.exp(1j * (kx * x + ky * y))
@@ -42,12 +59,12 @@ def evolve_fields(amp_rho, kx, ky, nx, ny, tau, c2, t, amp_u=(0.0, 0.0)):
     return rho, jx, jy
 
 
-def acoustic_eigs(kx, ky, tau, c2):
+def acoustic_eigs(kx, ky, tau, c2, model=0):
     """The two eigenvalues of M(k) of largest modulus (the sound modes)."""
-    lam = np.linalg.eigvals(matrix(kx, ky, tau, c2))
+    lam = np.linalg.eigvals(matrix(kx, ky, tau, c2, model))
     order = np.argsort(-np.abs(lam))
     return lam[order[:3]]
 
 
-def spectral_radius(kx, ky, tau, c2):
-    return np.max(np.abs(np.linalg.eigvals(matrix(kx, ky, tau, c2))))
+def spectral_radius(kx, ky, tau, c2, model=0):
+    return np.max(np.abs(np.linalg.eigvals(matrix(kx, ky, tau, c2, model))))
