@@ -5,7 +5,9 @@ Workload (one "step"): one time step of each of five periodic 4096 x 4096
 lattices, tau = 0.6, c^2 in {0.04, 0.2, 1/3, 0.5, 0.81} (c_e = 0.2 ... 0.9),
 each initialised with a plane sound wave of amplitude 1e-3 plus seeded
 uniform density noise +-1e-4. Headline: FP32 storage and arithmetic. The
-same sweep in FP64 is reported under "forms", beside the batched form (256
+same sweep in FP64, and the altered-equilibrium model (the other route to
+a free c^2, Sec. 3 opening) over c^2 in {0.04, 0.2, 1/3, 0.5, 0.56}, are
+reported under "forms", beside the batched form (256
 seeded lattices of uneven size, tau and c^2 in one pool) and the served form
 (a continuous-batching server fed Poisson job arrivals for a short window).
 
@@ -37,7 +39,9 @@ def parse():
     p.add_argument("--steps", type=int, default=1000)
     p.add_argument("--warmup", type=int, default=20)
     p.add_argument("--n", type=int, default=4096, help="lattice side")
-    p.add_argument("--forms", default="f64", help="extra forms to time, comma separated ('' for none)")
+    p.add_argument("--forms", default="f64,f32_eq",
+                   help="extra forms to time, comma separated ('' for none); a '_eq' suffix selects the "
+                        "altered-equilibrium model over its own c^2 sweep")
     p.add_argument("--form-steps", type=int, default=300)
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     p.add_argument("--cpu-steps", type=int, default=200)
@@ -58,10 +62,14 @@ def parse():
 
 
 def make_sweep(lbm, workloads, torch, n, dtype, stream):
+    # "<dtype>_eq": the altered-equilibrium model over its own c^2 sweep
+    model, sweep = lbm.MODEL_FORCING, workloads.C2_SWEEP
+    if dtype.endswith("_eq"):
+        dtype, model, sweep = dtype[:-3], lbm.MODEL_EQUILIBRIUM, workloads.C2_SWEEP_EQ
     lattices = []
-    for k, c2 in enumerate(workloads.C2_SWEEP):
+    for k, c2 in enumerate(sweep):
         rho, ux, uy = workloads.plane_wave_fields(n, n, c2, seed=k)
-        L = lbm.Lattice(n, n, 0.6, c2, dtype)
+        L = lbm.Lattice(n, n, 0.6, c2, dtype, model=model)
         L.set_stream(stream)
         L.init(rho, ux, uy)
         lattices.append(L)
@@ -88,6 +96,7 @@ def time_sweep(torch, lattices, steps, warmup, stream):
 
 def kernel_name(tile, dtype):
     vx, nw, h, flags = tile
+    dtype = dtype.removesuffix("_eq")
     t = {"f64": "double,false", "f32": "float,false", "f32s": "float,true", "f16s": "_Float16,true"}[dtype]
     if flags & 16:
         return f"lbm::step_vstack_kernel<{t},{vx},{nw},{'true' if flags & 2 else 'false'}>"
@@ -121,7 +130,7 @@ def measure_form(lbm, workloads, torch, n, dtype, steps, warmup):
     sites = n * n * len(lats)
     launches = steps * len(lats)
     mlups = sites * steps / sec / 1e6
-    gbs = BYTES_PER_SITE[dtype] * n * n / (sec / launches) / 1e9
+    gbs = BYTES_PER_SITE[dtype.removesuffix("_eq")] * n * n / (sec / launches) / 1e9
     return {"mlups": mlups, "ms_per_step": 1e3 * sec / steps, "kernel_us": 1e6 * sec / launches,
             "achieved_GBs": gbs, "frac": gbs / PEAK_HBM_GBS, "wall_s": wall,
             "mass_total_first": tot[0][0], "kernel": kernel_name(tile, dtype), "tile": list(tile)}
@@ -230,7 +239,7 @@ def measure_precision(lbm, workloads, torch, steps, warmup=5, n=8192):
         tile = L.get_tile()
         L.close()
         mlups = n * n * steps / sec / 1e6
-        gbs = BYTES_PER_SITE[dtype] * n * n * steps / sec / 1e9
+        gbs = BYTES_PER_SITE[dtype.removesuffix("_eq")] * n * n * steps / sec / 1e9
         out[dtype] = {"mlups": mlups, "achieved_GBs": gbs, "frac": gbs / PEAK_HBM_GBS, "steps": steps,
                       "kernel": kernel_name(tile, dtype), "lattice": [n, n]}
     return out

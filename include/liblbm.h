@@ -79,6 +79,24 @@ void lbm_destroy(lbm_lattice* L);
  * Synchronous. */
 int lbm_init(lbm_lattice* L, const double* rho, const double* ux, const double* uy);
 
+/* Which model a lattice steps. LBM_MODEL_FORCING (the default) is the
+ * paper's model, Eq. 5: relaxation to the Eq. 2 equilibrium plus the source
+ * 3 w_i alpha grad(rho).e_i with alpha = 1/3 - c2. LBM_MODEL_EQUILIBRIUM is
+ * the other route to a free sound speed the paper discusses (Sec. 3,
+ * opening: alter the equilibrium, i.e. the share of rest and moving
+ * particles), on D2Q9: relaxation to
+ *   feq_i = w_i rho [3 c2 + 3 e_i.u + 9/2 (e_i.u)^2 - 3/2 u.u]  (i != 0),
+ *   feq_0 = rho - sum_{i != 0} feq_i,
+ * with no source term; its momentum flux is c2 rho I + rho u u exactly, and
+ * c2 = 1/3 gives Eq. 2. */
+enum lbm_model { LBM_MODEL_FORCING = 0, LBM_MODEL_EQUILIBRIUM = 1 };
+/* Select the model for the following lbm_init / lbm_step calls (lbm_init
+ * sets f to that model's equilibrium). LBM_EINVAL for a NULL handle, an
+ * unknown model, or LBM_MODEL_EQUILIBRIUM with c2 >= 3/5 (its rest
+ * population rho (1 - 5 c2 / 3) would not be positive). Pools step the
+ * forcing model. */
+int lbm_set_model(lbm_lattice* L, int model);
+
 /* As lbm_init, but rho / ux / uy are DEVICE pointers (same layout) on the
  * lattice's device; asynchronous on the lattice's stream. */
 int lbm_init_device(lbm_lattice* L, const double* rho, const double* ux, const double* uy);

@@ -29,6 +29,7 @@ SIGNATURES = {
     "lbm_strerror": (ctypes.c_char_p, [_i]),
     "lbm_destroy": (None, [_vp]),
     "lbm_init": (_i, [_vp, _vp, _vp, _vp]),
+    "lbm_set_model": (_i, [_vp, _i]),
     "lbm_init_device": (_i, [_vp, _vp, _vp, _vp]),
     "lbm_step": (_i, [_vp, _i]),
     "lbm_moments": (_i, [_vp, _vp, _vp, _vp, _vp]),

@@ -15,7 +15,7 @@ namespace lbm {
 hipError_t launch_step(int dtype, int vx, int nw, int flags, const StepTile& t, hipStream_t st);
 bool step_shape_supported(int dtype, int vx, int nw, int flags);
 hipError_t launch_init(int dtype, void* s, const Geom& g, const double* rho, const double* ux, const double* uy,
-                       hipStream_t st);
+                       double eqs, hipStream_t st);
 hipError_t launch_set_f(int dtype, void* s, const Geom& g, const double* f, hipStream_t st);
 hipError_t launch_get_f(int dtype, const void* s, const Geom& g, double* f, hipStream_t st);
 int moments_blocks(const Geom& g);
@@ -109,12 +109,21 @@ inline size_t footprint(const Geom& g, int esize)
 
 inline size_t red_doubles(const Geom& g) { return (size_t)3 * moments_blocks(g) + 3; }
 
-inline Coef make_coef(double tau, double c2)
+// The equilibrium shift of the altered-equilibrium model: 3 c^2 - 1 (its
+// moving populations carry 3 c^2 in place of the 1 of Eq. 2); 0 for the
+// paper's model.
+inline double eq_shift(double c2, int model) { return model == LBM_MODEL_EQUILIBRIUM ? 3.0 * c2 - 1.0 : 0.0; }
+
+inline Coef make_coef(double tau, double c2, int model)
 {
     // Eq. 5 with alpha = 1/3 - c2 (Eq. 8), weights of Sec. 2; the 1/2 of the
-    // central differences is folded into as1, as2.
-    const double om = 1.0 / tau, alpha = 1.0 / 3.0 - c2;
+    // central differences is folded into as1, as2. The altered-equilibrium
+    // model has no source term and shifts the equilibrium instead: for
+    // i != 0, feq_i - w_i gains w_i rho (3 c^2 - 1); feq_0 loses the sum of
+    // those, (5/9) rho (3 c^2 - 1) = w_0 rho (5/4)(3 c^2 - 1).
+    const double om = 1.0 / tau, alpha = model == LBM_MODEL_EQUILIBRIUM ? 0.0 : 1.0 / 3.0 - c2;
     const double w0 = 4.0 / 9.0, w1 = 1.0 / 9.0, w2 = 1.0 / 36.0;
+    const double sh = eq_shift(c2, model);
     Coef k;
     k.om1 = 1.0 - om;
     k.wo0 = om * w0;
@@ -122,12 +131,16 @@ inline Coef make_coef(double tau, double c2)
     k.wo2 = om * w2;
     k.as1 = 1.5 * w1 * alpha;
     k.as2 = 1.5 * w2 * alpha;
+    k.e1 = sh;
+    k.e0 = -1.25 * sh;
     k.om1f = (float)k.om1;
     k.wo0f = (float)k.wo0;
     k.wo1f = (float)k.wo1;
     k.wo2f = (float)k.wo2;
     k.as1f = (float)k.as1;
     k.as2f = (float)k.as2;
+    k.e1f = (float)k.e1;
+    k.e0f = (float)k.e0;
     return k;
 }
 
@@ -142,6 +155,13 @@ inline int xcd_chunk_tiles(int nstrips)
     }
     const int groups = (16 + nstrips - 1) / nstrips;
     return groups * nstrips;
+}
+
+// Models an lbm_set_model call may select for (c2): the altered-equilibrium
+// model needs a positive rest population, 1 - 5 c^2 / 3 > 0.
+inline bool model_ok(int model, double c2)
+{
+    return model == LBM_MODEL_FORCING || (model == LBM_MODEL_EQUILIBRIUM && c2 < 0.6);
 }
 
 inline int status_of(hipError_t e)

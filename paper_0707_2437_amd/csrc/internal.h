@@ -38,11 +38,14 @@ struct Geom {
 // with om = 1/tau, om1 = 1 - om, wo_k = om w_k, and as_k = 3 w_k alpha / 2:
 // the source term 3 w_k alpha (e_i . grad rho) is applied to the undivided
 // central differences rho(x + 1) - rho(x - 1), so the 1/2 of the central
-// difference sits in the coefficient (an exact power-of-two scaling). The
-// FP32-compute kernels take the same values rounded once to FP32.
+// difference sits in the coefficient (an exact power-of-two scaling).
+// e1, e0 shift the equilibrium for the altered-equilibrium model (0 for the
+// paper's model): the moving pairs relax towards A + rho e1 in place of A,
+// the rest population towards A + rho e0. The FP32-compute kernels take the
+// same values rounded once to FP32.
 struct Coef {
-    double om1, wo0, wo1, wo2, as1, as2;
-    float om1f, wo0f, wo1f, wo2f, as1f, as2f;
+    double om1, wo0, wo1, wo2, as1, as2, e1, e0;
+    float om1f, wo0f, wo1f, wo2f, as1f, as2f, e1f, e0f;
 };
 
 // One lattice as seen by a step launch.

@@ -186,18 +186,25 @@ __device__ __constant__ int kEY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 
 __device__ __forceinline__ double wt64(int i) { return wt<double>(i); }
 
-// Eq. 2, returned as feq_i - w_i (accurate for the shifted forms).
-__device__ __forceinline__ double dfeq(int i, double rho, double ux, double uy)
+// Eq. 2, returned as feq_i - w_i (accurate for the shifted forms). eqs is
+// the equilibrium shift of the altered-equilibrium model (0 for Eq. 2): the
+// moving populations gain w_i rho eqs, the rest population loses their sum,
+// (1 - w_0) rho eqs.
+__device__ __forceinline__ double eq_adjust(int i, double rho, double eqs)
 {
-    const double eu = kEX[i] * ux + kEY[i] * uy;
-    const double usq = ux * ux + uy * uy;
-    return wt64(i) * ((rho - 1.0) + rho * (3.0 * eu + 4.5 * eu * eu - 1.5 * usq));
+    return i == 0 ? -(1.0 - wt64(0)) * rho * eqs : wt64(i) * rho * eqs;
 }
-__device__ __forceinline__ double feq(int i, double rho, double ux, double uy)
+__device__ __forceinline__ double dfeq(int i, double rho, double ux, double uy, double eqs)
 {
     const double eu = kEX[i] * ux + kEY[i] * uy;
     const double usq = ux * ux + uy * uy;
-    return wt64(i) * rho * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * usq);
+    return wt64(i) * ((rho - 1.0) + rho * (3.0 * eu + 4.5 * eu * eu - 1.5 * usq)) + eq_adjust(i, rho, eqs);
+}
+__device__ __forceinline__ double feq(int i, double rho, double ux, double uy, double eqs)
+{
+    const double eu = kEX[i] * ux + kEY[i] * uy;
+    const double usq = ux * ux + uy * uy;
+    return wt64(i) * rho * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * usq) + eq_adjust(i, rho, eqs);
 }
 
 template <class T, bool SHIFT> __device__ __forceinline__ T store_f64(double f, int i)
@@ -233,7 +240,7 @@ __device__ __forceinline__ RowIdx row_idx(const Geom& g, int w)
 // f_i(x, 0) = feq_i(x).
 template <class T, bool SHIFT>
 __global__ void init_kernel(T* __restrict__ s, Geom g, const double* __restrict__ rho, const double* __restrict__ ux,
-                            const double* __restrict__ uy)
+                            const double* __restrict__ uy, double eqs)
 {
     const RowIdx ri = row_idx(g, g.nx + 4);
     if (!ri.ok) return;
@@ -242,8 +249,8 @@ __global__ void init_kernel(T* __restrict__ s, Geom g, const double* __restrict_
     const long long q = (long long)sy * g.nx + sx;
     const double r = rho ? rho[q] : 1.0, vx = ux ? ux[q] : 0.0, vy = uy ? uy[q] : 0.0;
     T v;
-    if constexpr (SHIFT) v = (T)dfeq(i, r, vx, vy);
-    else v = (T)feq(i, r, vx, vy);
+    if constexpr (SHIFT) v = (T)dfeq(i, r, vx, vy, eqs);
+    else v = (T)feq(i, r, vx, vy, eqs);
     s[i * g.ps + (long long)y * g.rs + g.off + xx] = v;
 }
 
@@ -456,10 +463,10 @@ static dim3 plane_rows_grid(const Geom& g, int extra)
     }
 
 hipError_t launch_init(int dtype, void* s, const Geom& g, const double* rho, const double* ux, const double* uy,
-                       hipStream_t st)
+                       double eqs, hipStream_t st)
 {
     LBM_DISPATCH(dtype, {
-        hipLaunchKernelGGL((init_kernel<T, S>), plane_rows_grid(g, 4), dim3(256), 0, st, (T*)s, g, rho, ux, uy);
+        hipLaunchKernelGGL((init_kernel<T, S>), plane_rows_grid(g, 4), dim3(256), 0, st, (T*)s, g, rho, ux, uy, eqs);
         return hipGetLastError();
     })
 }

@@ -282,7 +282,7 @@ int lbm_pool_add(lbm_pool* P, int nx, int ny, double tau, double c2)
     S.tau = tau;
     S.c2 = c2;
     S.g = g;
-    S.coef = make_coef(tau, c2);
+    S.coef = make_coef(tau, c2, LBM_MODEL_FORCING);
     S.bytes = bytes;
     const size_t fb = footprint(g, P->esize);
     hipError_t e = hipMalloc(&S.buf, fb);
@@ -331,7 +331,7 @@ int lbm_pool_init(lbm_pool* P, int slot, const double* rho, const double* ux, co
         e = hipMemcpyAsync(d.p + c * n, src[c], n * sizeof(double), hipMemcpyHostToDevice, P->stream);
         dp[c] = d.p + c * n;
     }
-    if (e == hipSuccess) e = launch_init(P->dtype, S->b0, S->g, dp[0], dp[1], dp[2], P->stream);
+    if (e == hipSuccess) e = launch_init(P->dtype, S->b0, S->g, dp[0], dp[1], dp[2], 0.0, P->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(P->stream);
     if (e != hipSuccess) return status_of(e);
     S->t = 0;
@@ -343,7 +343,7 @@ int lbm_pool_init_device(lbm_pool* P, int slot, const double* rho, const double*
 {
     Slot* S = slot_of(P, slot);
     if (!S) return LBM_EINVAL;
-    hipError_t e = launch_init(P->dtype, S->b0, S->g, rho, ux, uy, P->stream);
+    hipError_t e = launch_init(P->dtype, S->b0, S->g, rho, ux, uy, 0.0, P->stream);
     if (e != hipSuccess) return status_of(e);
     S->t = 0;
     S->ready = true;

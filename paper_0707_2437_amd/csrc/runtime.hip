@@ -15,6 +15,7 @@ using namespace lbm;
 struct lbm_lattice {
     int nx, ny, dtype, esize, device;
     double tau, c2;
+    int model;         // lbm_model
     Geom g;
     Coef coef;
     size_t buf_bytes;
@@ -132,7 +133,8 @@ lbm_lattice* lbm_create(int nx, int ny, double tau, double c2, int dtype)
     L->tau = tau;
     L->c2 = c2;
     L->g = make_geom(nx, ny, L->esize, choose_interleaved(nx, ny, dtype));
-    L->coef = make_coef(tau, c2);
+    L->model = LBM_MODEL_FORCING;
+    L->coef = make_coef(tau, c2, L->model);
     const TileDefault td = default_tile(dtype);
     L->vx = td.vx;
     L->nw = td.nw;
@@ -242,10 +244,18 @@ int lbm_get_tile(const lbm_lattice* L, int* vx, int* nw, int* h, int* flags)
 int lbm_init_device(lbm_lattice* L, const double* rho, const double* ux, const double* uy)
 {
     if (!L) return LBM_EINVAL;
-    hipError_t e = launch_init(L->dtype, L->cur, L->g, rho, ux, uy, L->stream);
+    hipError_t e = launch_init(L->dtype, L->cur, L->g, rho, ux, uy, eq_shift(L->c2, L->model), L->stream);
     if (e != hipSuccess) return status_of(e);
     L->t = 0;
     L->ready = true;
+    return LBM_OK;
+}
+
+int lbm_set_model(lbm_lattice* L, int model)
+{
+    if (!L || !model_ok(model, L->c2)) return LBM_EINVAL;
+    L->model = model;
+    L->coef = make_coef(L->tau, L->c2, model);
     return LBM_OK;
 }
 

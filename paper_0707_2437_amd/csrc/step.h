@@ -300,13 +300,14 @@ template <class T, bool SHIFT, class C, int VX> __device__ __forceinline__ C drh
 }
 
 template <class C> struct CoefC {
-    C om1, wo0, wo1, wo2, as1, as2;
+    C om1, wo0, wo1, wo2, as1, as2, e1, e0;
 };
 
 template <class C> __device__ __forceinline__ CoefC<C> coef_c(const Coef& k)
 {
-    if constexpr (sizeof(C) == sizeof(float)) return CoefC<C>{k.om1f, k.wo0f, k.wo1f, k.wo2f, k.as1f, k.as2f};
-    else return CoefC<C>{k.om1, k.wo0, k.wo1, k.wo2, k.as1, k.as2};
+    if constexpr (sizeof(C) == sizeof(float))
+        return CoefC<C>{k.om1f, k.wo0f, k.wo1f, k.wo2f, k.as1f, k.as2f, k.e1f, k.e0f};
+    else return CoefC<C>{k.om1, k.wo0, k.wo1, k.wo2, k.as1, k.as2, k.e1, k.e0};
 }
 
 // Eq. 5 right-hand side in delta form for one site.
@@ -319,6 +320,8 @@ template <class C> __device__ __forceinline__ CoefC<C> coef_c(const Coef& k)
 // For a link pair (i, opp) with e_opp = -e_i, write A = drho - 3/2 rho u.u,
 // sym = A + 9/2 rho (e.u)^2, P = om w sym, Q = om w 3 rho (e.u) + as (e.D):
 //   d*_i = (1 - om) d_i + P + Q,  d*_opp = (1 - om) d_opp + P - Q.
+// The altered-equilibrium model (as = 0) uses A + rho e1 in sym and
+// A + rho e0 for the rest population (Coef).
 template <class V, class C>
 __device__ __forceinline__ void collide_col(const V& v, C drho, C gx, C gy, const CoefC<C>& k, C o[9])
 {
@@ -329,10 +332,13 @@ __device__ __forceinline__ void collide_col(const V& v, C drho, C gx, C gy, cons
     const C ux = jx * ir, uy = jy * ir;
     const C usq = fmac(ux, ux, uy * uy);
     const C A = fmac(C(-1.5) * rho, usq, drho);
+    // equilibrium shifts of the altered-equilibrium model (exactly A when
+    // e1 = e0 = 0, the paper's model)
+    const C Ap = fmac(rho, k.e1, A), A0 = fmac(rho, k.e0, A);
     const C r45 = C(4.5) * rho, r3 = C(3) * rho;
-    o[0] = v.fma(k.om1, 0, k.wo0 * A);
+    o[0] = v.fma(k.om1, 0, k.wo0 * A0);
     auto pair = [&](int i, int io, C eu, C eg, C wo, C as) {
-        const C P = wo * fmac(r45, eu * eu, A);
+        const C P = wo * fmac(r45, eu * eu, Ap);
         const C Q = fmac(as, eg, wo * (r3 * eu));
         o[i] = v.fma(k.om1, i, P + Q);
         o[io] = v.fma(k.om1, io, P - Q);

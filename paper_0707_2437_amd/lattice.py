@@ -16,6 +16,9 @@ DTYPE_NAMES = {v: k for k, v in DTYPES.items()}
 
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENONFINITE = 0, -1, -2, -3, -4, -5
 
+# lbm_model: the paper's forcing model (Eq. 5) or the altered-equilibrium one
+MODEL_FORCING, MODEL_EQUILIBRIUM = 0, 1
+
 
 class LBMError(RuntimeError):
     def __init__(self, status, what):
@@ -65,7 +68,7 @@ def _dptr(t, n):
 class Lattice:
     """A periodic nx x ny lattice of the variable-speed-of-sound model on the GPU."""
 
-    def __init__(self, nx, ny, tau, c2, dtype="f64"):
+    def __init__(self, nx, ny, tau, c2, dtype="f64", model=MODEL_FORCING):
         self.nx, self.ny, self.tau, self.c2 = int(nx), int(ny), float(tau), float(c2)
         self.dtype = _dtype_code(dtype)
         self._L = lib()
@@ -74,6 +77,13 @@ class Lattice:
             raise LBMError(self._L.lbm_last_error(), "lbm_create")
         self._h = ctypes.c_void_p(h)
         self._stream_ref = None
+        if model != MODEL_FORCING:
+            self.set_model(model)
+
+    def set_model(self, model):
+        """lbm_set_model: MODEL_FORCING (Eq. 5) or MODEL_EQUILIBRIUM; before init."""
+        _check(self._L.lbm_set_model(self._h, int(model)), "lbm_set_model")
+        return self
 
     # lifetime --------------------------------------------------------------
     def close(self):

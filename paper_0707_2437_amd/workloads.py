@@ -11,6 +11,8 @@ import numpy as np
 # c^2 sweep of the plain-kernel workload: c_e = 0.2 ... 0.9 (the paper's
 # waves (1) and (2) are the end points, Sec. 4).
 C2_SWEEP = (0.04, 0.2, 1.0 / 3.0, 0.5, 0.81)
+# the altered-equilibrium model needs c^2 < 3/5 (positive rest population)
+C2_SWEEP_EQ = (0.04, 0.2, 1.0 / 3.0, 0.5, 0.56)
 
 
 def grid(nx, ny):

@@ -60,7 +60,8 @@ def evolve_fields(amp_rho, kx, ky, nx, ny, tau, c2, t, amp_u=(0.0, 0.0), model=0
 
 
 def acoustic_eigs(kx, ky, tau, c2, model=0):
-    """The two eigenvalues of M(k) of largest modulus (the sound modes)."""
+    """The three eigenvalues of M(k) of largest modulus: the two sound modes
+    and the shear mode (which of them decays slowest depends on c2)."""
     lam = np.linalg.eigvals(matrix(kx, ky, tau, c2, model))
     order = np.argsort(-np.abs(lam))
     return lam[order[:3]]

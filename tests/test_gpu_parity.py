@@ -168,3 +168,45 @@ def test_shifted_storage_error_bounded(dtype, tol):
     err = max_rel_err(f, fr)
     print(f"C1 c2=0.2 {dtype}: max rel err f = {err:.3e}")
     assert err <= tol
+
+
+# ---------------------------------------------------------------------------
+# The altered-equilibrium model (lbm_set_model): the same kernels with the
+# equilibrium shift in the coefficients and no source term.
+def run_gpu_model(nx, ny, tau, c2, dtype, steps, fields, tile=None):
+    with lbm.Lattice(nx, ny, tau, c2, dtype, model=lbm.MODEL_EQUILIBRIUM) as L:
+        if tile:
+            L.set_tile(*tile)
+        L.init(*fields)
+        L.step(steps)
+        return L.get_f(), L.moments()
+
+
+@pytest.mark.parametrize("c2", [0.2, 0.45])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_equilibrium_model_c1_parity_1000_steps(c2, dtype):
+    fields = (c1_rho(), None, None)
+    f, (rho, ux, uy, tot) = run_gpu_model(64, 64, 0.8, c2, dtype, 1000, fields)
+    o = oracle.Oracle(64, 64, 0.8, c2, model=oracle.MODEL_EQUILIBRIUM).init(*fields).step(1000)
+    err = max_rel_err(f, o.get_f())
+    print(f"equilibrium model C1 c2={c2} {dtype}: max rel err f = {err:.3e}")
+    assert err <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "f32s", "f16s"])
+def test_equilibrium_model_tiles_and_edges(dtype):
+    """Ragged shapes, every tile shape bitwise the same, and the oracle."""
+    for nx, ny in [(397, 131), (5, 7), (130, 9)]:
+        fields = smooth_random_state(nx, ny, seed=nx + 3 * ny)
+        outs = [run_gpu_model(nx, ny, 0.7, 0.3, dtype, 30, fields, tile=t)[0] for t in EDGE_TILES]
+        for t, o in zip(EDGE_TILES[1:], outs[1:]):
+            assert np.array_equal(o, outs[0]), (nx, ny, t)
+        fr = oracle.Oracle(nx, ny, 0.7, 0.3, model=oracle.MODEL_EQUILIBRIUM).init(*fields).step(30).get_f()
+        assert max_rel_err(outs[0], fr) <= TILE_TOL[dtype], (nx, ny)
+
+
+def test_equilibrium_model_rejects_c2_from_three_fifths():
+    with lbm.Lattice(16, 16, 0.7, 0.6, "f32") as L:
+        with pytest.raises(lbm.LBMError) as ei:
+            L.set_model(lbm.MODEL_EQUILIBRIUM)
+        assert ei.value.status == lbm.EINVAL

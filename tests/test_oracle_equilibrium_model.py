@@ -13,6 +13,10 @@ code:
 - a progressive wave moves at c;
 - shear waves decay with nu = (2 tau - 1)/6 (the change touches only the
   isotropic part of the momentum flux);
+- sound decays at 1.5 (1 - c^2) nu k^2: the first-order stress keeps the
+  c-independent third moment of Eq. 2, so its trace part no longer cancels
+  and the effective longitudinal viscosity is 3 (1 - c^2) nu (nu k^2 at
+  c^2 = 1/3, as for the paper's model at every c);
 - mass and momentum are conserved and the rest state stays at rest;
 - c^2 >= 3/5 is rejected (the rest population would not be positive).
 """
@@ -109,6 +113,35 @@ def test_shear_viscosity_unchanged(c2):
     o.step(t)
     nu_meas = -np.log(abs(fourier(o.moments()[1], k, 0)) / a0) / (k * k * t)
     assert abs(nu_meas / ((2 * tau - 1) / 6) - 1) < 1e-3
+
+
+@pytest.mark.parametrize("c2", [0.1, 0.25, 0.5])
+def test_sound_decay_closed_form(c2):
+    """Acoustic energy c^2 |rho_k|^2 + |u_k|^2 of a progressive wave decays as
+    exp(-2 Gamma T), Gamma = 1.5 (1 - c^2) nu k^2 (Chapman-Enskog closed
+    form; the energy is insensitive to the weak counter-running wave the
+    equilibrium start excites). Also checked against the linear theory."""
+    L, ny, eps, tau, T = 128, 3, 1e-6, 0.8, 2000
+    nu = (2 * tau - 1) / 6
+    k = 2 * np.pi / L
+    c = np.sqrt(c2)
+    x = np.arange(L)[None, :] * np.ones((ny, 1))
+    s = np.sin(k * x)
+    o = oracle.Oracle(L, ny, tau, c2, model=oracle.MODEL_EQUILIBRIUM).init(rho=1 + eps * s, ux=c * eps * s)
+
+    def energy():
+        rho, ux, _, _ = o.moments()
+        return c2 * abs(fourier(rho - 1, k, 1)) ** 2 + abs(fourier(ux, k, 1)) ** 2
+
+    e0 = energy()
+    o.step(T)
+    gamma = -np.log(energy() / e0) / (2 * k * k * T)
+    assert abs(gamma / (1.5 * (1 - c2) * nu) - 1) < 2e-3
+    kl = 2 * np.pi / 512
+    lam = lt.acoustic_eigs(kl, 0.0, tau, c2, model=1)
+    lam = lam[np.abs(np.angle(lam)) > 0.5 * c * kl]  # the sound pair
+    assert len(lam) == 2
+    assert np.allclose(-np.log(np.abs(lam)) / (kl * kl), 1.5 * (1 - c2) * nu, rtol=1e-3)
 
 
 def test_conservation_and_rest_state():
