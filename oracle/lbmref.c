@@ -23,6 +23,7 @@ struct lbmref {
     double alpha;   /* forcing amplitude, Eq. 5; alpha = 1/3 - c_e^2       */
     double c2;      /* c_e^2 as requested                                  */
     int model;      /* enum lbmref_model                                   */
+    double* A;      /* alpha(x) of a c2 field, [ny][nx]; NULL: uniform     */
     long long t;    /* completed steps                                     */
     int ready;      /* set by init / set_f                                 */
     double* f;      /* f_i(x, t), [9][ny][nx]                              */
@@ -123,7 +124,7 @@ int lbmref_set_model(lbmref* L, int model)
         L->model = model;
         return LBMREF_OK;
     }
-    if (model == LBMREF_MODEL_EQUILIBRIUM && L->c2 < 0.6) {
+    if (model == LBMREF_MODEL_EQUILIBRIUM && L->c2 < 0.6 && !L->A) {
         L->model = model;
         return LBMREF_OK;
     }
@@ -181,7 +182,28 @@ void lbmref_destroy(lbmref* L)
     free(L->R);
     free(L->UX);
     free(L->UY);
+    free(L->A);
     free(L);
+}
+
+int lbmref_set_c2_field(lbmref* L, const double* c2)
+{
+    if (!L || L->model != LBMREF_MODEL_FORCING) return LBMREF_EINVAL;
+    size_t n = (size_t)L->nx * L->ny;
+    if (!c2) {
+        free(L->A);
+        L->A = NULL;
+        return LBMREF_OK;
+    }
+    for (size_t s = 0; s < n; ++s)
+        if (!isfinite(c2[s]) || !(c2[s] > 0.0)) return LBMREF_EINVAL;
+    if (!L->A) {
+        L->A = (double*)malloc(n * sizeof(double));
+        if (!L->A) return LBMREF_ENOMEM;
+    }
+    /* Eq. 8 at every site */
+    for (size_t s = 0; s < n; ++s) L->A[s] = lbmref_alpha(c2[s]);
+    return LBMREF_OK;
 }
 
 int lbmref_init(lbmref* L, const double* rho, const double* ux, const double* uy)
@@ -245,8 +267,10 @@ static void step_once(lbmref* L)
                          L->R[(size_t)wrap(y - 1, ny) * nx + x]) / 2.0;
             double feq[9], src[9];
             model_equilibrium(L, L->R[s], L->UX[s], L->UY[s], feq);
-            /* the equilibrium model has no source term */
-            lbmref_source(L->model == LBMREF_MODEL_EQUILIBRIUM ? 0.0 : L->alpha, gx, gy, src);
+            /* alpha at this site (a c2 field), else the lattice's;
+             * the equilibrium model has no source term */
+            double alpha = L->A ? L->A[s] : L->alpha;
+            lbmref_source(L->model == LBMREF_MODEL_EQUILIBRIUM ? 0.0 : alpha, gx, gy, src);
             for (int i = 0; i < 9; ++i) {
                 /* Right-hand side of Eq. 5 added to f_i(x, t) ... */
                 double fi = L->f[i * n + s];

@@ -72,9 +72,21 @@ int lbmref_last_error(void);
 void lbmref_destroy(lbmref* L);
 
 /* Select the model (enum lbmref_model) before init; LBMREF_EINVAL for an
- * unknown model, or for the equilibrium model with c2 >= 3/5 (its rest
- * population feq[0] = rho (1 - 5 c^2 / 3) would not be positive). */
+ * unknown model, for the equilibrium model with c2 >= 3/5 (its rest
+ * population feq[0] = rho (1 - 5 c^2 / 3) would not be positive), or for the
+ * equilibrium model on a lattice with a c2 field. */
 int lbmref_set_model(lbmref* L, int model);
+
+/* A speed of sound that varies in space (the paper's outlook, Sec. 5: alpha
+ * need not be constant; e.g. an acoustic lens or a temperature gradient).
+ * c2 has nx*ny entries, c2[y*nx + x] = c_e^2 at that site; the source term
+ * of Eq. 5 at x then uses alpha(x) = 1/3 - c2[x] (Eq. 8 site by site), and
+ * the gradient stays the central difference of rho. NULL restores the
+ * lattice's uniform c2. May be called between steps (alpha varying in
+ * time). LBMREF_EINVAL for a non-finite or non-positive entry, or for a
+ * lattice on the equilibrium model (the field is a forcing-model feature);
+ * the lattice keeps its previous field then. */
+int lbmref_set_c2_field(lbmref* L, const double* c2);
 
 /* f_i(x, 0) = feq_i(rho(x), u(x)) of the lattice's model. NULL rho means rho = 1, NULL ux / uy
  * mean 0. Arrays have nx*ny entries. Sets t = 0. */

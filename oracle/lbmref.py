@@ -45,6 +45,8 @@ def load(path=None):
     lib.lbmref_set_model.argtypes = [ctypes.c_void_p, ctypes.c_int]
     lib.lbmref_set_model.restype = ctypes.c_int
     lib.lbmref_source.restype = None
+    lib.lbmref_set_c2_field.argtypes = [ctypes.c_void_p, _dp]
+    lib.lbmref_set_c2_field.restype = ctypes.c_int
     lib.lbmref_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double]
     lib.lbmref_create.restype = ctypes.c_void_p
     lib.lbmref_last_error.argtypes = []
@@ -152,6 +154,12 @@ class Oracle:
         if a.shape != (self.ny, self.nx):
             a = np.ascontiguousarray(np.broadcast_to(a, (self.ny, self.nx)))
         return a
+
+    def set_c2_field(self, c2):
+        """Per-site c_e^2 (shape (ny, nx), broadcast if smaller); None: uniform again."""
+        c2 = self._field(c2)
+        self._check(self.lib.lbmref_set_c2_field(self._h, _ptr(c2)), "set_c2_field")
+        return self
 
     def init(self, rho=None, ux=None, uy=None):
         rho, ux, uy = self._field(rho), self._field(ux), self._field(uy)

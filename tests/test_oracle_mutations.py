@@ -22,7 +22,7 @@ MUTANTS = {
     "alpha_sign": ("return 1.0 / 3.0 - c2;", "return c2 - 1.0 / 3.0;"),
     "forward_difference_x": ("L->R[(size_t)y * nx + wrap(x - 1, nx)]) / 2.0", "L->R[s]) / 1.0"),
     "missing_half_y": ("L->R[(size_t)wrap(y - 1, ny) * nx + x]) / 2.0", "L->R[(size_t)wrap(y - 1, ny) * nx + x]) / 1.0"),
-    "swapped_gradient": ("0.0 : L->alpha, gx, gy, src)", "0.0 : L->alpha, gy, gx, src)"),
+    "swapped_gradient": ("0.0 : alpha, gx, gy, src)", "0.0 : alpha, gy, gx, src)"),
     "y_gradient_wrong_column": ("L->R[(size_t)wrap(y + 1, ny) * nx + x]", "L->R[(size_t)wrap(y + 1, ny) * nx + wrap(x + 1, nx)]"),
     "stream_backwards_x": ("int xd = wrap(x + e[2 * i], nx);", "int xd = wrap(x - e[2 * i], nx);"),
     "stream_transposed": ("int yd = wrap(y + e[2 * i + 1], ny);", "int yd = wrap(y + e[2 * i], ny);"),
@@ -34,12 +34,18 @@ MUTANTS = {
     # the altered-equilibrium model
     "c2_rest_share": ("feq[0] = rho - moving;", "feq[0] = w[0] * rho;"),
     "c2_ignored": ("w[i] * rho * (3.0 * c2 + 3.0 * eu", "w[i] * rho * (1.0 + 3.0 * eu"),
-    "c2_model_keeps_source": ("L->model == LBMREF_MODEL_EQUILIBRIUM ? 0.0 : L->alpha", "L->alpha"),
+    "c2_model_keeps_source": ("L->model == LBMREF_MODEL_EQUILIBRIUM ? 0.0 : alpha", "alpha"),
+    # a c2 field (alpha varying in space)
+    "c2_field_ignored": ("double alpha = L->A ? L->A[s] : L->alpha;", "double alpha = L->alpha;"),
+    "c2_field_transposed": ("L->A ? L->A[s]", "L->A ? L->A[(size_t)x * ny + y]"),
+    "c2_field_neighbour": ("L->A ? L->A[s]", "L->A ? L->A[(size_t)y * nx + wrap(x + 1, nx)]"),
+    "c2_field_sign": ("L->A[s] = lbmref_alpha(c2[s]);", "L->A[s] = c2[s] - 1.0 / 3.0;"),
 }
 
 FAST_PINS = [os.path.join(ROOT, "tests", "test_oracle_pins.py"),
              os.path.join(ROOT, "tests", "test_oracle_physics.py"),
-             os.path.join(ROOT, "tests", "test_oracle_equilibrium_model.py")]
+             os.path.join(ROOT, "tests", "test_oracle_equilibrium_model.py"),
+             os.path.join(ROOT, "tests", "test_oracle_c2_field.py")]
 
 
 def run_pins_against(source_text, tmp_path):

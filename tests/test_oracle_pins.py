@@ -94,8 +94,10 @@ def test_standard_case_has_zero_forcing():
 # ---------------------------------------------------------------- P4 ----
 def brute_step(f, nx, ny, tau, c2):
     """One step of Eq. 5 in exact rationals, written in pull form:
-    f_i(x, t+1) = f*_i(x - e_i, t), f* = f - (f - feq)/tau + 3 w alpha grad(rho).e."""
-    alpha = Fr(1, 3) - c2
+    f_i(x, t+1) = f*_i(x - e_i, t), f* = f - (f - feq)/tau + 3 w alpha grad(rho).e.
+    c2 is one number, or a per-site grid c2[y][x] (alpha(x) = 1/3 - c2[y][x])."""
+    def alpha_at(y, x):
+        return Fr(1, 3) - (c2[y][x] if isinstance(c2, list) else c2)
     rho = [[sum(f[i][y][x] for i in range(9)) for x in range(nx)] for y in range(ny)]
     jx = [[sum(f[i][y][x] * E_PAPER[i][0] for i in range(9)) for x in range(nx)] for y in range(ny)]
     jy = [[sum(f[i][y][x] * E_PAPER[i][1] for i in range(9)) for x in range(nx)] for y in range(ny)]
@@ -109,7 +111,7 @@ def brute_step(f, nx, ny, tau, c2):
             for i, (ex, ey) in enumerate(E_PAPER):
                 eu = ex * ux + ey * uy
                 feq = W_PAPER[i] * r * (1 + 3 * eu + Fr(9, 2) * eu * eu - Fr(3, 2) * (ux * ux + uy * uy))
-                src = 3 * W_PAPER[i] * alpha * (ex * gx + ey * gy)
+                src = 3 * W_PAPER[i] * alpha_at(y, x) * (ex * gx + ey * gy)
                 fstar[i][y][x] = f[i][y][x] - (f[i][y][x] - feq) / tau + src
     return [[[fstar[i][(y - E_PAPER[i][1]) % ny][(x - E_PAPER[i][0]) % nx] for x in range(nx)]
              for y in range(ny)] for i in range(9)]
