@@ -31,6 +31,7 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "step_f32_4096_traffic.json")
 BYTES_PER_SITE = {"f64": 144, "f32": 72, "f32s": 72, "f16s": 36}  # 9 reads + 9 writes
+FIELD_BYTES = {"f64": 8, "f32": 4, "f32s": 4, "f16s": 4}  # one read of a c^2 field's coefficient
 
 
 def parse():
@@ -39,9 +40,9 @@ def parse():
     p.add_argument("--steps", type=int, default=1000)
     p.add_argument("--warmup", type=int, default=20)
     p.add_argument("--n", type=int, default=4096, help="lattice side")
-    p.add_argument("--forms", default="f64,f32_eq",
+    p.add_argument("--forms", default="f64,f32_eq,f32_field",
                    help="extra forms to time, comma separated ('' for none); a '_eq' suffix selects the "
-                        "altered-equilibrium model over its own c^2 sweep")
+                        "altered-equilibrium model over its own c^2 sweep, '_field' a c^2 field per lattice")
     p.add_argument("--form-steps", type=int, default=300)
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     p.add_argument("--cpu-steps", type=int, default=200)
@@ -61,15 +62,32 @@ def parse():
     return p.parse_args()
 
 
-def make_sweep(lbm, workloads, torch, n, dtype, stream):
-    # "<dtype>_eq": the altered-equilibrium model over its own c^2 sweep
+def form_parts(form):
+    """'<dtype>[_eq|_field]' -> (dtype, variant)."""
+    for v in ("_eq", "_field"):
+        if form.endswith(v):
+            return form[:-len(v)], v[1:]
+    return form, ""
+
+
+def form_bytes_per_site(form):
+    dtype, variant = form_parts(form)
+    return BYTES_PER_SITE[dtype] + (FIELD_BYTES[dtype] if variant == "field" else 0)
+
+
+def make_sweep(lbm, workloads, torch, n, form, stream):
+    # "<dtype>_eq": the altered-equilibrium model over its own c^2 sweep;
+    # "<dtype>_field": each lattice of the sweep with a lens-shaped c^2 field
+    dtype, variant = form_parts(form)
     model, sweep = lbm.MODEL_FORCING, workloads.C2_SWEEP
-    if dtype.endswith("_eq"):
-        dtype, model, sweep = dtype[:-3], lbm.MODEL_EQUILIBRIUM, workloads.C2_SWEEP_EQ
+    if variant == "eq":
+        model, sweep = lbm.MODEL_EQUILIBRIUM, workloads.C2_SWEEP_EQ
     lattices = []
     for k, c2 in enumerate(sweep):
         rho, ux, uy = workloads.plane_wave_fields(n, n, c2, seed=k)
         L = lbm.Lattice(n, n, 0.6, c2, dtype, model=model)
+        if variant == "field":
+            L.set_c2_field(workloads.lens_c2_field(n, n, c2, depth=0.5))
         L.set_stream(stream)
         L.init(rho, ux, uy)
         lattices.append(L)
@@ -94,12 +112,13 @@ def time_sweep(torch, lattices, steps, warmup, stream):
     return e0.elapsed_time(e1) / 1e3, wall
 
 
-def kernel_name(tile, dtype):
+def kernel_name(tile, form):
     vx, nw, h, flags = tile
-    dtype = dtype.removesuffix("_eq")
+    dtype, variant = form_parts(form)
     t = {"f64": "double,false", "f32": "float,false", "f32s": "float,true", "f16s": "_Float16,true"}[dtype]
     if flags & 16:
-        return f"lbm::step_vstack_kernel<{t},{vx},{nw},{'true' if flags & 2 else 'false'}>"
+        return (f"lbm::step_vstack_kernel<{t},{vx},{nw},{'true' if flags & 2 else 'false'},"
+                f"{'true' if variant == 'field' else 'false'}>")
     pf = 2 if flags & 8 else (flags & 1)
     return f"lbm::step_kernel<{t},{vx},{nw},{pf},{'true' if flags & 2 else 'false'}> (h={h})"
 
@@ -130,7 +149,7 @@ def measure_form(lbm, workloads, torch, n, dtype, steps, warmup):
     sites = n * n * len(lats)
     launches = steps * len(lats)
     mlups = sites * steps / sec / 1e6
-    gbs = BYTES_PER_SITE[dtype.removesuffix("_eq")] * n * n / (sec / launches) / 1e9
+    gbs = form_bytes_per_site(dtype) * n * n / (sec / launches) / 1e9
     return {"mlups": mlups, "ms_per_step": 1e3 * sec / steps, "kernel_us": 1e6 * sec / launches,
             "achieved_GBs": gbs, "frac": gbs / PEAK_HBM_GBS, "wall_s": wall,
             "mass_total_first": tot[0][0], "kernel": kernel_name(tile, dtype), "tile": list(tile)}
@@ -239,7 +258,7 @@ def measure_precision(lbm, workloads, torch, steps, warmup=5, n=8192):
         tile = L.get_tile()
         L.close()
         mlups = n * n * steps / sec / 1e6
-        gbs = BYTES_PER_SITE[dtype.removesuffix("_eq")] * n * n * steps / sec / 1e9
+        gbs = form_bytes_per_site(dtype) * n * n * steps / sec / 1e9
         out[dtype] = {"mlups": mlups, "achieved_GBs": gbs, "frac": gbs / PEAK_HBM_GBS, "steps": steps,
                       "kernel": kernel_name(tile, dtype), "lattice": [n, n]}
     return out

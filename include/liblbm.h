@@ -93,9 +93,37 @@ enum lbm_model { LBM_MODEL_FORCING = 0, LBM_MODEL_EQUILIBRIUM = 1 };
 /* Select the model for the following lbm_init / lbm_step calls (lbm_init
  * sets f to that model's equilibrium). LBM_EINVAL for a NULL handle, an
  * unknown model, or LBM_MODEL_EQUILIBRIUM with c2 >= 3/5 (its rest
- * population rho (1 - 5 c2 / 3) would not be positive). Pools step the
+ * population rho (1 - 5 c2 / 3) would not be positive), or for any model
+ * but LBM_MODEL_FORCING while the lattice has a c2 field. Pools step the
  * forcing model. */
 int lbm_set_model(lbm_lattice* L, int model);
+
+/* A speed of sound that varies in space, the extension the paper's
+ * conclusion (Sec. 5) proposes: alpha need not be constant, e.g. to model
+ * an acoustic lens or a temperature gradient. c2 is a HOST FP64 array of
+ * nx * ny entries, c2[y * nx + x] = c_e^2 at site (x, y); the source term of
+ * Eq. 5 at that site then uses alpha(x) = 1/3 - c2[y * nx + x] (Eq. 8 site
+ * by site), the gradient is unchanged. The lattice's own c2 (lbm_create) is
+ * no longer used by the step. NULL removes the field (the uniform c2
+ * applies again) and frees its memory. The field can be replaced between
+ * steps (alpha varying in time). Synchronous.
+ * The field is held in device memory in the compute precision (FP64 for
+ * LBM_F64, else FP32): ny * ceil(nx / 256) * 256 * 4 or 8 bytes beyond
+ * lbm_footprint_bytes, allocated by the first call; each step reads it
+ * once (76 B per site in place of 72 for LBM_F32).
+ * A lattice with a field steps with the vertical-stack kernels: a
+ * march-form tile (no LBM_TILE_VSTACK) is replaced by the dtype's default
+ * tile, and lbm_set_tile refuses one while the field exists.
+ * LBM_EINVAL for a NULL handle, an entry that is not finite or not > 0 (the
+ * field is then unchanged), or a lattice on LBM_MODEL_EQUILIBRIUM;
+ * LBM_ENOMEM if the field cannot be allocated. */
+int lbm_set_c2_field(lbm_lattice* L, const double* c2);
+
+/* As lbm_set_c2_field with a DEVICE FP64 array (same layout) on the
+ * lattice's device: asynchronous on the lattice's stream, for fields that
+ * change every few steps. The entries are not checked: they must be finite
+ * and > 0. NULL removes the field (synchronises the stream). */
+int lbm_set_c2_field_device(lbm_lattice* L, const double* c2);
 
 /* As lbm_init, but rho / ux / uy are DEVICE pointers (same layout) on the
  * lattice's device; asynchronous on the lattice's stream. */
@@ -150,8 +178,10 @@ size_t lbm_footprint_bytes(int nx, int ny, int dtype);
  * rows. Vertical-stack form (LBM_TILE_VSTACK): nw = 4, 8 or 16 waves per
  * workgroup covering one strip and nw - 2 rows (h is ignored). Default:
  * vertical stack with non-temporal stores; vx = 2 and nw = 8 for LBM_F64,
- * LBM_F32 and LBM_F32S, vx = 4 and nw = 16 for LBM_F16S. Results do not
- * depend on the shape (bitwise). LBM_EINVAL for an unsupported shape.
+ * LBM_F32 and LBM_F32S, vx = 4 and nw = 8 for LBM_F16S. Results do not
+ * depend on the shape (bitwise). LBM_EINVAL for an unsupported shape, or
+ * for a march-form shape (no LBM_TILE_VSTACK) while the lattice has a c2
+ * field.
  * lbm_get_tile: any pointer may be NULL. */
 enum lbm_tile_flags {
     LBM_TILE_PREFETCH = 1, /* issue the next row's loads before relaxing the current row */

@@ -30,6 +30,8 @@ SIGNATURES = {
     "lbm_destroy": (None, [_vp]),
     "lbm_init": (_i, [_vp, _vp, _vp, _vp]),
     "lbm_set_model": (_i, [_vp, _i]),
+    "lbm_set_c2_field": (_i, [_vp, _vp]),
+    "lbm_set_c2_field_device": (_i, [_vp, _vp]),
     "lbm_init_device": (_i, [_vp, _vp, _vp, _vp]),
     "lbm_step": (_i, [_vp, _i]),
     "lbm_moments": (_i, [_vp, _vp, _vp, _vp, _vp]),

@@ -16,6 +16,7 @@ hipError_t launch_step(int dtype, int vx, int nw, int flags, const StepTile& t, 
 bool step_shape_supported(int dtype, int vx, int nw, int flags);
 hipError_t launch_init(int dtype, void* s, const Geom& g, const double* rho, const double* ux, const double* uy,
                        double eqs, hipStream_t st);
+hipError_t launch_field(int dtype, void* field, int nx, int ny, int fpitch, const double* c2, hipStream_t st);
 hipError_t launch_set_f(int dtype, void* s, const Geom& g, const double* f, hipStream_t st);
 hipError_t launch_get_f(int dtype, const void* s, const Geom& g, double* f, hipStream_t st);
 int moments_blocks(const Geom& g);
@@ -121,7 +122,7 @@ inline Coef make_coef(double tau, double c2, int model)
     // model has no source term and shifts the equilibrium instead: for
     // i != 0, feq_i - w_i gains w_i rho (3 c^2 - 1); feq_0 loses the sum of
     // those, (5/9) rho (3 c^2 - 1) = w_0 rho (5/4)(3 c^2 - 1).
-    const double om = 1.0 / tau, alpha = model == LBM_MODEL_EQUILIBRIUM ? 0.0 : 1.0 / 3.0 - c2;
+    const double om = 1.0 / tau;
     const double w0 = 4.0 / 9.0, w1 = 1.0 / 9.0, w2 = 1.0 / 36.0;
     const double sh = eq_shift(c2, model);
     Coef k;
@@ -129,8 +130,8 @@ inline Coef make_coef(double tau, double c2, int model)
     k.wo0 = om * w0;
     k.wo1 = om * w1;
     k.wo2 = om * w2;
-    k.as1 = 1.5 * w1 * alpha;
-    k.as2 = 1.5 * w2 * alpha;
+    k.as1 = model == LBM_MODEL_EQUILIBRIUM ? 0.0 : source_as1(c2);
+    k.as2 = 0.25 * k.as1;
     k.e1 = sh;
     k.e0 = -1.25 * sh;
     k.om1f = (float)k.om1;
@@ -143,6 +144,13 @@ inline Coef make_coef(double tau, double c2, int model)
     k.e0f = (float)k.e0;
     return k;
 }
+
+// A c2 field: row pitch (elements) and bytes of the per-site coefficient
+// array of a lattice (compute precision: FP64 for LBM_F64, else FP32). The
+// pitch covers every column a vertical-stack lane of up to 4 columns reads.
+inline int field_pitch(int nx) { return (nx + 255) / 256 * 256; }
+inline size_t field_esize(int dtype) { return dtype == LBM_F64 ? sizeof(double) : sizeof(float); }
+inline size_t field_bytes(int nx, int ny, int dtype) { return (size_t)ny * field_pitch(nx) * field_esize(dtype); }
 
 // Tiles per XCD chunk of the vertical-stack kernels (see xcd_tile): whole
 // row groups of a lattice, at least 16 tiles. LBM_XCD_CHUNK=<n> overrides

@@ -59,7 +59,22 @@ struct StepTile {
     int nchunks;  // row chunks
     int rowband;  // tile order: 1 = strip groups of a chunk first
     int xcd_chunk;  // vertical-stack tile order over the 8 XCDs (see xcd_tile in step.h)
+    // Per-site source coefficients (a c2 field): field[y * fpitch + x] =
+    // as1 at site (x, y) in compute precision (as2 = as1 / 4); nullptr for
+    // the uniform coefficients of c.
+    const void* field;
+    int fpitch;
 };
+
+// The source coefficient of the axis links, as1 = 3 w_1 alpha / 2 with
+// alpha = 1/3 - c2 (Eq. 8; the diagonal links take as2 = as1 / 4, exactly,
+// since w_2 = w_1 / 4). One definition for the uniform coefficients and the
+// per-site field, so that a uniform field gives the same bits.
+__host__ __device__ inline double source_as1(double c2)
+{
+    const double alpha = 1.0 / 3.0 - c2;
+    return 1.5 * (1.0 / 9.0) * alpha;
+}
 
 // One lattice of a batched launch (device array, read by every workgroup).
 // tile.src holds the buffer of even times and tile.dst the buffer of odd

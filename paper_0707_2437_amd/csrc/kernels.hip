@@ -165,7 +165,8 @@ __global__ __launch_bounds__(64 * NW) void step_kernel(StepTile a, int ntiles)
 // chunks (xcd_tile), so the set of rows being streamed at any time stays
 // one compact band. Each row is read (R + 2) / R times; the extra reads of
 // the boundary rows are served by the caches.
-template <class T, bool SHIFT, int VX, int NW, bool NTS>
+// FIELD: a lattice with a c2 field (per-site source coefficients).
+template <class T, bool SHIFT, int VX, int NW, bool NTS, bool FIELD>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(MinWaves<T>::value, 8))) void step_vstack_kernel(
     StepTile a, int ntiles)
 {
@@ -173,7 +174,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(MinWave
     __shared__ C lds[NW][64 * VX];
     const int t = xcd_tile(blockIdx.x, gridDim.x, a.xcd_chunk);
     if (t >= ntiles) return;
-    vstack_tile<T, SHIFT, VX, NW, NTS>(a, a.src, a.dst, t % a.nstrips, t / a.nstrips, lds);
+    vstack_tile<T, SHIFT, VX, NW, NTS, FIELD>(a, a.src, a.dst, t % a.nstrips, t / a.nstrips, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -392,10 +393,14 @@ static hipError_t launch_vstack_t(int flags, const StepTile& t, hipStream_t st)
     const int ntiles = t.nstrips * t.nchunks;  // strips x row groups of NW - 2 rows
     const int q = t.xcd_chunk > 0 ? 8 * t.xcd_chunk : 8;
     const int grid = (ntiles + q - 1) / q * q;
-    if (flags & 2)
-        hipLaunchKernelGGL((step_vstack_kernel<T, SHIFT, VX, NW, true>), dim3(grid), dim3(64 * NW), 0, st, t, ntiles);
-    else
-        hipLaunchKernelGGL((step_vstack_kernel<T, SHIFT, VX, NW, false>), dim3(grid), dim3(64 * NW), 0, st, t, ntiles);
+    const dim3 gd(grid), bd(64 * NW);
+    if (t.field) {
+        if (flags & 2) hipLaunchKernelGGL((step_vstack_kernel<T, SHIFT, VX, NW, true, true>), gd, bd, 0, st, t, ntiles);
+        else hipLaunchKernelGGL((step_vstack_kernel<T, SHIFT, VX, NW, false, true>), gd, bd, 0, st, t, ntiles);
+    } else {
+        if (flags & 2) hipLaunchKernelGGL((step_vstack_kernel<T, SHIFT, VX, NW, true, false>), gd, bd, 0, st, t, ntiles);
+        else hipLaunchKernelGGL((step_vstack_kernel<T, SHIFT, VX, NW, false, false>), gd, bd, 0, st, t, ntiles);
+    }
     return hipGetLastError();
 }
 
@@ -438,6 +443,7 @@ bool step_shape_supported(int dtype, int vx, int nw, int flags)
 hipError_t launch_step(int dtype, int vx, int nw, int flags, const StepTile& t, hipStream_t st)
 {
     if (!step_shape_supported(dtype, vx, nw, flags)) return hipErrorInvalidValue;
+    if (t.field && !(flags & 16)) return hipErrorInvalidValue;  // c2 fields: vertical-stack kernels only
     switch (dtype) {
     case 0: return launch_vx<double, false>(vx, nw, flags, t, st);
     case 1: return launch_vx<float, false>(vx, nw, flags, t, st);
@@ -445,6 +451,26 @@ hipError_t launch_step(int dtype, int vx, int nw, int flags, const StepTile& t, 
     case 3: return launch_vx<_Float16, true>(vx, nw, flags, t, st);
     }
     return hipErrorInvalidValue;
+}
+
+// c2 field -> per-site source coefficients in compute precision C; the
+// pitch padding (x >= nx) is zero.
+template <class C>
+__global__ void field_kernel(C* __restrict__ field, int nx, int ny, int fpitch, const double* __restrict__ c2)
+{
+    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (long long)ny * fpitch) return;
+    const int y = (int)(k / fpitch), x = (int)(k % fpitch);
+    field[k] = x < nx ? (C)source_as1(c2[(size_t)y * nx + x]) : C(0);
+}
+
+hipError_t launch_field(int dtype, void* field, int nx, int ny, int fpitch, const double* c2, hipStream_t st)
+{
+    const long long n = (long long)ny * fpitch;
+    const dim3 grid((unsigned)((n + 255) / 256));
+    if (dtype == 0) hipLaunchKernelGGL(field_kernel<double>, grid, dim3(256), 0, st, (double*)field, nx, ny, fpitch, c2);
+    else hipLaunchKernelGGL(field_kernel<float>, grid, dim3(256), 0, st, (float*)field, nx, ny, fpitch, c2);
+    return hipGetLastError();
 }
 
 static dim3 plane_rows_grid(const Geom& g, int extra)

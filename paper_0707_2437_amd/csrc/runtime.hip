@@ -2,6 +2,7 @@
 // argument validation and the C ABI declared in include/liblbm.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -29,6 +30,8 @@ struct lbm_lattice {
     bool ready;
     int vx, nw, h;     // step tile
     int kflags;        // LBM_TILE_* bits
+    void* field;       // per-site source coefficients of a c2 field, or nullptr
+    int fpitch;        // its row pitch (elements)
 };
 
 namespace {
@@ -46,7 +49,7 @@ TileDefault default_tile(int dtype)
     case LBM_F64: return {2, 8, 8, LBM_TILE_VSTACK | LBM_TILE_NT_STORE};
     case LBM_F32: return {2, 8, 8, LBM_TILE_VSTACK | LBM_TILE_NT_STORE};
     case LBM_F32S: return {2, 8, 8, LBM_TILE_VSTACK | LBM_TILE_NT_STORE};
-    default: return {4, 16, 8, LBM_TILE_VSTACK | LBM_TILE_NT_STORE};
+    default: return {4, 8, 8, LBM_TILE_VSTACK | LBM_TILE_NT_STORE};
     }
 }
 
@@ -85,7 +88,43 @@ StepTile make_tile(const lbm_lattice* L)
         t.nchunks = (L->ny + L->h - 1) / L->h;
     }
     t.rowband = (L->kflags & LBM_TILE_ROWBAND) ? 1 : 0;
+    t.field = L->field;
+    t.fpitch = L->fpitch;
     return t;
+}
+
+// A lattice with a c2 field steps with the vertical-stack kernels only: a
+// march-form tile is replaced by the dtype's default.
+void field_tile(lbm_lattice* L)
+{
+    if (L->kflags & LBM_TILE_VSTACK) return;
+    const TileDefault td = default_tile(L->dtype);
+    L->vx = td.vx;
+    L->nw = td.nw;
+    L->h = td.h;
+    L->kflags = td.flags;
+}
+
+// Allocate the field array on first use.
+int ensure_field(lbm_lattice* L)
+{
+    if (L->field) return LBM_OK;
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, field_bytes(L->nx, L->ny, L->dtype));
+    if (e != hipSuccess) return e == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE;
+    L->field = p;
+    L->fpitch = field_pitch(L->nx);
+    return LBM_OK;
+}
+
+int drop_field(lbm_lattice* L)
+{
+    if (!L->field) return LBM_OK;
+    hipError_t e = hipStreamSynchronize(L->stream);
+    (void)hipFree(L->field);
+    L->field = nullptr;
+    L->fpitch = 0;
+    return status_of(e);
 }
 
 }  // namespace
@@ -171,6 +210,7 @@ void lbm_destroy(lbm_lattice* L)
     if (L->own) (void)hipStreamSynchronize(L->stream);
     if (L->buf) (void)hipFree(L->buf);
     if (L->red) (void)hipFree(L->red);
+    if (L->field) (void)hipFree(L->field);
     if (L->own) (void)hipStreamDestroy(L->own);
     delete L;
 }
@@ -198,7 +238,7 @@ long long lbm_time(const lbm_lattice* L) { return L ? L->t : -1; }
 int lbm_set_tile(lbm_lattice* L, int vx, int nw, int h, int flags)
 {
     if (!L || (flags & ~31) || !step_shape_supported(L->dtype, vx, nw, flags)) return LBM_EINVAL;
-    if (!(flags & LBM_TILE_VSTACK) && h < 1) return LBM_EINVAL;
+    if (!(flags & LBM_TILE_VSTACK) && (h < 1 || L->field)) return LBM_EINVAL;
     L->vx = vx;
     L->nw = nw;
     L->h = h;
@@ -211,10 +251,15 @@ int lbm_autotune(lbm_lattice* L, int reps, int use_cache)
     if (!L || reps < 1) return LBM_EINVAL;
     if (!L->ready) return LBM_ESTATE;
     char key[160];
-    std::snprintf(key, sizeof(key), "%s|lattice|%d|%dx%d", device_arch().c_str(), L->dtype, L->nx, L->ny);
+    std::snprintf(key, sizeof(key), "%s|%s|%d|%dx%d", device_arch().c_str(), L->field ? "lattice-field" : "lattice",
+                  L->dtype, L->nx, L->ny);
     TileCand c{};
     if (use_cache && tune_cache_get(key, &c)) return lbm_set_tile(L, c.vx, c.nw, c.h, c.flags);
-    const std::vector<TileCand> cands = lattice_candidates(L->dtype);
+    std::vector<TileCand> cands = lattice_candidates(L->dtype);
+    if (L->field)  // the vertical-stack kernels only
+        cands.erase(std::remove_if(cands.begin(), cands.end(),
+                                   [](const TileCand& k) { return !(k.flags & LBM_TILE_VSTACK); }),
+                    cands.end());
     // read cur, write nxt, no swap: the state does not change
     auto launch = [&](const TileCand& k) -> hipError_t {
         lbm_lattice tmp = *L;
@@ -253,9 +298,40 @@ int lbm_init_device(lbm_lattice* L, const double* rho, const double* ux, const d
 
 int lbm_set_model(lbm_lattice* L, int model)
 {
-    if (!L || !model_ok(model, L->c2)) return LBM_EINVAL;
+    if (!L || !model_ok(model, L->c2) || (L->field && model != LBM_MODEL_FORCING)) return LBM_EINVAL;
     L->model = model;
     L->coef = make_coef(L->tau, L->c2, model);
+    return LBM_OK;
+}
+
+int lbm_set_c2_field(lbm_lattice* L, const double* c2)
+{
+    if (!L || L->model != LBM_MODEL_FORCING) return LBM_EINVAL;
+    if (!c2) return drop_field(L);
+    const size_t n = (size_t)L->nx * L->ny;
+    for (size_t k = 0; k < n; ++k)
+        if (!std::isfinite(c2[k]) || !(c2[k] > 0.0)) return LBM_EINVAL;
+    int st = ensure_field(L);
+    if (st != LBM_OK) return st;
+    DevScratch d;
+    hipError_t e = d.alloc(n);
+    if (e == hipSuccess) e = hipMemcpyAsync(d.p, c2, n * sizeof(double), hipMemcpyHostToDevice, L->stream);
+    if (e == hipSuccess) e = launch_field(L->dtype, L->field, L->nx, L->ny, L->fpitch, d.p, L->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+    if (e != hipSuccess) return status_of(e);
+    field_tile(L);
+    return LBM_OK;
+}
+
+int lbm_set_c2_field_device(lbm_lattice* L, const double* c2)
+{
+    if (!L || L->model != LBM_MODEL_FORCING) return LBM_EINVAL;
+    if (!c2) return drop_field(L);
+    int st = ensure_field(L);
+    if (st != LBM_OK) return st;
+    hipError_t e = launch_field(L->dtype, L->field, L->nx, L->ny, L->fpitch, c2, L->stream);
+    if (e != hipSuccess) return status_of(e);
+    field_tile(L);
     return LBM_OK;
 }
 

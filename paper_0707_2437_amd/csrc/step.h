@@ -502,11 +502,31 @@ __device__ __forceinline__ void plane_bases(const void* src, void* dst, const Ge
     }
 }
 
+// The per-site source coefficients (a c2 field) of the VX columns a lane
+// owns in row y (a row of the field array, see StepTile).
+template <class C, int VX>
+__device__ __forceinline__ Pack<C, VX> field_row(const StepTile& a, int y, int x)
+{
+    const char* row = (const char*)a.field + (size_t)y * a.fpitch * sizeof(C);
+    return ld_vec<C, VX, 4>(row, (unsigned)x * (unsigned)sizeof(C));
+}
+
+// Coefficients of one site: the uniform ones, or with the source
+// coefficients of the site (as2 = as1 / 4 exactly).
+template <bool FIELD, class C> __device__ __forceinline__ CoefC<C> site_coef(const CoefC<C>& k, C as1)
+{
+    if constexpr (!FIELD) return k;
+    CoefC<C> s = k;
+    s.as1 = as1;
+    s.as2 = C(0.25) * as1;
+    return s;
+}
+
 // vstack_tile for FP16 storage (shifted form): the same tile, rows,
 // summation orders and roundings, with the populations kept as the packed
 // halves they were loaded as (see ColH) and the results rounded to FP16 two
 // at a time.
-template <int VX, int NW, bool NTS, bool EDGE>
+template <int VX, int NW, bool NTS, bool EDGE, bool FIELD>
 __device__ __forceinline__ void vstack_tile_h(const StepTile& a, const void* src, void* dst, int strip, int grp,
                                               float (&lds)[NW][64 * VX])
 {
@@ -529,11 +549,14 @@ __device__ __forceinline__ void vstack_tile_h(const StepTile& a, const void* src
 
     unsigned u[9][NWD];
     float w[WV];
+    Pack<float, VX> af{};
     if (active) {
         // An odd-length window (VX = 1) loads one half past its end (at most
         // column nx + 2, row padding).
         Pack<unsigned, NWD> raw[9];
         gather_raw<T, WV, unsigned, NWD, EDGE>(sb, g, y, x, raw);
+        if constexpr (FIELD)
+            if (wave >= 1 && wave <= nrows) af = field_row<float, VX>(a, y, x);
 #pragma unroll
         for (int i = 0; i < 9; ++i)
 #pragma unroll
@@ -554,7 +577,7 @@ __device__ __forceinline__ void vstack_tile_h(const StepTile& a, const void* src
             // undivided central differences at time t (Sec. 4)
             const float gx = w[j + 2] - w[j];
             const float gy = lds[wave + 1][lane * VX + j] - lds[wave - 1][lane * VX + j];
-            collide_col(col_h<j + 1>(u), w[j + 1], gx, gy, k, o[j]);
+            collide_col(col_h<j + 1>(u), w[j + 1], gx, gy, site_coef<FIELD>(k, af.v[j]), o[j]);
         });
         Pack<T, VX> out[9];
 #pragma unroll
@@ -574,7 +597,7 @@ __device__ __forceinline__ void vstack_tile_h(const StepTile& a, const void* src
     }
 }
 
-template <class T, bool SHIFT, int VX, int NW, bool NTS, bool EDGE>
+template <class T, bool SHIFT, int VX, int NW, bool NTS, bool EDGE, bool FIELD>
 __device__ __forceinline__ void vstack_tile_f(const StepTile& a, const void* src, void* dst, int strip, int grp,
                                               typename CompT<T>::type (&lds)[NW][64 * VX])
 {
@@ -598,9 +621,12 @@ __device__ __forceinline__ void vstack_tile_f(const StepTile& a, const void* src
 
     K d[9][VX];
     C w[WV];
+    Pack<C, VX> af{};
     if (active) {
         Rw raw[9];
         gather_raw<T, WV, T, WV, EDGE>(sb, g, y, x, raw);
+        if constexpr (FIELD)
+            if (wave >= 1 && wave <= nrows) af = field_row<C, VX>(a, y, x);
         K tmp[9][WV];
 #pragma unroll
         for (int i = 0; i < 9; ++i)
@@ -625,7 +651,7 @@ __device__ __forceinline__ void vstack_tile_f(const StepTile& a, const void* src
             const C gx = w[j + 2] - w[j];
             const C gy = lds[wave + 1][lane * VX + j] - lds[wave - 1][lane * VX + j];
             C o[9];
-            collide<T, SHIFT, C, VX>(d, j, w[j + 1], gx, gy, k, o);
+            collide<T, SHIFT, C, VX>(d, j, w[j + 1], gx, gy, site_coef<FIELD>(k, af.v[j]), o);
 #pragma unroll
             for (int i = 0; i < 9; ++i) out[i].v[j] = from_d<T, SHIFT, C>(o[i], i);
         }
@@ -647,18 +673,20 @@ __device__ __forceinline__ void vstack_tile_f(const StepTile& a, const void* src
 // take a separate copy of the code with the edge patches; the others issue
 // their loads and start the arithmetic as the loads land, with no patch code
 // in between. The branch is uniform over the workgroup.
-template <class T, bool SHIFT, int VX, int NW, bool NTS>
+// FIELD: the source coefficients come per site from a.field (a c2 field);
+// the interior waves load them with their windows.
+template <class T, bool SHIFT, int VX, int NW, bool NTS, bool FIELD = false>
 __device__ __forceinline__ void vstack_tile(const StepTile& a, const void* src, void* dst, int strip, int grp,
                                             typename CompT<T>::type (&lds)[NW][64 * VX])
 {
     if constexpr (std::is_same<T, _Float16>::value) {
         static_assert(SHIFT, "FP16 storage is the shifted form");
         static_assert(GhostCols<T>::value, "FP16 rows carry ghost columns");
-        vstack_tile_h<VX, NW, NTS, false>(a, src, dst, strip, grp, lds);
+        vstack_tile_h<VX, NW, NTS, false, FIELD>(a, src, dst, strip, grp, lds);
     } else {
         const bool edge = strip == 0 || (strip + 1) * (64 * VX) + 2 > a.g.nx;
-        if (edge) vstack_tile_f<T, SHIFT, VX, NW, NTS, true>(a, src, dst, strip, grp, lds);
-        else vstack_tile_f<T, SHIFT, VX, NW, NTS, false>(a, src, dst, strip, grp, lds);
+        if (edge) vstack_tile_f<T, SHIFT, VX, NW, NTS, true, FIELD>(a, src, dst, strip, grp, lds);
+        else vstack_tile_f<T, SHIFT, VX, NW, NTS, false, FIELD>(a, src, dst, strip, grp, lds);
     }
 }
 

@@ -85,6 +85,19 @@ class Lattice:
         _check(self._L.lbm_set_model(self._h, int(model)), "lbm_set_model")
         return self
 
+    def set_c2_field(self, c2):
+        """lbm_set_c2_field: per-site c_e^2 (host array, shape (ny, nx), broadcast
+        if smaller), or None to remove the field."""
+        c2 = _host(c2, (self.ny, self.nx))
+        _check(self._L.lbm_set_c2_field(self._h, _hptr(c2)), "lbm_set_c2_field")
+        return self
+
+    def set_c2_field_device(self, c2):
+        """lbm_set_c2_field_device: a device FP64 tensor of nx * ny entries
+        (row-major), or None; asynchronous on the lattice's stream."""
+        _check(self._L.lbm_set_c2_field_device(self._h, _dptr(c2, self.nx * self.ny)), "lbm_set_c2_field_device")
+        return self
+
     # lifetime --------------------------------------------------------------
     def close(self):
         if getattr(self, "_h", None):

@@ -51,6 +51,20 @@ def gaussian_pulse_fields(nx, ny, amp, sigma=None):
     return 1.0 + amp * np.exp(-r2 / (2.0 * sigma * sigma)), None, None
 
 
+def lens_c2_field(nx, ny, c2, depth=0.5, noise=0.0, seed=0):
+    """A c^2 field shaped like an acoustic lens (the paper's example of a
+    pre-determined variation, Sec. 5): c^2 (1 - depth exp(-r^2 / (2 sigma^2)))
+    around the centre, sigma = min(nx, ny) / 6, times a seeded factor
+    1 + U[-noise, noise] per site (so that every site differs)."""
+    x, y = grid(nx, ny)
+    sigma = min(nx, ny) / 6.0
+    r2 = (x - nx / 2.0) ** 2 + (y - ny / 2.0) ** 2
+    f = c2 * (1.0 - depth * np.exp(-r2 / (2.0 * sigma * sigma)))
+    if noise > 0:
+        f = f * (1.0 + np.random.default_rng(seed).uniform(-noise, noise, size=(ny, nx)))
+    return f
+
+
 def batch_specs(n=256, seed=0, lo=64, hi=1024):
     """The batching workload: n independent periodic lattices with
     nx, ny ~ U{lo..hi}, tau ~ U[0.55, 1.5], c^2 ~ U[0.04, 0.6] (inside the
