@@ -5,7 +5,7 @@ CPU-baseline leg load this package. The product library never does, and the
 two share no code.
 """
 from .lbmref import (Oracle, lattice, alpha, equilibrium, equilibrium_c2, source, load, set_threads, get_threads,
-                     MODEL_FORCING, MODEL_EQUILIBRIUM)
+                     MODEL_FORCING, MODEL_EQUILIBRIUM, XBC_PERIODIC, XBC_INLET_OUTLET)
 
 __all__ = ["Oracle", "lattice", "alpha", "equilibrium", "equilibrium_c2", "source", "load", "set_threads", "get_threads",
-           "MODEL_FORCING", "MODEL_EQUILIBRIUM"]
+           "MODEL_FORCING", "MODEL_EQUILIBRIUM", "XBC_PERIODIC", "XBC_INLET_OUTLET"]

@@ -24,6 +24,8 @@ struct lbmref {
     double c2;      /* c_e^2 as requested                                  */
     int model;      /* enum lbmref_model                                   */
     double* A;      /* alpha(x) of a c2 field, [ny][nx]; NULL: uniform     */
+    int xbc;        /* enum lbmref_xbc                                     */
+    double amp, period; /* inlet density oscillation (LBMREF_XBC_INLET_OUTLET) */
     long long t;    /* completed steps                                     */
     int ready;      /* set by init / set_f                                 */
     double* f;      /* f_i(x, t), [9][ny][nx]                              */
@@ -186,6 +188,22 @@ void lbmref_destroy(lbmref* L)
     free(L);
 }
 
+int lbmref_set_x_boundaries(lbmref* L, int mode, double amplitude, double period)
+{
+    if (!L) return LBMREF_EINVAL;
+    if (mode == LBMREF_XBC_PERIODIC) {
+        L->xbc = mode;
+        return LBMREF_OK;
+    }
+    if (mode != LBMREF_XBC_INLET_OUTLET || L->nx < 5 || !isfinite(period) || !(period > 0.0) ||
+        !isfinite(amplitude) || !(fabs(amplitude) < 1.0))
+        return LBMREF_EINVAL;
+    L->xbc = mode;
+    L->amp = amplitude;
+    L->period = period;
+    return LBMREF_OK;
+}
+
 int lbmref_set_c2_field(lbmref* L, const double* c2)
 {
     if (!L || L->model != LBMREF_MODEL_FORCING) return LBMREF_EINVAL;
@@ -256,6 +274,17 @@ static void step_once(lbmref* L)
     /* rho(x, t) and u(x, t) from Eq. 3. */
     compute_moments(L);
 
+    /* Fig. 1 boundaries: what the two boundary columns emit in this step,
+     * their equilibria at rest at the inlet density and at rho = 1. */
+    const int xbc = L->xbc == LBMREF_XBC_INLET_OUTLET;
+    double fin[9], fout[9];
+    if (xbc) {
+        const double pi = 3.14159265358979323846;
+        double rho_in = 1.0 + L->amp * sin(2.0 * pi * (double)L->t / L->period);
+        model_equilibrium(L, rho_in, 0.0, 0.0, fin);
+        model_equilibrium(L, 1.0, 0.0, 0.0, fout);
+    }
+
 #pragma omp parallel for schedule(static)
     for (int y = 0; y < ny; ++y) {
         for (int x = 0; x < nx; ++x) {
@@ -275,6 +304,14 @@ static void step_once(lbmref* L)
                 /* Right-hand side of Eq. 5 added to f_i(x, t) ... */
                 double fi = L->f[i * n + s];
                 double fstar = fi - (fi - feq[i]) / L->tau + src[i];
+                if (xbc && (x == 0 || x == nx - 1)) {
+                    /* a boundary column emits its equilibrium; across the
+                     * cut seam the entered column's equilibrium arrives */
+                    int crosses = (x == 0 && e[2 * i] < 0) || (x == nx - 1 && e[2 * i] > 0);
+                    const double* own = x == 0 ? fin : fout;
+                    const double* entered = x == 0 ? fout : fin;
+                    fstar = crosses ? entered[i] : own[i];
+                }
                 /* ... lands at x + e_i at time t + 1 (left-hand side). */
                 int xd = wrap(x + e[2 * i], nx);
                 int yd = wrap(y + e[2 * i + 1], ny);

@@ -88,6 +88,21 @@ int lbmref_set_model(lbmref* L, int model);
  * the lattice keeps its previous field then. */
 int lbmref_set_c2_field(lbmref* L, const double* c2);
 
+/* Boundaries in x. LBMREF_XBC_PERIODIC (default): periodic, as everywhere
+ * else. LBMREF_XBC_INLET_OUTLET: the set-up of Fig. 1 (Sec. 4), an
+ * oscillating density at x = 0 and rho = 1, u = 0 at the far end. The
+ * sites of columns x = 0 and x = nx - 1 do not collide: in the step from
+ * time t they emit the model's equilibrium at rest, at the density
+ * rho_in(t) = 1 + amplitude sin(2 pi t / period) (x = 0) and 1
+ * (x = nx - 1). The periodic seam between the two columns is cut: a
+ * population that would cross it (leaving x = 0 towards -x, or x = nx - 1
+ * towards +x) arrives as the equilibrium population of the column it
+ * enters, at that column's boundary density. y stays periodic.
+ * LBMREF_EINVAL for an unknown mode, or for the inlet/outlet with nx < 5,
+ * period not finite and > 0, or |amplitude| not < 1. */
+enum lbmref_xbc { LBMREF_XBC_PERIODIC = 0, LBMREF_XBC_INLET_OUTLET = 1 };
+int lbmref_set_x_boundaries(lbmref* L, int mode, double amplitude, double period);
+
 /* f_i(x, 0) = feq_i(rho(x), u(x)) of the lattice's model. NULL rho means rho = 1, NULL ux / uy
  * mean 0. Arrays have nx*ny entries. Sets t = 0. */
 int lbmref_init(lbmref* L, const double* rho, const double* ux, const double* uy);

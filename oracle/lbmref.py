@@ -45,6 +45,8 @@ def load(path=None):
     lib.lbmref_set_model.argtypes = [ctypes.c_void_p, ctypes.c_int]
     lib.lbmref_set_model.restype = ctypes.c_int
     lib.lbmref_source.restype = None
+    lib.lbmref_set_x_boundaries.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_double]
+    lib.lbmref_set_x_boundaries.restype = ctypes.c_int
     lib.lbmref_set_c2_field.argtypes = [ctypes.c_void_p, _dp]
     lib.lbmref_set_c2_field.restype = ctypes.c_int
     lib.lbmref_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double]
@@ -100,6 +102,7 @@ def equilibrium_c2(c2, rho, ux, uy, lib=None):
 
 
 MODEL_FORCING, MODEL_EQUILIBRIUM = 0, 1
+XBC_PERIODIC, XBC_INLET_OUTLET = 0, 1
 
 
 def source(alpha_, gx, gy, lib=None):
@@ -154,6 +157,12 @@ class Oracle:
         if a.shape != (self.ny, self.nx):
             a = np.ascontiguousarray(np.broadcast_to(a, (self.ny, self.nx)))
         return a
+
+    def set_x_boundaries(self, mode, amplitude=0.0, period=0.0):
+        """XBC_PERIODIC, or XBC_INLET_OUTLET (Fig. 1: rho_in(t) at x = 0, rho = 1 at x = nx - 1)."""
+        self._check(self.lib.lbmref_set_x_boundaries(self._h, int(mode), float(amplitude), float(period)),
+                    "set_x_boundaries")
+        return self
 
     def set_c2_field(self, c2):
         """Per-site c_e^2 (shape (ny, nx), broadcast if smaller); None: uniform again."""

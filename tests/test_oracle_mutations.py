@@ -40,12 +40,19 @@ MUTANTS = {
     "c2_field_transposed": ("L->A ? L->A[s]", "L->A ? L->A[(size_t)x * ny + y]"),
     "c2_field_neighbour": ("L->A ? L->A[s]", "L->A ? L->A[(size_t)y * nx + wrap(x + 1, nx)]"),
     "c2_field_sign": ("L->A[s] = lbmref_alpha(c2[s]);", "L->A[s] = c2[s] - 1.0 / 3.0;"),
+    # Fig. 1 boundaries
+    "inlet_phase": ("sin(2.0 * pi * (double)L->t / L->period)", "sin(2.0 * pi * (double)(L->t + 1) / L->period)"),
+    "inlet_cosine": ("sin(2.0 * pi * (double)L->t / L->period)", "cos(2.0 * pi * (double)L->t / L->period) - 1.0"),
+    "seam_not_cut": ("fstar = crosses ? entered[i] : own[i];", "fstar = own[i];"),
+    "boundary_collides": ("if (xbc && (x == 0 || x == nx - 1)) {", "if (xbc && x < 0) {"),
+    "outlet_at_inlet_density": ("model_equilibrium(L, 1.0, 0.0, 0.0, fout);", "model_equilibrium(L, rho_in, 0.0, 0.0, fout);"),
 }
 
 FAST_PINS = [os.path.join(ROOT, "tests", "test_oracle_pins.py"),
              os.path.join(ROOT, "tests", "test_oracle_physics.py"),
              os.path.join(ROOT, "tests", "test_oracle_equilibrium_model.py"),
-             os.path.join(ROOT, "tests", "test_oracle_c2_field.py")]
+             os.path.join(ROOT, "tests", "test_oracle_c2_field.py"),
+             os.path.join(ROOT, "tests", "test_oracle_inlet.py")]
 
 
 def run_pins_against(source_text, tmp_path):
