@@ -98,6 +98,23 @@ enum lbm_model { LBM_MODEL_FORCING = 0, LBM_MODEL_EQUILIBRIUM = 1 };
  * forcing model. */
 int lbm_set_model(lbm_lattice* L, int model);
 
+/* Boundaries in x. LBM_XBC_PERIODIC (the default): periodic, as in y.
+ * LBM_XBC_INLET_OUTLET: the set-up of Fig. 1 (Sec. 4), an oscillating
+ * density at x = 0 and rho = 1, u = 0 at the far end. The sites of columns
+ * x = 0 and x = nx - 1 do not collide: in the step from time t they emit
+ * the lattice model's equilibrium at rest at the density
+ *   rho_in(t) = 1 + amplitude sin(2 pi t / period)   (x = 0)
+ * and 1 (x = nx - 1), and the periodic seam between the two columns is
+ * cut: a population that would cross it arrives as the equilibrium
+ * population of the column it enters, at that column's boundary density.
+ * t is lbm_time() (so lbm_init / lbm_set_f restart the inlet's phase). Each
+ * step then adds one small launch (the two columns). LBM_EINVAL for a NULL
+ * handle, an unknown mode, or the inlet/outlet with nx < 5, a period that
+ * is not finite and > 0, or |amplitude| >= 1. Takes effect at the next
+ * step; pools are periodic. */
+enum lbm_xbc { LBM_XBC_PERIODIC = 0, LBM_XBC_INLET_OUTLET = 1 };
+int lbm_set_x_boundaries(lbm_lattice* L, int mode, double amplitude, double period);
+
 /* A speed of sound that varies in space, the extension the paper's
  * conclusion (Sec. 5) proposes: alpha need not be constant, e.g. to model
  * an acoustic lens or a temperature gradient. c2 is a HOST FP64 array of

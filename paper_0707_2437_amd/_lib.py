@@ -30,6 +30,7 @@ SIGNATURES = {
     "lbm_destroy": (None, [_vp]),
     "lbm_init": (_i, [_vp, _vp, _vp, _vp]),
     "lbm_set_model": (_i, [_vp, _i]),
+    "lbm_set_x_boundaries": (_i, [_vp, _i, _d, _d]),
     "lbm_set_c2_field": (_i, [_vp, _vp]),
     "lbm_set_c2_field_device": (_i, [_vp, _vp]),
     "lbm_init_device": (_i, [_vp, _vp, _vp, _vp]),

@@ -16,6 +16,7 @@ hipError_t launch_step(int dtype, int vx, int nw, int flags, const StepTile& t, 
 bool step_shape_supported(int dtype, int vx, int nw, int flags);
 hipError_t launch_init(int dtype, void* s, const Geom& g, const double* rho, const double* ux, const double* uy,
                        double eqs, hipStream_t st);
+hipError_t launch_xbc(int dtype, void* s, const Geom& g, double rho_in, double eqs, hipStream_t st);
 hipError_t launch_field(int dtype, void* field, int nx, int ny, int fpitch, const double* c2, hipStream_t st);
 hipError_t launch_set_f(int dtype, void* s, const Geom& g, const double* f, hipStream_t st);
 hipError_t launch_get_f(int dtype, const void* s, const Geom& g, double* f, hipStream_t st);
@@ -151,6 +152,13 @@ inline Coef make_coef(double tau, double c2, int model)
 inline int field_pitch(int nx) { return (nx + 255) / 256 * 256; }
 inline size_t field_esize(int dtype) { return dtype == LBM_F64 ? sizeof(double) : sizeof(float); }
 inline size_t field_bytes(int nx, int ny, int dtype) { return (size_t)ny * field_pitch(nx) * field_esize(dtype); }
+
+// Inlet density of the Fig. 1 boundaries at time t (Sec. 4): an oscillation
+// of the given amplitude and period about rho = 1.
+inline double inlet_density(double amplitude, double period, long long t)
+{
+    return 1.0 + amplitude * std::sin(2.0 * 3.14159265358979323846 * (double)t / period);
+}
 
 // Tiles per XCD chunk of the vertical-stack kernels (see xcd_tile): whole
 // row groups of a lattice, at least 16 tiles. LBM_XCD_CHUNK=<n> overrides

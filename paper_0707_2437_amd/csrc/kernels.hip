@@ -453,6 +453,44 @@ hipError_t launch_step(int dtype, int vx, int nw, int flags, const StepTile& t, 
     return hipErrorInvalidValue;
 }
 
+// Fig. 1 boundaries, after the step from time t into `s` (which then holds
+// the post-collision populations S_i(x) = f*_i(x, t)): the sites of columns
+// 0 and nx - 1 emit the equilibrium at rest at rho_in and 1 in place of
+// their collision, and a population that crosses the cut periodic seam
+// carries the equilibrium of the column it enters. One thread per (plane,
+// row, column) over columns 0, nx - 1 and their ghost images nx and -1
+// (read in place of the wrap by the FP16 kernels; padding otherwise).
+template <class T, bool SHIFT>
+__global__ void xbc_kernel(T* __restrict__ s, Geom g, double rho_in, double eqs)
+{
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= 36LL * g.ny) return;
+    const int k = (int)(q & 3);
+    const long long row = q >> 2;
+    const int i = (int)(row / g.ny), y = (int)(row - (long long)i * g.ny);
+    const bool inlet = k == 0 || k == 2;  // column 0, or its image nx
+    const int col = k == 0 ? 0 : (k == 1 ? g.nx - 1 : (k == 2 ? g.nx : -1));
+    const bool crosses = inlet ? kEX[i] < 0 : kEX[i] > 0;
+    const double rho = inlet != crosses ? rho_in : 1.0;
+    T v;
+    if constexpr (SHIFT) v = (T)dfeq(i, rho, 0.0, 0.0, eqs);
+    else v = (T)feq(i, rho, 0.0, 0.0, eqs);
+    s[i * g.ps + (long long)y * g.rs + g.off + col] = v;
+}
+
+hipError_t launch_xbc(int dtype, void* s, const Geom& g, double rho_in, double eqs, hipStream_t st)
+{
+    const dim3 grid((unsigned)((36LL * g.ny + 255) / 256));
+    switch (dtype) {
+    case 0: hipLaunchKernelGGL((xbc_kernel<double, false>), grid, dim3(256), 0, st, (double*)s, g, rho_in, eqs); break;
+    case 1: hipLaunchKernelGGL((xbc_kernel<float, false>), grid, dim3(256), 0, st, (float*)s, g, rho_in, eqs); break;
+    case 2: hipLaunchKernelGGL((xbc_kernel<float, true>), grid, dim3(256), 0, st, (float*)s, g, rho_in, eqs); break;
+    case 3: hipLaunchKernelGGL((xbc_kernel<_Float16, true>), grid, dim3(256), 0, st, (_Float16*)s, g, rho_in, eqs); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 // c2 field -> per-site source coefficients in compute precision C; the
 // pitch padding (x >= nx) is zero.
 template <class C>

@@ -32,6 +32,8 @@ struct lbm_lattice {
     int kflags;        // LBM_TILE_* bits
     void* field;       // per-site source coefficients of a c2 field, or nullptr
     int fpitch;        // its row pitch (elements)
+    int xbc;           // lbm_xbc
+    double amp, period;  // inlet density oscillation (LBM_XBC_INLET_OUTLET)
 };
 
 namespace {
@@ -304,6 +306,22 @@ int lbm_set_model(lbm_lattice* L, int model)
     return LBM_OK;
 }
 
+int lbm_set_x_boundaries(lbm_lattice* L, int mode, double amplitude, double period)
+{
+    if (!L) return LBM_EINVAL;
+    if (mode == LBM_XBC_PERIODIC) {
+        L->xbc = mode;
+        return LBM_OK;
+    }
+    if (mode != LBM_XBC_INLET_OUTLET || L->nx < 5 || !std::isfinite(period) || !(period > 0.0) ||
+        !std::isfinite(amplitude) || !(std::fabs(amplitude) < 1.0))
+        return LBM_EINVAL;
+    L->xbc = mode;
+    L->amp = amplitude;
+    L->period = period;
+    return LBM_OK;
+}
+
 int lbm_set_c2_field(lbm_lattice* L, const double* c2)
 {
     if (!L || L->model != LBM_MODEL_FORCING) return LBM_EINVAL;
@@ -361,6 +379,9 @@ int lbm_step(lbm_lattice* L, int n)
     for (int k = 0; k < n; ++k) {
         StepTile t = make_tile(L);
         hipError_t e = launch_step(L->dtype, L->vx, L->nw, L->kflags, t, L->stream);
+        if (e == hipSuccess && L->xbc == LBM_XBC_INLET_OUTLET)
+            e = launch_xbc(L->dtype, L->nxt, L->g, inlet_density(L->amp, L->period, L->t), eq_shift(L->c2, L->model),
+                           L->stream);
         if (e != hipSuccess) return status_of(e);
         void* tmp = L->cur;
         L->cur = L->nxt;

@@ -18,6 +18,7 @@ OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENONFINITE = 0, -1, -2, -3, -4, -5
 
 # lbm_model: the paper's forcing model (Eq. 5) or the altered-equilibrium one
 MODEL_FORCING, MODEL_EQUILIBRIUM = 0, 1
+XBC_PERIODIC, XBC_INLET_OUTLET = 0, 1
 
 
 class LBMError(RuntimeError):
@@ -83,6 +84,13 @@ class Lattice:
     def set_model(self, model):
         """lbm_set_model: MODEL_FORCING (Eq. 5) or MODEL_EQUILIBRIUM; before init."""
         _check(self._L.lbm_set_model(self._h, int(model)), "lbm_set_model")
+        return self
+
+    def set_x_boundaries(self, mode, amplitude=0.0, period=0.0):
+        """lbm_set_x_boundaries: XBC_PERIODIC, or XBC_INLET_OUTLET (Fig. 1:
+        rho_in(t) = 1 + amplitude sin(2 pi t / period) at x = 0, rho = 1 at x = nx - 1)."""
+        _check(self._L.lbm_set_x_boundaries(self._h, int(mode), float(amplitude), float(period)),
+               "lbm_set_x_boundaries")
         return self
 
     def set_c2_field(self, c2):

@@ -68,6 +68,7 @@ def test_null_handle_calls_are_errors():
     assert L.lbm_init(None, None, None, None) == lbm.EINVAL
     assert L.lbm_set_model(None, lbm.MODEL_EQUILIBRIUM) == lbm.EINVAL
     assert L.lbm_set_c2_field(None, None) == lbm.EINVAL
+    assert L.lbm_set_x_boundaries(None, 0, 0.0, 0.0) == lbm.EINVAL
     assert L.lbm_set_c2_field_device(None, None) == lbm.EINVAL
     assert L.lbm_moments(None, None, None, None, None) == lbm.EINVAL
     assert L.lbm_time(None) == -1
