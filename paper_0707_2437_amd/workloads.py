@@ -37,6 +37,17 @@ def plane_wave_fields(nx, ny, c2, amp=1e-3, noise=1e-4, seed=0):
     return 1.0 + amp * s + xi, np.sqrt(c2) * amp * s, None
 
 
+def simple_wave_fields(nx, ny, c2, u0):
+    """A right-going simple wave of finite amplitude (the paper's nonlinear
+    progressive waves, Sec. 4): u_x = u0 sin(2 pi x / nx) and rho =
+    exp(u_x / c), the relation that holds along a right-going simple wave of
+    a gas with p = c^2 rho (its Riemann invariant u - c ln rho is zero), so
+    that no left-going wave is excited at any order."""
+    x, _ = grid(nx, ny)
+    u = u0 * np.sin(2 * np.pi * x / nx)
+    return np.exp(u / np.sqrt(c2)), u, None
+
+
 def shear_wave_fields(nx, ny, amp=0.01):
     """Shear wave u_x = amp sin(2 pi y / ny), rho = 1 (x-invariant)."""
     _, y = grid(nx, ny)

@@ -1,0 +1,67 @@
+"""The paper's nonlinear progressive waves at full scale on the GPU (Sec. 4,
+Figs. 2-3): lambda = 4000 on a lambda x 4 lattice, u0 = 0.002, nu = 0.01
+(tau = 0.53); wave (1) with alpha = 0.2933 (c_e = 0.2) observed at 5, 10,
+15 and 20 wavelengths, wave (2) with alpha = -0.47667 (c_e = 0.9) at 45
+wavelengths (Eq. 9 puts the shock at about 16 and 72 wavelengths). The
+velocity's harmonics are compared with the exact Burgers solution
+(tests/burgers.py); the first 20 000 steps also against the oracle.
+
+Bars: FP64 5e-3 u0 (the oracle's pin at lambda = 400; dispersion is smaller
+here). Shifted FP32 storage and arithmetic: these waves change each
+population by ~1e-4 of itself per step, so each step's two roundings (the
+stored population, the FP32 arithmetic; relative 2^-24 each) accumulate
+over the 10^5 steps as an error of up to n 2^-23 u0 after n steps, which is
+the bar (it is what limits the FP32 forms on the paper's longest runs)."""
+import numpy as np
+import pytest
+
+import burgers
+import oracle
+from gpu_util import max_rel_err
+from paper_0707_2437_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_0707_2437_amd as lbm  # noqa: E402
+
+LAM, NY, U0, TAU = 4000, 4, 0.002, 0.53
+NU = (2 * TAU - 1) / 6
+K = 2 * np.pi / LAM
+WAVES = {"wave1": (1.0 / 3.0 - 0.2933, (5, 10, 15, 20)), "wave2": (1.0 / 3.0 + 0.47667, (45,))}
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32s"])
+@pytest.mark.parametrize("wave", sorted(WAVES))
+def test_paper_wave_harmonics_follow_burgers(wave, dtype):
+    c2, distances = WAVES[wave]
+    c = np.sqrt(c2)
+    with lbm.Lattice(LAM, NY, TAU, c2, dtype) as L:
+        L.init(*workloads.simple_wave_fields(LAM, NY, c2, U0))
+        for d in distances:
+            t = int(round(d * LAM / c))
+            L.step(t - L.time)
+            ux = L.moments()[1]
+            got = np.abs(np.fft.rfft(ux[0]) * (2.0 / LAM))[1:7]
+            want = burgers.harmonics(U0, K, NU, t, 6)
+            err = np.max(np.abs(got - want)) / U0
+            print(f"{wave} {dtype} at {d} wavelengths (sigma = {K * U0 * t:.2f}): harmonics/u0 {np.round(got / U0, 4)}"
+                  f" Burgers {np.round(want / U0, 4)}, max diff {err:.2e} u0", flush=True)
+            assert err < (5e-3 if dtype == "f64" else t * 2.0 ** -23)
+
+
+def test_paper_wave_parity_with_oracle():
+    """FP64, 20 000 steps. The two sides differ only in rounding order (the
+    kernels' FMAs); on a wave this slow the per-step differences add up
+    coherently rather than cancel, so the bar is one unit of 2^-52 per step."""
+    c2, n = WAVES["wave1"][0], 20000
+    fields = workloads.simple_wave_fields(LAM, NY, c2, U0)
+    with lbm.Lattice(LAM, NY, TAU, c2, "f64") as L:
+        f = L.init(*fields).step(n).get_f()
+    fr = oracle.Oracle(LAM, NY, TAU, c2).init(*fields).step(n).get_f()
+    err = max_rel_err(f, fr)
+    print(f"wave1 FP64 after {n} steps: max rel err f = {err:.2e} (bar {n * 2.0 ** -52:.2e})")
+    assert err <= n * 2.0 ** -52
