@@ -35,12 +35,14 @@
 extern "C" {
 #endif
 
-/* Storage / arithmetic forms. */
+/* Storage / arithmetic forms. r_i is the lattice model's equilibrium at
+ * rest (rho0 = 1, u = 0): the weights w_i for the paper's model (Eq. 2),
+ * w_i 3 c2 (i != 0) and 1 - 5 c2 / 3 (i = 0) for LBM_MODEL_EQUILIBRIUM. */
 enum lbm_dtype {
     LBM_F64 = 0,  /* f_i stored in FP64, FP64 arithmetic                         */
-    LBM_F32 = 1,  /* f_i stored in FP32, FP32 arithmetic on d_i = f_i - w_i       */
-    LBM_F32S = 2, /* g_i = f_i - w_i (rho0 = 1) stored in FP32, FP32 arithmetic  */
-    LBM_F16S = 3  /* g_i = f_i - w_i stored in FP16, FP32 arithmetic             */
+    LBM_F32 = 1,  /* f_i stored in FP32, FP32 arithmetic on d_i = f_i - r_i       */
+    LBM_F32S = 2, /* g_i = f_i - r_i stored in FP32, FP32 arithmetic             */
+    LBM_F16S = 3  /* g_i = f_i - r_i stored in FP16, FP32 arithmetic             */
 };
 
 enum lbm_status {
@@ -91,7 +93,9 @@ int lbm_init(lbm_lattice* L, const double* rho, const double* ux, const double* 
  * c2 = 1/3 gives Eq. 2. */
 enum lbm_model { LBM_MODEL_FORCING = 0, LBM_MODEL_EQUILIBRIUM = 1 };
 /* Select the model for the following lbm_init / lbm_step calls (lbm_init
- * sets f to that model's equilibrium). LBM_EINVAL for a NULL handle, an
+ * sets f to that model's equilibrium); on an initialised lattice the
+ * populations f are kept (the shifted forms store f_i - r_i with r_i the
+ * model's equilibrium at rest, and are re-centred, synchronously). LBM_EINVAL for a NULL handle, an
  * unknown model, or LBM_MODEL_EQUILIBRIUM with c2 >= 3/5 (its rest
  * population rho (1 - 5 c2 / 3) would not be positive), or for any model
  * but LBM_MODEL_FORCING while the lattice has a c2 field. Pools step the
@@ -162,7 +166,8 @@ int lbm_moments_device(lbm_lattice* L, double* rho, double* ux, double* uy, doub
 
 /* Canonical populations f_i(x, t) (the pre-collision state of Eq. 5) to /
  * from a HOST FP64 array [9][ny][nx]. lbm_set_f resets t to 0. Synchronous.
- * For the shifted forms the stored value is f_i - w_i, converted on the way. */
+ * For the shifted forms the stored value is f_i - r_i, converted on the way
+ * (r_i: the lattice model's equilibrium at rest, w_i for the paper's model). */
 int lbm_get_f(lbm_lattice* L, double* f);
 int lbm_set_f(lbm_lattice* L, const double* f);
 

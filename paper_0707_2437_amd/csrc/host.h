@@ -18,10 +18,12 @@ hipError_t launch_init(int dtype, void* s, const Geom& g, const double* rho, con
                        double eqs, hipStream_t st);
 hipError_t launch_xbc(int dtype, void* s, const Geom& g, double rho_in, double eqs, hipStream_t st);
 hipError_t launch_field(int dtype, void* field, int nx, int ny, int fpitch, const double* c2, hipStream_t st);
-hipError_t launch_set_f(int dtype, void* s, const Geom& g, const double* f, hipStream_t st);
-hipError_t launch_get_f(int dtype, const void* s, const Geom& g, double* f, hipStream_t st);
+// eqs: the model's equilibrium shift (eq_shift), which sets the centre of
+// the shifted storage.
+hipError_t launch_set_f(int dtype, void* s, const Geom& g, const double* f, double eqs, hipStream_t st);
+hipError_t launch_get_f(int dtype, const void* s, const Geom& g, double* f, double eqs, hipStream_t st);
 int moments_blocks(const Geom& g);
-hipError_t launch_sample_f(int dtype, const void* s, const Geom& g, int n, const int* xy, double* out,
+hipError_t launch_sample_f(int dtype, const void* s, const Geom& g, int n, const int* xy, double* out, double eqs,
                            hipStream_t st);
 hipError_t launch_moments(int dtype, const void* s, const Geom& g, double* rho, double* ux, double* uy,
                           double* partials, double* totals, hipStream_t st);

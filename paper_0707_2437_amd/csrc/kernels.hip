@@ -70,6 +70,7 @@ __global__ __launch_bounds__(64 * NW) void step_kernel(StepTile a, int ntiles)
     const int nv = min(VX, g.nx - x);
     if (nv <= 0) return;  // no barrier below: lanes past the edge simply leave
     const CoefC<C> k = coef_c<C>(a.c);
+    const Centre<C> cn = centre_c<C>(k);
     const int ylo = chunk * a.h;
     const int yhi = min(ylo + a.h, g.ny);
     const int dir = (chunk & 1) ? -1 : 1;  // alternate chunks march upward
@@ -92,9 +93,9 @@ __global__ __launch_bounds__(64 * NW) void step_kernel(StepTile a, int ntiles)
 #pragma unroll
         for (int i = 0; i < 9; ++i)
 #pragma unroll
-            for (int j = 0; j < WV; ++j) tmp[i][j] = keep_of<T, SHIFT, C>(v[i].v[j], i);
+            for (int j = 0; j < WV; ++j) tmp[i][j] = keep_of<T, SHIFT, C>(v[i].v[j], i, cn);
 #pragma unroll
-        for (int j = 0; j < WV; ++j) w[j] = drho_of<T, SHIFT, C, WV>(tmp, j);
+        for (int j = 0; j < WV; ++j) w[j] = drho_of<T, SHIFT, C, WV>(tmp, j, cn);
 #pragma unroll
         for (int i = 0; i < 9; ++i)
 #pragma unroll
@@ -112,9 +113,9 @@ __global__ __launch_bounds__(64 * NW) void step_kernel(StepTile a, int ntiles)
             const C up = wn[j + 1], dw = rprev[j];
             const C gy = dir > 0 ? up - dw : dw - up;
             C o[9];
-            collide<T, SHIFT, C, VX>(dc, j, wc[j + 1], gx, gy, k, o);
+            collide<T, SHIFT, C, VX>(dc, j, wc[j + 1], gx, gy, k, cn, o);
 #pragma unroll
-            for (int i = 0; i < 9; ++i) out[i].v[j] = from_d<T, SHIFT, C>(o[i], i);
+            for (int i = 0; i < 9; ++i) out[i].v[j] = from_d<T, SHIFT, C>(o[i], i, cn);
         }
         write_row<T, VX, NTS>(dbase, g, y, x, nv, out);
     };
@@ -187,19 +188,23 @@ __device__ __constant__ int kEY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 
 __device__ __forceinline__ double wt64(int i) { return wt<double>(i); }
 
-// Eq. 2, returned as feq_i - w_i (accurate for the shifted forms). eqs is
-// the equilibrium shift of the altered-equilibrium model (0 for Eq. 2): the
-// moving populations gain w_i rho eqs, the rest population loses their sum,
-// (1 - w_0) rho eqs.
+// eqs is the equilibrium shift of the altered-equilibrium model (0 for
+// Eq. 2): the moving populations gain w_i rho eqs, the rest population loses
+// their sum, (1 - w_0) rho eqs.
 __device__ __forceinline__ double eq_adjust(int i, double rho, double eqs)
 {
     return i == 0 ? -(1.0 - wt64(0)) * rho * eqs : wt64(i) * rho * eqs;
 }
+// The model's equilibrium at rest, r_i = w_i + eq_adjust(i, 1): the centre
+// of the shifted storage (Centre in step.h); w_i for Eq. 2.
+__device__ __forceinline__ double centre64(int i, double eqs) { return wt64(i) + eq_adjust(i, 1.0, eqs); }
+// Eq. 2 (with the model's shift), returned as feq_i - r_i (accurate for the
+// shifted forms): eq_adjust is linear in rho, so its part is eq_adjust(rho - 1).
 __device__ __forceinline__ double dfeq(int i, double rho, double ux, double uy, double eqs)
 {
     const double eu = kEX[i] * ux + kEY[i] * uy;
     const double usq = ux * ux + uy * uy;
-    return wt64(i) * ((rho - 1.0) + rho * (3.0 * eu + 4.5 * eu * eu - 1.5 * usq)) + eq_adjust(i, rho, eqs);
+    return wt64(i) * ((rho - 1.0) + rho * (3.0 * eu + 4.5 * eu * eu - 1.5 * usq)) + eq_adjust(i, rho - 1.0, eqs);
 }
 __device__ __forceinline__ double feq(int i, double rho, double ux, double uy, double eqs)
 {
@@ -208,14 +213,14 @@ __device__ __forceinline__ double feq(int i, double rho, double ux, double uy, d
     return wt64(i) * rho * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * usq) + eq_adjust(i, rho, eqs);
 }
 
-template <class T, bool SHIFT> __device__ __forceinline__ T store_f64(double f, int i)
+template <class T, bool SHIFT> __device__ __forceinline__ T store_f64(double f, int i, double eqs)
 {
-    if constexpr (SHIFT) return (T)(f - wt64(i));
+    if constexpr (SHIFT) return (T)(f - centre64(i, eqs));
     else return (T)f;
 }
-template <class T, bool SHIFT> __device__ __forceinline__ double load_f64(T v, int i)
+template <class T, bool SHIFT> __device__ __forceinline__ double load_f64(T v, int i, double eqs)
 {
-    if constexpr (SHIFT) return (double)v + wt64(i);
+    if constexpr (SHIFT) return (double)v + centre64(i, eqs);
     else return (double)v;
 }
 
@@ -256,37 +261,40 @@ __global__ void init_kernel(T* __restrict__ s, Geom g, const double* __restrict_
 }
 
 // S_i(x) = f_i(x + e_i), x in [-2, nx + 1], from a canonical FP64 array [9][ny][nx].
-template <class T, bool SHIFT> __global__ void set_f_kernel(T* __restrict__ s, Geom g, const double* __restrict__ f)
+template <class T, bool SHIFT>
+__global__ void set_f_kernel(T* __restrict__ s, Geom g, const double* __restrict__ f, double eqs)
 {
     const RowIdx ri = row_idx(g, g.nx + 4);
     if (!ri.ok) return;
     const int i = ri.i, y = ri.y, xx = ri.col - 2;  // -2 .. nx + 1
     const int sx = wrapx2(xx + kEX[i], g.nx), sy = wrapy(y + kEY[i], g.ny);
     s[i * g.ps + (long long)y * g.rs + g.off + xx] =
-        store_f64<T, SHIFT>(f[((long long)i * g.ny + sy) * g.nx + sx], i);
+        store_f64<T, SHIFT>(f[((long long)i * g.ny + sy) * g.nx + sx], i, eqs);
 }
 
 // f_i(x) = S_i(x - e_i) into a canonical FP64 array [9][ny][nx].
-template <class T, bool SHIFT> __global__ void get_f_kernel(const T* __restrict__ s, Geom g, double* __restrict__ f)
+template <class T, bool SHIFT>
+__global__ void get_f_kernel(const T* __restrict__ s, Geom g, double* __restrict__ f, double eqs)
 {
     const RowIdx ri = row_idx(g, g.nx);
     if (!ri.ok) return;
     const int i = ri.i, y = ri.y, xx = ri.col;
     const int sy = wrapy(y - kEY[i], g.ny), sx = wrapx2(xx - kEX[i], g.nx);
-    f[((long long)i * g.ny + y) * g.nx + xx] = load_f64<T, SHIFT>(s[i * g.ps + (long long)sy * g.rs + g.off + sx], i);
+    f[((long long)i * g.ny + y) * g.nx + xx] =
+        load_f64<T, SHIFT>(s[i * g.ps + (long long)sy * g.rs + g.off + sx], i, eqs);
 }
 
 // f_i at n listed sites into out[n][9].
 template <class T, bool SHIFT>
 __global__ void sample_f_kernel(const T* __restrict__ s, Geom g, int n, const int* __restrict__ xy,
-                                double* __restrict__ out)
+                                double* __restrict__ out, double eqs)
 {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= 9 * n) return;
     const int k = q / 9, i = q - 9 * k;
     const int x = xy[2 * k], y = xy[2 * k + 1];
     const int sy = wrapy(y - kEY[i], g.ny), sx = wrapx2(x - kEX[i], g.nx);
-    out[q] = load_f64<T, SHIFT>(s[i * g.ps + (long long)sy * g.rs + g.off + sx], i);
+    out[q] = load_f64<T, SHIFT>(s[i * g.ps + (long long)sy * g.rs + g.off + sx], i, eqs);
 }
 
 // Moments (Eq. 3) of f(x, t) in FP64, optional fields, and per-block
@@ -535,28 +543,28 @@ hipError_t launch_init(int dtype, void* s, const Geom& g, const double* rho, con
     })
 }
 
-hipError_t launch_set_f(int dtype, void* s, const Geom& g, const double* f, hipStream_t st)
+hipError_t launch_set_f(int dtype, void* s, const Geom& g, const double* f, double eqs, hipStream_t st)
 {
     LBM_DISPATCH(dtype, {
-        hipLaunchKernelGGL((set_f_kernel<T, S>), plane_rows_grid(g, 4), dim3(256), 0, st, (T*)s, g, f);
+        hipLaunchKernelGGL((set_f_kernel<T, S>), plane_rows_grid(g, 4), dim3(256), 0, st, (T*)s, g, f, eqs);
         return hipGetLastError();
     })
 }
 
-hipError_t launch_get_f(int dtype, const void* s, const Geom& g, double* f, hipStream_t st)
+hipError_t launch_get_f(int dtype, const void* s, const Geom& g, double* f, double eqs, hipStream_t st)
 {
     LBM_DISPATCH(dtype, {
-        hipLaunchKernelGGL((get_f_kernel<T, S>), plane_rows_grid(g, 0), dim3(256), 0, st, (const T*)s, g, f);
+        hipLaunchKernelGGL((get_f_kernel<T, S>), plane_rows_grid(g, 0), dim3(256), 0, st, (const T*)s, g, f, eqs);
         return hipGetLastError();
     })
 }
 
-hipError_t launch_sample_f(int dtype, const void* s, const Geom& g, int n, const int* xy, double* out,
+hipError_t launch_sample_f(int dtype, const void* s, const Geom& g, int n, const int* xy, double* out, double eqs,
                            hipStream_t st)
 {
     const dim3 grid((unsigned)((9LL * n + 255) / 256));
     LBM_DISPATCH(dtype, {
-        hipLaunchKernelGGL((sample_f_kernel<T, S>), grid, dim3(256), 0, st, (const T*)s, g, n, xy, out);
+        hipLaunchKernelGGL((sample_f_kernel<T, S>), grid, dim3(256), 0, st, (const T*)s, g, n, xy, out, eqs);
         return hipGetLastError();
     })
 }

@@ -427,7 +427,7 @@ int lbm_pool_get_f(lbm_pool* P, int slot, double* f)
     const size_t n = (size_t)9 * S->nx * S->ny;
     DevScratch d;
     hipError_t e = d.alloc(n);
-    if (e == hipSuccess) e = launch_get_f(P->dtype, cur_buf(*S), S->g, d.p, P->stream);
+    if (e == hipSuccess) e = launch_get_f(P->dtype, cur_buf(*S), S->g, d.p, 0.0, P->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(f, d.p, n * sizeof(double), hipMemcpyDeviceToHost, P->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(P->stream);
     return status_of(e);

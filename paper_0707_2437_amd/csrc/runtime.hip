@@ -301,6 +301,17 @@ int lbm_init_device(lbm_lattice* L, const double* rho, const double* ux, const d
 int lbm_set_model(lbm_lattice* L, int model)
 {
     if (!L || !model_ok(model, L->c2) || (L->field && model != LBM_MODEL_FORCING)) return LBM_EINVAL;
+    const double old_shift = eq_shift(L->c2, L->model), new_shift = eq_shift(L->c2, model);
+    if (L->ready && new_shift != old_shift && (L->dtype == LBM_F32S || L->dtype == LBM_F16S)) {
+        // The shifted storage is centred on the model's state at rest: keep
+        // f by reading it with the old centre and storing it with the new.
+        DevScratch d;
+        hipError_t e = d.alloc((size_t)9 * L->nx * L->ny);
+        if (e == hipSuccess) e = launch_get_f(L->dtype, L->cur, L->g, d.p, old_shift, L->stream);
+        if (e == hipSuccess) e = launch_set_f(L->dtype, L->cur, L->g, d.p, new_shift, L->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+        if (e != hipSuccess) return status_of(e);
+    }
     L->model = model;
     L->coef = make_coef(L->tau, L->c2, model);
     return LBM_OK;
@@ -433,7 +444,7 @@ int lbm_get_f(lbm_lattice* L, double* f)
     const size_t n = (size_t)9 * L->nx * L->ny;
     DevScratch d;
     hipError_t e = d.alloc(n);
-    if (e == hipSuccess) e = launch_get_f(L->dtype, L->cur, L->g, d.p, L->stream);
+    if (e == hipSuccess) e = launch_get_f(L->dtype, L->cur, L->g, d.p, eq_shift(L->c2, L->model), L->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(f, d.p, n * sizeof(double), hipMemcpyDeviceToHost, L->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
     return status_of(e);
@@ -457,7 +468,7 @@ int lbm_sample_f(lbm_lattice* L, int n, const int* xs, const int* ys, double* f)
     int* dxy = (int*)(d.p + (size_t)9 * n);
     if (e == hipSuccess)
         e = hipMemcpyAsync(dxy, hxy, sizeof(int) * 2 * (size_t)n, hipMemcpyHostToDevice, L->stream);
-    if (e == hipSuccess) e = launch_sample_f(L->dtype, L->cur, L->g, n, dxy, d.p, L->stream);
+    if (e == hipSuccess) e = launch_sample_f(L->dtype, L->cur, L->g, n, dxy, d.p, eq_shift(L->c2, L->model), L->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(f, d.p, sizeof(double) * 9 * (size_t)n, hipMemcpyDeviceToHost, L->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
     std::free(hxy);
@@ -471,7 +482,7 @@ int lbm_set_f(lbm_lattice* L, const double* f)
     DevScratch d;
     hipError_t e = d.alloc(n);
     if (e == hipSuccess) e = hipMemcpyAsync(d.p, f, n * sizeof(double), hipMemcpyHostToDevice, L->stream);
-    if (e == hipSuccess) e = launch_set_f(L->dtype, L->cur, L->g, d.p, L->stream);
+    if (e == hipSuccess) e = launch_set_f(L->dtype, L->cur, L->g, d.p, eq_shift(L->c2, L->model), L->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
     if (e != hipSuccess) return status_of(e);
     L->t = 0;

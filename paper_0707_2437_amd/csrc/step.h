@@ -39,13 +39,29 @@ template <class C> __device__ __forceinline__ C wt(int i)
 
 __device__ __forceinline__ int wrapy(int r, int ny) { return r < 0 ? r + ny : (r >= ny ? r - ny : r); }
 
-// Stored value -> d_i = f_i - w_i in compute precision, and back.
-template <class T, bool SHIFT, class C> __device__ __forceinline__ C to_d(T v, int i)
+// The state the arithmetic is centred on: d_i = f_i - r_i. FP32 arithmetic
+// (and the shifted storage, which it reads as is) centres on the lattice
+// model's equilibrium at rest (rho = 1, u = 0), r_i = w_i (1 + e): e = 0 for
+// Eq. 2 (r_i = w_i), e = 3 c^2 - 1 (moving) and -(5/4)(3 c^2 - 1) (rest) for
+// the altered-equilibrium model, whose populations at small c^2 sit far from
+// the weights; keeping d small next to f is what FP32 needs. FP64
+// arithmetic centres on the weights, r_i = w_i, for both models. Either way
+// sum_i r_i = 1 and sum_i r_i e_i = 0, so rho = 1 + sum_i d_i and
+// rho u = sum_i d_i e_i.
+template <class C> struct ModelCentred { static constexpr bool value = sizeof(C) == sizeof(float); };
+template <class C> struct Centre {
+    C r0, r1, r2;
+    __device__ __forceinline__ C at(int i) const { return i == 0 ? r0 : (i < 5 ? r1 : r2); }
+};
+
+// Stored value -> d_i = f_i - r_i in compute precision, and back (shifted
+// storage already holds d_i).
+template <class T, bool SHIFT, class C> __device__ __forceinline__ C to_d(T v, int i, const Centre<C>& cn)
 {
     if constexpr (SHIFT) return (C)v;
-    else return (C)v - wt<C>(i);
+    else return (C)v - cn.at(i);
 }
-template <class T, bool SHIFT, class C> __device__ __forceinline__ T from_d(C d, int i)
+template <class T, bool SHIFT, class C> __device__ __forceinline__ T from_d(C d, int i, const Centre<C>& cn)
 {
     if constexpr (sizeof(T) < sizeof(C)) {
         // The relaxed value is rounded to FP32 and then to the storage type.
@@ -56,7 +72,7 @@ template <class T, bool SHIFT, class C> __device__ __forceinline__ T from_d(C d,
         asm("" : "+v"(d));
     }
     if constexpr (SHIFT) return (T)d;
-    else return (T)(wt<C>(i) + d);
+    else return (T)(cn.at(i) + d);
 }
 
 // Compile-time loop: f(std::integral_constant<int, I>) for I = B .. E - 1.
@@ -176,14 +192,15 @@ template <> __device__ __forceinline__ float recip<float>(float r) { return __bu
 // the registers) and converted where it is used.
 template <class T, class C> using KeepT = typename std::conditional<(sizeof(T) < sizeof(C)), T, C>::type;
 
-template <class T, bool SHIFT, class C> __device__ __forceinline__ KeepT<T, C> keep_of(T v, int i)
+template <class T, bool SHIFT, class C>
+__device__ __forceinline__ KeepT<T, C> keep_of(T v, int i, const Centre<C>& cn)
 {
     if constexpr (sizeof(T) < sizeof(C)) return v;
-    else return to_d<T, SHIFT, C>(v, i);
+    else return to_d<T, SHIFT, C>(v, i, cn);
 }
-template <class T, bool SHIFT, class C> __device__ __forceinline__ C d_of(KeepT<T, C> v, int i)
+template <class T, bool SHIFT, class C> __device__ __forceinline__ C d_of(KeepT<T, C> v, int i, const Centre<C>& cn)
 {
-    if constexpr (sizeof(T) < sizeof(C)) return to_d<T, SHIFT, C>(v, i);
+    if constexpr (sizeof(T) < sizeof(C)) return to_d<T, SHIFT, C>(v, i, cn);
     else return v;
 }
 
@@ -280,11 +297,12 @@ template <class C> struct ColF {
     __device__ __forceinline__ C fma(C m, int a, C c) const { return fmac(m, d[a], c); }
 };
 
-template <class T, bool SHIFT, class C, int VX> __device__ __forceinline__ ColF<C> col_of(const KeepT<T, C> d[9][VX], int j)
+template <class T, bool SHIFT, class C, int VX>
+__device__ __forceinline__ ColF<C> col_of(const KeepT<T, C> d[9][VX], int j, const Centre<C>& cn)
 {
     ColF<C> v;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) v.d[i] = d_of<T, SHIFT, C>(d[i][j], i);
+    for (int i = 0; i < 9; ++i) v.d[i] = d_of<T, SHIFT, C>(d[i][j], i, cn);
     return v;
 }
 
@@ -294,9 +312,10 @@ template <class V> __device__ __forceinline__ auto drho_col(const V& v)
     return v.plus(8, (v.add(0, 1) + v.add(2, 3)) + (v.add(4, 5) + v.add(6, 7)));
 }
 
-template <class T, bool SHIFT, class C, int VX> __device__ __forceinline__ C drho_of(const KeepT<T, C> d[9][VX], int j)
+template <class T, bool SHIFT, class C, int VX>
+__device__ __forceinline__ C drho_of(const KeepT<T, C> d[9][VX], int j, const Centre<C>& cn)
 {
-    return drho_col(col_of<T, SHIFT, C, VX>(d, j));
+    return drho_col(col_of<T, SHIFT, C, VX>(d, j, cn));
 }
 
 template <class C> struct CoefC {
@@ -310,6 +329,15 @@ template <class C> __device__ __forceinline__ CoefC<C> coef_c(const Coef& k)
     else return CoefC<C>{k.om1, k.wo0, k.wo1, k.wo2, k.as1, k.as2, k.e1, k.e0};
 }
 
+// The centre in compute precision (see Centre): w_i (1 + e) for FP32, which
+// is w_i itself for the paper's model (e = 0); w_i for FP64.
+template <class C> __device__ __forceinline__ Centre<C> centre_c(const CoefC<C>& k)
+{
+    if constexpr (ModelCentred<C>::value)
+        return Centre<C>{wt<C>(0) * (C(1) + k.e0), wt<C>(1) * (C(1) + k.e1), wt<C>(5) * (C(1) + k.e1)};
+    else return Centre<C>{wt<C>(0), wt<C>(1), wt<C>(5)};
+}
+
 // Eq. 5 right-hand side in delta form for one site.
 //   rho = 1 + drho, u = j / rho (Eq. 3)
 //   feq_i - w_i = w_i [drho + rho (3 e.u + 9/2 (e.u)^2 - 3/2 u.u)]      (Eq. 2)
@@ -320,8 +348,10 @@ template <class C> __device__ __forceinline__ CoefC<C> coef_c(const Coef& k)
 // For a link pair (i, opp) with e_opp = -e_i, write A = drho - 3/2 rho u.u,
 // sym = A + 9/2 rho (e.u)^2, P = om w sym, Q = om w 3 rho (e.u) + as (e.D):
 //   d*_i = (1 - om) d_i + P + Q,  d*_opp = (1 - om) d_opp + P - Q.
-// The altered-equilibrium model (as = 0) uses A + rho e1 in sym and
-// A + rho e0 for the rest population (Coef).
+// The altered-equilibrium model (as = 0): its feq_i - w_i is
+// w_i [drho + rho e + rho (3 e.u + 9/2 (e.u)^2 - 3/2 u.u)], so sym uses
+// A + rho e1 and the rest population A + rho e0 (Coef); centred on its own
+// state at rest (FP32, see Centre) the shift is drho e instead of rho e.
 template <class V, class C>
 __device__ __forceinline__ void collide_col(const V& v, C drho, C gx, C gy, const CoefC<C>& k, C o[9])
 {
@@ -334,7 +364,8 @@ __device__ __forceinline__ void collide_col(const V& v, C drho, C gx, C gy, cons
     const C A = fmac(C(-1.5) * rho, usq, drho);
     // equilibrium shifts of the altered-equilibrium model (exactly A when
     // e1 = e0 = 0, the paper's model)
-    const C Ap = fmac(rho, k.e1, A), A0 = fmac(rho, k.e0, A);
+    const C es = ModelCentred<C>::value ? drho : rho;
+    const C Ap = fmac(es, k.e1, A), A0 = fmac(es, k.e0, A);
     const C r45 = C(4.5) * rho, r3 = C(3) * rho;
     o[0] = v.fma(k.om1, 0, k.wo0 * A0);
     auto pair = [&](int i, int io, C eu, C eg, C wo, C as) {
@@ -351,9 +382,9 @@ __device__ __forceinline__ void collide_col(const V& v, C drho, C gx, C gy, cons
 
 template <class T, bool SHIFT, class C, int VX>
 __device__ __forceinline__ void collide(const KeepT<T, C> dk[9][VX], int j, C drho, C gx, C gy, const CoefC<C>& k,
-                                        C o[9])
+                                        const Centre<C>& cn, C o[9])
 {
-    collide_col(col_of<T, SHIFT, C, VX>(dk, j), drho, gx, gy, k, o);
+    collide_col(col_of<T, SHIFT, C, VX>(dk, j, cn), drho, gx, gy, k, o);
 }
 
 // ---------------------------------------------------------------------------
@@ -622,6 +653,8 @@ __device__ __forceinline__ void vstack_tile_f(const StepTile& a, const void* src
     K d[9][VX];
     C w[WV];
     Pack<C, VX> af{};
+    const CoefC<C> k = coef_c<C>(a.c);
+    const Centre<C> cn = centre_c<C>(k);
     if (active) {
         Rw raw[9];
         gather_raw<T, WV, T, WV, EDGE>(sb, g, y, x, raw);
@@ -631,9 +664,9 @@ __device__ __forceinline__ void vstack_tile_f(const StepTile& a, const void* src
 #pragma unroll
         for (int i = 0; i < 9; ++i)
 #pragma unroll
-            for (int j = 0; j < WV; ++j) tmp[i][j] = keep_of<T, SHIFT, C>(raw[i].v[j], i);
+            for (int j = 0; j < WV; ++j) tmp[i][j] = keep_of<T, SHIFT, C>(raw[i].v[j], i, cn);
 #pragma unroll
-        for (int j = 0; j < WV; ++j) w[j] = drho_of<T, SHIFT, C, WV>(tmp, j);
+        for (int j = 0; j < WV; ++j) w[j] = drho_of<T, SHIFT, C, WV>(tmp, j, cn);
 #pragma unroll
         for (int i = 0; i < 9; ++i)
 #pragma unroll
@@ -643,7 +676,6 @@ __device__ __forceinline__ void vstack_tile_f(const StepTile& a, const void* src
     }
     __syncthreads();
     if (active && wave >= 1 && wave <= nrows) {
-        const CoefC<C> k = coef_c<C>(a.c);
         Pack<T, VX> out[9];
 #pragma unroll
         for (int j = 0; j < VX; ++j) {
@@ -651,9 +683,9 @@ __device__ __forceinline__ void vstack_tile_f(const StepTile& a, const void* src
             const C gx = w[j + 2] - w[j];
             const C gy = lds[wave + 1][lane * VX + j] - lds[wave - 1][lane * VX + j];
             C o[9];
-            collide<T, SHIFT, C, VX>(d, j, w[j + 1], gx, gy, site_coef<FIELD>(k, af.v[j]), o);
+            collide<T, SHIFT, C, VX>(d, j, w[j + 1], gx, gy, site_coef<FIELD>(k, af.v[j]), cn, o);
 #pragma unroll
-            for (int i = 0; i < 9; ++i) out[i].v[j] = from_d<T, SHIFT, C>(o[i], i);
+            for (int i = 0; i < 9; ++i) out[i].v[j] = from_d<T, SHIFT, C>(o[i], i, cn);
         }
         write_row<T, VX, NTS>(dbase, g, y, x, nv, out);
     }

@@ -41,13 +41,17 @@ def sample_sites(seed=0):
     return np.array(xs), np.array(ys)
 
 
-def window_oracle(fields, xc, yc, c2, steps):
+def window_oracle(fields, xc, yc, c2, steps, model=oracle.MODEL_FORCING, c2_field=None):
+    """The oracle's value at (xc, yc) after `steps` steps, from a periodic
+    window cut from the same initial fields (and c2 field, which is local)."""
     R = 2 * steps + 2
     idx_y = (yc + np.arange(-R, R + 1)) % N
     idx_x = (xc + np.arange(-R, R + 1)) % N
     sub = [None if f is None else f[np.ix_(idx_y, idx_x)] for f in fields]
-    o = oracle.Oracle(2 * R + 1, 2 * R + 1, TAU, c2).init(*sub).step(steps)
-    return o.get_f()[:, R, R]
+    o = oracle.Oracle(2 * R + 1, 2 * R + 1, TAU, c2, model=model)
+    if c2_field is not None:
+        o.set_c2_field(c2_field[np.ix_(idx_y, idx_x)])
+    return o.init(*sub).step(steps).get_f()[:, R, R]
 
 
 @pytest.mark.parametrize("c2", [0.04, 0.81])
@@ -62,6 +66,39 @@ def test_sampled_sites_match_windowed_oracle(dtype, c2):
     want = np.array([window_oracle(fields, x, y, c2, steps) for x, y in zip(xs, ys)])
     err = max_rel_err(got, want)
     print(f"{dtype} c2={c2}: max rel err over {len(xs)} sampled sites after {steps} steps = {err:.3e}")
+    assert err <= TOL[dtype]
+
+
+@pytest.mark.parametrize("c2", [0.04, 0.56])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_sampled_sites_equilibrium_model(dtype, c2):
+    """The benchmark's altered-equilibrium form (its c^2 sweep ends at 0.56)."""
+    steps = 25
+    fields = workloads.plane_wave_fields(N, N, c2, seed=5)
+    xs, ys = sample_sites(1)
+    with lbm.Lattice(N, N, TAU, c2, dtype, model=lbm.MODEL_EQUILIBRIUM) as L:
+        got = L.init(*fields).step(steps).sample_f(xs, ys)
+    want = np.array([window_oracle(fields, x, y, c2, steps, model=oracle.MODEL_EQUILIBRIUM)
+                     for x, y in zip(xs, ys)])
+    err = max_rel_err(got, want)
+    print(f"equilibrium model {dtype} c2={c2}: max rel err over {len(xs)} sampled sites = {err:.3e}")
+    assert err <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_sampled_sites_c2_field(dtype):
+    """The benchmark's c^2-field form: a lens-shaped field (depth 0.5) around c^2 = 0.5."""
+    steps, c2 = 25, 0.5
+    fields = workloads.plane_wave_fields(N, N, c2, seed=6)
+    c2f = workloads.lens_c2_field(N, N, c2, depth=0.5)
+    xs, ys = sample_sites(2)
+    xs = np.append(xs, [N // 2, N // 2 + 1])  # the lens centre
+    ys = np.append(ys, [N // 2, N // 2 - 300])
+    with lbm.Lattice(N, N, TAU, c2, dtype) as L:
+        got = L.set_c2_field(c2f).init(*fields).step(steps).sample_f(xs, ys)
+    want = np.array([window_oracle(fields, x, y, c2, steps, c2_field=c2f) for x, y in zip(xs, ys)])
+    err = max_rel_err(got, want)
+    print(f"c2 field {dtype}: max rel err over {len(xs)} sampled sites = {err:.3e}")
     assert err <= TOL[dtype]
 
 
