@@ -31,7 +31,9 @@ __device__ __forceinline__ bool batch_item(const BatchLat* __restrict__ lats, co
     const int t1 = min(t0 + L.per_item, L.ntiles);
     for (int t = t0; t < t1; ++t) {
         if (t > t0) __syncthreads();  // lds of the previous tile is still being read
-        vstack_tile<T, SHIFT, VX, NW, NTS>(L.tile, src, dst, t % L.tile.nstrips, t / L.tile.nstrips, lds);
+        // pools step the paper's model: centred on the weights (see Centre)
+        vstack_tile<T, SHIFT, VX, NW, NTS, false, false>(L.tile, src, dst, t % L.tile.nstrips, t / L.tile.nstrips,
+                                                         lds);
     }
     return true;
 }

@@ -70,7 +70,7 @@ __global__ __launch_bounds__(64 * NW) void step_kernel(StepTile a, int ntiles)
     const int nv = min(VX, g.nx - x);
     if (nv <= 0) return;  // no barrier below: lanes past the edge simply leave
     const CoefC<C> k = coef_c<C>(a.c);
-    const Centre<C> cn = centre_c<C>(k);
+    const Centre<C> cn = centre_c<C>(a.c);
     const int ylo = chunk * a.h;
     const int yhi = min(ylo + a.h, g.ny);
     const int dir = (chunk & 1) ? -1 : 1;  // alternate chunks march upward

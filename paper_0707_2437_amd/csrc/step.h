@@ -47,7 +47,10 @@ __device__ __forceinline__ int wrapy(int r, int ny) { return r < 0 ? r + ny : (r
 // the weights; keeping d small next to f is what FP32 needs. FP64
 // arithmetic centres on the weights, r_i = w_i, for both models. Either way
 // sum_i r_i = 1 and sum_i r_i e_i = 0, so rho = 1 + sum_i d_i and
-// rho u = sum_i d_i e_i.
+// rho u = sum_i d_i e_i. The batched kernels, whose lattices all step the
+// paper's model (r_i = w_i), centre on the weights at every precision
+// (their coefficients sit behind two dependent loads, and the weights are
+// compile-time constants); RC below selects the centring.
 template <class C> struct ModelCentred { static constexpr bool value = sizeof(C) == sizeof(float); };
 template <class C> struct Centre {
     C r0, r1, r2;
@@ -331,11 +334,16 @@ template <class C> __device__ __forceinline__ CoefC<C> coef_c(const Coef& k)
 
 // The centre in compute precision (see Centre): w_i (1 + e) for FP32, which
 // is w_i itself for the paper's model (e = 0); w_i for FP64.
-template <class C> __device__ __forceinline__ Centre<C> centre_c(const CoefC<C>& k)
+// Only the model's shifts are read, so the centre is all a tile holds of
+// the coefficients while its loads are in flight.
+template <class C, bool RC = ModelCentred<C>::value> __device__ __forceinline__ Centre<C> centre_c(const Coef& c)
 {
-    if constexpr (ModelCentred<C>::value)
+    if constexpr (RC) {
+        const CoefC<C> k = coef_c<C>(c);
         return Centre<C>{wt<C>(0) * (C(1) + k.e0), wt<C>(1) * (C(1) + k.e1), wt<C>(5) * (C(1) + k.e1)};
-    else return Centre<C>{wt<C>(0), wt<C>(1), wt<C>(5)};
+    } else {
+        return Centre<C>{wt<C>(0), wt<C>(1), wt<C>(5)};
+    }
 }
 
 // Eq. 5 right-hand side in delta form for one site.
@@ -352,7 +360,7 @@ template <class C> __device__ __forceinline__ Centre<C> centre_c(const CoefC<C>&
 // w_i [drho + rho e + rho (3 e.u + 9/2 (e.u)^2 - 3/2 u.u)], so sym uses
 // A + rho e1 and the rest population A + rho e0 (Coef); centred on its own
 // state at rest (FP32, see Centre) the shift is drho e instead of rho e.
-template <class V, class C>
+template <bool RC, class V, class C>
 __device__ __forceinline__ void collide_col(const V& v, C drho, C gx, C gy, const CoefC<C>& k, C o[9])
 {
     const C jx = (v.sub(1, 3) + v.sub(5, 6)) + v.sub(8, 7);
@@ -364,7 +372,7 @@ __device__ __forceinline__ void collide_col(const V& v, C drho, C gx, C gy, cons
     const C A = fmac(C(-1.5) * rho, usq, drho);
     // equilibrium shifts of the altered-equilibrium model (exactly A when
     // e1 = e0 = 0, the paper's model)
-    const C es = ModelCentred<C>::value ? drho : rho;
+    const C es = RC ? drho : rho;
     const C Ap = fmac(es, k.e1, A), A0 = fmac(es, k.e0, A);
     const C r45 = C(4.5) * rho, r3 = C(3) * rho;
     o[0] = v.fma(k.om1, 0, k.wo0 * A0);
@@ -380,11 +388,11 @@ __device__ __forceinline__ void collide_col(const V& v, C drho, C gx, C gy, cons
     pair(6, 8, uy - ux, gy - gx, k.wo2, k.as2);
 }
 
-template <class T, bool SHIFT, class C, int VX>
+template <class T, bool SHIFT, class C, int VX, bool RC = ModelCentred<C>::value>
 __device__ __forceinline__ void collide(const KeepT<T, C> dk[9][VX], int j, C drho, C gx, C gy, const CoefC<C>& k,
                                         const Centre<C>& cn, C o[9])
 {
-    collide_col(col_of<T, SHIFT, C, VX>(dk, j, cn), drho, gx, gy, k, o);
+    collide_col<RC>(col_of<T, SHIFT, C, VX>(dk, j, cn), drho, gx, gy, k, o);
 }
 
 // ---------------------------------------------------------------------------
@@ -557,7 +565,7 @@ template <bool FIELD, class C> __device__ __forceinline__ CoefC<C> site_coef(con
 // summation orders and roundings, with the populations kept as the packed
 // halves they were loaded as (see ColH) and the results rounded to FP16 two
 // at a time.
-template <int VX, int NW, bool NTS, bool EDGE, bool FIELD>
+template <int VX, int NW, bool NTS, bool EDGE, bool FIELD, bool RC>
 __device__ __forceinline__ void vstack_tile_h(const StepTile& a, const void* src, void* dst, int strip, int grp,
                                               float (&lds)[NW][64 * VX])
 {
@@ -608,7 +616,7 @@ __device__ __forceinline__ void vstack_tile_h(const StepTile& a, const void* src
             // undivided central differences at time t (Sec. 4)
             const float gx = w[j + 2] - w[j];
             const float gy = lds[wave + 1][lane * VX + j] - lds[wave - 1][lane * VX + j];
-            collide_col(col_h<j + 1>(u), w[j + 1], gx, gy, site_coef<FIELD>(k, af.v[j]), o[j]);
+            collide_col<RC>(col_h<j + 1>(u), w[j + 1], gx, gy, site_coef<FIELD>(k, af.v[j]), o[j]);
         });
         Pack<T, VX> out[9];
 #pragma unroll
@@ -628,7 +636,7 @@ __device__ __forceinline__ void vstack_tile_h(const StepTile& a, const void* src
     }
 }
 
-template <class T, bool SHIFT, int VX, int NW, bool NTS, bool EDGE, bool FIELD>
+template <class T, bool SHIFT, int VX, int NW, bool NTS, bool EDGE, bool FIELD, bool RC>
 __device__ __forceinline__ void vstack_tile_f(const StepTile& a, const void* src, void* dst, int strip, int grp,
                                               typename CompT<T>::type (&lds)[NW][64 * VX])
 {
@@ -653,8 +661,7 @@ __device__ __forceinline__ void vstack_tile_f(const StepTile& a, const void* src
     K d[9][VX];
     C w[WV];
     Pack<C, VX> af{};
-    const CoefC<C> k = coef_c<C>(a.c);
-    const Centre<C> cn = centre_c<C>(k);
+    const Centre<C> cn = centre_c<C, RC>(a.c);
     if (active) {
         Rw raw[9];
         gather_raw<T, WV, T, WV, EDGE>(sb, g, y, x, raw);
@@ -676,6 +683,7 @@ __device__ __forceinline__ void vstack_tile_f(const StepTile& a, const void* src
     }
     __syncthreads();
     if (active && wave >= 1 && wave <= nrows) {
+        const CoefC<C> k = coef_c<C>(a.c);
         Pack<T, VX> out[9];
 #pragma unroll
         for (int j = 0; j < VX; ++j) {
@@ -683,7 +691,7 @@ __device__ __forceinline__ void vstack_tile_f(const StepTile& a, const void* src
             const C gx = w[j + 2] - w[j];
             const C gy = lds[wave + 1][lane * VX + j] - lds[wave - 1][lane * VX + j];
             C o[9];
-            collide<T, SHIFT, C, VX>(d, j, w[j + 1], gx, gy, site_coef<FIELD>(k, af.v[j]), cn, o);
+            collide<T, SHIFT, C, VX, RC>(d, j, w[j + 1], gx, gy, site_coef<FIELD>(k, af.v[j]), cn, o);
 #pragma unroll
             for (int i = 0; i < 9; ++i) out[i].v[j] = from_d<T, SHIFT, C>(o[i], i, cn);
         }
@@ -706,19 +714,22 @@ __device__ __forceinline__ void vstack_tile_f(const StepTile& a, const void* src
 // their loads and start the arithmetic as the loads land, with no patch code
 // in between. The branch is uniform over the workgroup.
 // FIELD: the source coefficients come per site from a.field (a c2 field);
-// the interior waves load them with their windows.
-template <class T, bool SHIFT, int VX, int NW, bool NTS, bool FIELD = false>
+// the interior waves load them with their windows. RC: centre the
+// arithmetic on the lattice model's state at rest (see Centre); the batched
+// kernels (paper's model only) pass false.
+template <class T, bool SHIFT, int VX, int NW, bool NTS, bool FIELD = false,
+          bool RC = ModelCentred<typename CompT<T>::type>::value>
 __device__ __forceinline__ void vstack_tile(const StepTile& a, const void* src, void* dst, int strip, int grp,
                                             typename CompT<T>::type (&lds)[NW][64 * VX])
 {
     if constexpr (std::is_same<T, _Float16>::value) {
         static_assert(SHIFT, "FP16 storage is the shifted form");
         static_assert(GhostCols<T>::value, "FP16 rows carry ghost columns");
-        vstack_tile_h<VX, NW, NTS, false, FIELD>(a, src, dst, strip, grp, lds);
+        vstack_tile_h<VX, NW, NTS, false, FIELD, RC>(a, src, dst, strip, grp, lds);
     } else {
         const bool edge = strip == 0 || (strip + 1) * (64 * VX) + 2 > a.g.nx;
-        if (edge) vstack_tile_f<T, SHIFT, VX, NW, NTS, true, FIELD>(a, src, dst, strip, grp, lds);
-        else vstack_tile_f<T, SHIFT, VX, NW, NTS, false, FIELD>(a, src, dst, strip, grp, lds);
+        if (edge) vstack_tile_f<T, SHIFT, VX, NW, NTS, true, FIELD, RC>(a, src, dst, strip, grp, lds);
+        else vstack_tile_f<T, SHIFT, VX, NW, NTS, false, FIELD, RC>(a, src, dst, strip, grp, lds);
     }
 }
 
