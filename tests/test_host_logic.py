@@ -1,0 +1,83 @@
+"""Host-side logic that needs no GPU: the benchmark's command line and form
+names, the seeded input generators (which hold none of the method's
+arithmetic), and the served form's job stream."""
+import math
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+from paper_0707_2437_amd import serve, workloads  # noqa: E402
+
+
+def test_bench_refuses_more_than_one_gpu():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def test_bench_form_names_and_bytes():
+    assert bench.form_parts("f32") == ("f32", "")
+    assert bench.form_parts("f32_eq") == ("f32", "eq")
+    assert bench.form_parts("f64_field") == ("f64", "field")
+    # 9 loads + 9 stores of the storage type, plus the field's coefficient
+    assert bench.form_bytes_per_site("f32") == 72 and bench.form_bytes_per_site("f64") == 144
+    assert bench.form_bytes_per_site("f16s") == 36 and bench.form_bytes_per_site("f32_eq") == 72
+    assert bench.form_bytes_per_site("f32_field") == 76 and bench.form_bytes_per_site("f64_field") == 152
+    assert bench.kernel_name((2, 8, 8, 18), "f32_field") == "lbm::step_vstack_kernel<float,false,2,8,true,true>"
+    assert bench.kernel_name((2, 8, 8, 18), "f32_eq") == "lbm::step_vstack_kernel<float,false,2,8,true,false>"
+
+
+def test_c2_sweeps():
+    assert max(workloads.C2_SWEEP) == 0.81 and min(workloads.C2_SWEEP) == 0.04
+    assert max(workloads.C2_SWEEP_EQ) < 0.6  # the altered-equilibrium model's range
+
+
+def test_plane_wave_is_right_going():
+    rho, ux, uy = workloads.plane_wave_fields(64, 8, 0.25, amp=1e-3, noise=0.0)
+    assert uy is None and np.allclose(ux, 0.5 * (rho - 1.0), rtol=0, atol=1e-16)  # rounding of 1 + x
+    r1, _, _ = workloads.plane_wave_fields(64, 8, 0.25, seed=3)
+    r2, _, _ = workloads.plane_wave_fields(64, 8, 0.25, seed=3)
+    assert np.array_equal(r1, r2)
+
+
+def test_simple_wave_riemann_invariant_is_zero():
+    rho, ux, _ = workloads.simple_wave_fields(400, 3, 0.04, 0.002)
+    assert np.max(np.abs(ux - 0.2 * np.log(rho))) < 1e-16  # rounding of exp and log
+    assert abs(np.max(ux) - 0.002) < 1e-9
+
+
+def test_lens_field():
+    f = workloads.lens_c2_field(96, 64, 0.5, depth=0.6)
+    assert f.shape == (64, 96)
+    assert abs(f.min() - 0.5 * 0.4) < 1e-12 and f.max() <= 0.5
+    g = workloads.lens_c2_field(96, 64, 0.5, depth=0.6, noise=0.05, seed=4)
+    assert np.all(np.abs(g / f - 1) <= 0.05) and len(np.unique(g)) > 0.9 * g.size
+
+
+def test_batch_specs():
+    a = workloads.batch_specs(256, seed=0)
+    assert a == workloads.batch_specs(256, seed=0)
+    assert all(64 <= s["nx"] <= 1024 and 64 <= s["ny"] <= 1024 for s in a)
+    assert all(0.55 <= s["tau"] <= 1.5 and 0.04 <= s["c2"] <= 0.6 for s in a)
+    assert sum(s["nx"] * s["ny"] for s in a) == 84833258  # the batched benchmark's sites
+
+
+def test_job_stream():
+    jobs = serve.job_stream(50.0, 30.0, seed=0)
+    assert jobs == serve.job_stream(50.0, 30.0, seed=0)
+    t = [j.arrival for j in jobs]
+    assert t == sorted(t) and 0 < t[0] and t[-1] <= 30.0
+    assert abs(len(jobs) - 1500) < 5 * math.sqrt(1500)  # Poisson count at 50 per second
+    assert all(j.nx == j.ny and 128 <= j.nx <= 2048 for j in jobs)
+    assert all(500 <= j.steps <= 20000 and 0.55 <= j.tau <= 1.5 and 0.04 <= j.c2 <= 0.6 for j in jobs)
+    assert serve.offered_mlups(jobs, 30.0) == pytest.approx(sum(j.sites * j.steps for j in jobs) / 30e6)
+    assert len(serve.job_stream(50.0, 30.0, seed=0, max_jobs=10)) == 10
