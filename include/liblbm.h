@@ -201,9 +201,10 @@ size_t lbm_footprint_bytes(int nx, int ny, int dtype);
  * workgroup covering one strip and nw - 2 rows (h is ignored). Default:
  * vertical stack with non-temporal stores; vx = 2 and nw = 8 for LBM_F64,
  * LBM_F32 and LBM_F32S, vx = 4 and nw = 8 for LBM_F16S. Results do not
- * depend on the shape (bitwise). LBM_EINVAL for an unsupported shape, or
- * for a march-form shape (no LBM_TILE_VSTACK) while the lattice has a c2
- * field.
+ * depend on the shape (bitwise). LBM_EINVAL for an unsupported shape, for
+ * a march-form shape (no LBM_TILE_VSTACK) while the lattice has a c2 field,
+ * or for a shape whose grid would exceed one dispatch (2^32 work items) on
+ * this lattice (only small shapes on the largest lattices).
  * lbm_get_tile: any pointer may be NULL. */
 enum lbm_tile_flags {
     LBM_TILE_PREFETCH = 1, /* issue the next row's loads before relaxing the current row */

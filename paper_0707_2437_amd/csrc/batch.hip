@@ -120,6 +120,7 @@ static hipError_t launch_batch_t(bool persistent, const BatchLat* lats, const in
     if (!persistent) {
         const int q = ch > 0 ? 8 * ch : 8;
         const int grid = (nitems + q - 1) / q * q;
+        if (!grid_fits(grid, 64 * NW)) return hipErrorInvalidConfiguration;
         hipLaunchKernelGGL((batch_step_kernel<T, SHIFT, VX, NW, NTS>), dim3(grid), dim3(64 * NW), 0, st, lats,
                            item_lat, nitems, s_or_n, ch);
         return hipGetLastError();

@@ -186,6 +186,7 @@ inline int status_of(hipError_t e)
 {
     if (e == hipSuccess) return LBM_OK;
     if (e == hipErrorOutOfMemory) return LBM_ENOMEM;
+    if (e == hipErrorInvalidConfiguration) return LBM_EINVAL;  // a grid too large for one dispatch
     return LBM_EDEVICE;
 }
 

@@ -66,6 +66,10 @@ struct StepTile {
     int fpitch;
 };
 
+// A dispatch's work-item count is 32-bit: launchers refuse a grid that
+// would exceed it (hipErrorInvalidConfiguration) rather than have it cut.
+inline bool grid_fits(long long blocks, int threads) { return blocks * threads <= 0xffffffffLL; }
+
 // The source coefficient of the axis links, as1 = 3 w_1 alpha / 2 with
 // alpha = 1/3 - c2 (Eq. 8; the diagonal links take as2 = as1 / 4, exactly,
 // since w_2 = w_1 / 4). One definition for the uniform coefficients and the

@@ -225,20 +225,20 @@ template <class T, bool SHIFT> __device__ __forceinline__ double load_f64(T v, i
 }
 
 // Element (i, y, xx) of a 1-D launch over 9 * ny rows of `w` columns.
-struct RowIdx {
-    int i, y, col;
-    bool ok;
-};
-__device__ __forceinline__ RowIdx row_idx(const Geom& g, int w)
+// Every element (i, y, col) of 9 * ny rows of w columns, by a grid-stride
+// loop: a large lattice has more elements than one dispatch may have work
+// items (the count is 32-bit), so the grid is capped (plane_rows_grid) and
+// each thread visits every (grid size)-th element.
+template <class F> __device__ __forceinline__ void for_each_row_elem(const Geom& g, int w, F&& f)
 {
-    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    RowIdx r;
-    const long long row = q / w;
-    r.ok = row < 9LL * g.ny;
-    r.col = (int)(q - row * w);
-    r.i = (int)(row / g.ny);
-    r.y = (int)(row - (long long)r.i * g.ny);
-    return r;
+    const long long n = 9LL * g.ny * w, stride = (long long)gridDim.x * blockDim.x;
+    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) {
+        const long long row = q / w;
+        const int col = (int)(q - row * w);
+        const int i = (int)(row / g.ny);
+        const int y = (int)(row - (long long)i * g.ny);
+        f(i, y, col);
+    }
 }
 
 // S_i(x, y) = feq_i(rho, u at (x + e_i, y + e_i)) for x in [-2, nx + 1] (the
@@ -248,40 +248,39 @@ template <class T, bool SHIFT>
 __global__ void init_kernel(T* __restrict__ s, Geom g, const double* __restrict__ rho, const double* __restrict__ ux,
                             const double* __restrict__ uy, double eqs)
 {
-    const RowIdx ri = row_idx(g, g.nx + 4);
-    if (!ri.ok) return;
-    const int i = ri.i, y = ri.y, xx = ri.col - 2;  // -2 .. nx + 1
-    const int sx = wrapx2(xx + kEX[i], g.nx), sy = wrapy(y + kEY[i], g.ny);
-    const long long q = (long long)sy * g.nx + sx;
-    const double r = rho ? rho[q] : 1.0, vx = ux ? ux[q] : 0.0, vy = uy ? uy[q] : 0.0;
-    T v;
-    if constexpr (SHIFT) v = (T)dfeq(i, r, vx, vy, eqs);
-    else v = (T)feq(i, r, vx, vy, eqs);
-    s[i * g.ps + (long long)y * g.rs + g.off + xx] = v;
+    for_each_row_elem(g, g.nx + 4, [&](int i, int y, int col) {
+        const int xx = col - 2;  // -2 .. nx + 1
+        const int sx = wrapx2(xx + kEX[i], g.nx), sy = wrapy(y + kEY[i], g.ny);
+        const long long q = (long long)sy * g.nx + sx;
+        const double r = rho ? rho[q] : 1.0, vx = ux ? ux[q] : 0.0, vy = uy ? uy[q] : 0.0;
+        T v;
+        if constexpr (SHIFT) v = (T)dfeq(i, r, vx, vy, eqs);
+        else v = (T)feq(i, r, vx, vy, eqs);
+        s[i * g.ps + (long long)y * g.rs + g.off + xx] = v;
+    });
 }
 
 // S_i(x) = f_i(x + e_i), x in [-2, nx + 1], from a canonical FP64 array [9][ny][nx].
 template <class T, bool SHIFT>
 __global__ void set_f_kernel(T* __restrict__ s, Geom g, const double* __restrict__ f, double eqs)
 {
-    const RowIdx ri = row_idx(g, g.nx + 4);
-    if (!ri.ok) return;
-    const int i = ri.i, y = ri.y, xx = ri.col - 2;  // -2 .. nx + 1
-    const int sx = wrapx2(xx + kEX[i], g.nx), sy = wrapy(y + kEY[i], g.ny);
-    s[i * g.ps + (long long)y * g.rs + g.off + xx] =
-        store_f64<T, SHIFT>(f[((long long)i * g.ny + sy) * g.nx + sx], i, eqs);
+    for_each_row_elem(g, g.nx + 4, [&](int i, int y, int col) {
+        const int xx = col - 2;  // -2 .. nx + 1
+        const int sx = wrapx2(xx + kEX[i], g.nx), sy = wrapy(y + kEY[i], g.ny);
+        s[i * g.ps + (long long)y * g.rs + g.off + xx] =
+            store_f64<T, SHIFT>(f[((long long)i * g.ny + sy) * g.nx + sx], i, eqs);
+    });
 }
 
 // f_i(x) = S_i(x - e_i) into a canonical FP64 array [9][ny][nx].
 template <class T, bool SHIFT>
 __global__ void get_f_kernel(const T* __restrict__ s, Geom g, double* __restrict__ f, double eqs)
 {
-    const RowIdx ri = row_idx(g, g.nx);
-    if (!ri.ok) return;
-    const int i = ri.i, y = ri.y, xx = ri.col;
-    const int sy = wrapy(y - kEY[i], g.ny), sx = wrapx2(xx - kEX[i], g.nx);
-    f[((long long)i * g.ny + y) * g.nx + xx] =
-        load_f64<T, SHIFT>(s[i * g.ps + (long long)sy * g.rs + g.off + sx], i, eqs);
+    for_each_row_elem(g, g.nx, [&](int i, int y, int xx) {
+        const int sy = wrapy(y - kEY[i], g.ny), sx = wrapx2(xx - kEX[i], g.nx);
+        f[((long long)i * g.ny + y) * g.nx + xx] =
+            load_f64<T, SHIFT>(s[i * g.ps + (long long)sy * g.rs + g.off + sx], i, eqs);
+    });
 }
 
 // f_i at n listed sites into out[n][9].
@@ -374,6 +373,7 @@ static hipError_t launch_step_t(const StepTile& t, hipStream_t st)
 {
     const int ntiles = t.nstrips * t.nchunks;  // nstrips counts groups of NW strips
     const int grid = (ntiles + 7) / 8 * 8;
+    if (!grid_fits(grid, 64 * NW)) return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL((step_kernel<T, SHIFT, VX, NW, PF, NTS>), dim3(grid), dim3(64 * NW), 0, st, t, ntiles);
     return hipGetLastError();
 }
@@ -401,6 +401,7 @@ static hipError_t launch_vstack_t(int flags, const StepTile& t, hipStream_t st)
     const int ntiles = t.nstrips * t.nchunks;  // strips x row groups of NW - 2 rows
     const int q = t.xcd_chunk > 0 ? 8 * t.xcd_chunk : 8;
     const int grid = (ntiles + q - 1) / q * q;
+    if (!grid_fits(grid, 64 * NW)) return hipErrorInvalidConfiguration;
     const dim3 gd(grid), bd(64 * NW);
     if (t.field) {
         if (flags & 2) hipLaunchKernelGGL((step_vstack_kernel<T, SHIFT, VX, NW, true, true>), gd, bd, 0, st, t, ntiles);
@@ -519,10 +520,14 @@ hipError_t launch_field(int dtype, void* field, int nx, int ny, int fpitch, cons
     return hipGetLastError();
 }
 
+// Blocks of 256 for the set-up kernels' grid-stride loops over 9 * ny rows of
+// nx + extra elements: one element per thread up to 2^20 blocks (2^28 work
+// items, well inside the 32-bit dispatch size).
 static dim3 plane_rows_grid(const Geom& g, int extra)
 {
     const long long n = 9LL * g.ny * (g.nx + extra);
-    return dim3((unsigned)((n + 255) / 256));
+    const long long b = (n + 255) / 256;
+    return dim3((unsigned)(b < (1LL << 20) ? b : (1LL << 20)));
 }
 
 #define LBM_DISPATCH(dtype, CALL)                                  \

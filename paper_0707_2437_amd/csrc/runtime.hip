@@ -241,6 +241,17 @@ int lbm_set_tile(lbm_lattice* L, int vx, int nw, int h, int flags)
 {
     if (!L || (flags & ~31) || !step_shape_supported(L->dtype, vx, nw, flags)) return LBM_EINVAL;
     if (!(flags & LBM_TILE_VSTACK) && (h < 1 || L->field)) return LBM_EINVAL;
+    {
+        // the shape's grid must fit one dispatch for this lattice
+        lbm_lattice tmp = *L;
+        tmp.vx = vx;
+        tmp.nw = nw;
+        tmp.h = h;
+        tmp.kflags = flags;
+        const StepTile t = make_tile(&tmp);
+        const long long tiles = (long long)t.nstrips * t.nchunks;
+        if (!grid_fits(tiles + 8LL * (t.xcd_chunk > 0 ? t.xcd_chunk : 1), 64 * nw)) return LBM_EINVAL;
+    }
     L->vx = vx;
     L->nw = nw;
     L->h = h;

@@ -42,11 +42,20 @@ def test_oracle_exports_every_declared_symbol():
 @pytest.mark.parametrize("args", [(2, 8, 0.8, 0.2, 0), (8, 2, 0.8, 0.2, 0), (8, 8, 0.5, 0.2, 0),
                                   (8, 8, 0.4, 0.2, 1), (8, 8, float("nan"), 0.2, 0), (8, 8, float("inf"), 0.2, 0),
                                   (8, 8, 0.8, 0.0, 0), (8, 8, 0.8, -1.0, 2), (8, 8, 0.8, float("nan"), 3),
-                                  (8, 8, 0.8, 0.2, 4), (8, 8, 0.8, 0.2, -1)])
+                                  (8, 8, 0.8, 0.2, 4), (8, 8, 0.8, 0.2, -1),
+                                  # one row past the largest lattice whose planes fit 32-bit byte offsets
+                                  (32768, 32704, 0.8, 0.2, 1), (32768, 16368, 0.8, 0.2, 0)])
 def test_create_rejects_invalid_arguments_before_device_work(args):
     L = _lib.lib()
     assert not L.lbm_create(*args)
     assert L.lbm_last_error() == lbm.EINVAL
+
+
+def test_largest_lattices_accepted():
+    """The largest lattices the maximum-size GPU tests create (32768 wide)."""
+    L = _lib.lib()
+    assert L.lbm_footprint_bytes(32768, 32703, 1) > 0 and L.lbm_footprint_bytes(32768, 32704, 1) == 0
+    assert L.lbm_footprint_bytes(32768, 16367, 0) > 0 and L.lbm_footprint_bytes(32768, 16368, 0) == 0
 
 
 def test_footprint_bytes():
