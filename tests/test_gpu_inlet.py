@@ -85,3 +85,40 @@ def test_boundaries_switch_off_and_rules():
     with lbm.Lattice(4, 4, 0.7, 0.3, "f64") as L:
         with pytest.raises(lbm.LBMError):
             L.set_x_boundaries(lbm.XBC_INLET_OUTLET, 0.1, 10.0)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_fig1_sound_speed_over_alpha(dtype):
+    """Fig. 1 on the GPU: the Fig. 1 set-up (inlet period 500 steps, 2400 x 4
+    channel, tau = 0.6) for alpha from -0.8 to 0.3 (c_e = 0.18 ... 1.06); the
+    phase speed between probes at x = 200 and 400 in the periodic regime, and
+    u / delta rho there, against c_e = sqrt(1/3 - alpha) (Eq. 8). The window
+    closes before the outlet's echo reaches the probes."""
+    nx, ny, tau, T, amp, x1, x2 = 2400, 4, 0.6, 500, 1e-3, 200, 400
+    w = 2 * np.pi / T
+    rows = []
+    for alpha in (-0.8, -0.6, -0.3, 0.0, 0.2, 0.3):
+        c2 = 1.0 / 3.0 - alpha
+        c = np.sqrt(c2)
+        t0 = int(x2 / c + 3 * T)
+        t1 = t0 + 4 * T
+        assert (2 * nx - x2) / c > t1
+        R, U = np.empty((t1 - t0, 2)), np.empty((t1 - t0, 2))
+        with lbm.Lattice(nx, ny, tau, c2, dtype) as L:
+            L.set_x_boundaries(lbm.XBC_INLET_OUTLET, amp, T).init()
+            L.step(t0)
+            for t in range(t0, t1):
+                rho, ux, _, _ = L.moments()
+                R[t - t0], U[t - t0] = rho[0, [x1, x2]] - 1, ux[0, [x1, x2]]
+                L.step(1)
+        ph = np.exp(-1j * w * np.arange(t0, t1))[:, None]
+        a, b = (R * ph).mean(0), (U * ph).mean(0)
+        dphi = np.angle(a[0] / a[1])
+        dphi += 2 * np.pi * np.round((w / c * (x2 - x1) - dphi) / (2 * np.pi))
+        speed = w * (x2 - x1) / dphi
+        ratio = abs(b[1] / a[1])
+        rows.append((alpha, c, speed, ratio))
+        print(f"Fig. 1 {dtype}: alpha = {alpha:+.2f}  c_e = {c:.4f}  measured {speed:.4f}  u/drho {ratio:.4f}")
+    for alpha, c, speed, ratio in rows:
+        assert abs(speed / c - 1) < 1e-2, alpha
+        assert abs(ratio / c - 1) < 2e-2, alpha
