@@ -81,3 +81,43 @@ def test_job_stream():
     assert all(500 <= j.steps <= 20000 and 0.55 <= j.tau <= 1.5 and 0.04 <= j.c2 <= 0.6 for j in jobs)
     assert serve.offered_mlups(jobs, 30.0) == pytest.approx(sum(j.sites * j.steps for j in jobs) / 30e6)
     assert len(serve.job_stream(50.0, 30.0, seed=0, max_jobs=10)) == 10
+
+
+def _pmc_csv(path, rows):
+    import csv
+    with open(path, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for k, c, v in rows:
+            w.writerow({"Kernel_Name": k, "Counter_Name": c, "Counter_Value": v})
+
+
+def test_traffic_record_scales_by_the_copy(tmp_path):
+    """HBM bytes from the counters: each counter is scaled by what it reads for
+    a copy of known size (FETCH_SIZE counts about half of the bytes read)."""
+    from paper_0707_2437_amd import profiling
+    k = "void lbm::step_vstack_kernel<float, false, 2, 8, true, false>(lbm::StepTile, int)"
+    _pmc_csv(tmp_path / "f.csv", [(k, "FETCH_SIZE", 400.0), (k, "FETCH_SIZE", 600.0), ("other", "FETCH_SIZE", 1e9)])
+    _pmc_csv(tmp_path / "w.csv", [(k, "WRITE_SIZE", 1000.0), (k, "WRITE_SIZE", 1000.0)])
+    _pmc_csv(tmp_path / "cf.csv", [("__amd_rocclr_copyBuffer", "FETCH_SIZE", 512.0)])
+    _pmc_csv(tmp_path / "cw.csv", [("__amd_rocclr_copyBuffer", "WRITE_SIZE", 1024.0)])
+    rec = profiling.traffic_record("float, false, 2, 8, true, false", str(tmp_path / "f.csv"),
+                                   str(tmp_path / "w.csv"), str(tmp_path / "cf.csv"), str(tmp_path / "cw.csv"),
+                                   1024.0 * 1024.0, 3 * 1024.0 * 1024.0)
+    assert rec["dispatches"] == {"fetch": 2, "write": 2}
+    assert rec["copy_reference"]["fetch_scale"] == 2.0 and rec["copy_reference"]["write_scale"] == 1.0
+    assert rec["read_bytes_per_launch"] == 500.0 * 1024 * 2 and rec["write_bytes_per_launch"] == 1000.0 * 1024
+    assert rec["traffic_over_algorithmic"] == (1000.0 * 1024 + 1000.0 * 1024) / (3 * 1024.0 * 1024.0)
+    assert rec["kernel_source_sha256"] == profiling.kernel_source_sha()
+    with pytest.raises(ValueError):
+        profiling.pmc_mean(str(tmp_path / "f.csv"), "no such kernel", "FETCH_SIZE")
+
+
+def test_committed_traffic_record_matches_the_kernel_sources():
+    """The benchmark reports roofline.traffic only from a counter record taken
+    on the current kernel sources; the committed one must be current."""
+    import json
+    from paper_0707_2437_amd import profiling
+    rec = json.load(open(os.path.join(ROOT, "profiles", "step_f32_4096_traffic.json")))
+    assert rec["kernel_source_sha256"] == profiling.kernel_source_sha()
+    assert bench.measured_traffic(rec["kernel"], 4096) == rec["traffic_bytes_per_launch"]
