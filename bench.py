@@ -191,7 +191,7 @@ def measure_batched(lbm, workloads, torch, nlat, steps, mode, warmup=5, persiste
         s = P.add(sp["nx"], sp["ny"], sp["tau"], sp["c2"])
         P.init(s, *workloads.batch_fields(sp))
         slots.append(s)
-    tile = P.autotune(slots, reps=3)
+    tile = P.autotune(slots, reps=5)
     P.step(slots, warmup)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
