@@ -194,6 +194,15 @@ def measure_batched(lbm, workloads, torch, nlat, steps, mode, warmup=5, persiste
     tile = P.autotune(slots, reps=5)
     P.step(slots, warmup)
     torch.cuda.synchronize()
+    capture = None
+    if mode == "graph":
+        # The first call of a shape captures and instantiates its graph (host
+        # work, once per shape); the timed call below replays it. The first
+        # call's wall time less one replay's is reported as the capture cost.
+        t = time.perf_counter()
+        P.step(slots, steps)
+        torch.cuda.synchronize()
+        capture = time.perf_counter() - t
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
@@ -240,7 +249,8 @@ def measure_batched(lbm, workloads, torch, nlat, steps, mode, warmup=5, persiste
     return {"mlups": mlups, "frac": mlups * 1e6 * BYTES_PER_SITE["f32"] / 1e9 / PEAK_HBM_GBS,
             "lattices": nlat, "sites": sites, "steps": steps, "mode": mode, "tile": list(tile),
             "seconds": sec, "plain_mlups": plain, "vs_plain": mlups / plain, "nonfinite_lattices": nonfinite,
-            "persistent_mlups": pers}
+            "persistent_mlups": pers,
+            "graph_capture_s": None if capture is None else max(0.0, capture - sec)}
 
 
 def measure_precision(lbm, workloads, torch, steps, warmup=5, n=8192):

@@ -247,7 +247,11 @@ enum lbm_pool_mode {
 
 /* Create an empty pool for lattices of `dtype` whose device memory
  * (lbm_pool_slot_bytes each) may total at most budget_bytes. NULL on
- * failure; lbm_pool_last_error() tells why. */
+ * failure; lbm_pool_last_error() tells why. Slots are carved from a few
+ * large device allocations (up to 2 GiB each, at most about the budget in
+ * total unless freed ranges are too fragmented to reuse), taken as slots are
+ * added and kept until lbm_pool_destroy: removing a slot returns its range
+ * to the pool, not to the device. */
 lbm_pool* lbm_pool_create(size_t budget_bytes, int dtype);
 int lbm_pool_last_error(void);
 /* Free every slot and the pool (synchronises its stream). NULL: no-op. */

@@ -104,6 +104,39 @@ def test_budget_admission_and_slot_reuse():
         assert P.add(256, 256, 0.8, 0.3) == s[1]  # id reused
 
 
+def test_freed_ranges_reused_without_crosstalk():
+    """Slots are ranges of a few large device allocations: removing two
+    adjacent slots and admitting larger and smaller lattices reuses (and
+    merges) their ranges; every lattice then steps bitwise as it does alone,
+    and initialising a new slot leaves its neighbours' state untouched."""
+    shapes = [(100, 90), (64, 64), (130, 77), (257, 129), (40, 300)]
+    with lbm.Pool(1 << 28, "f32") as P:
+        live = {}
+        for k, (nx, ny) in enumerate(shapes):
+            f = smooth_random_state(nx, ny, seed=60 + k)
+            s = P.add(nx, ny, 0.7, 0.3)
+            P.init(s, *f)
+            live[s] = (nx, ny, f, 0)
+        P.step(list(live), 7)
+        live = {s: (nx, ny, f, 7) for s, (nx, ny, f, _) in live.items()}
+        before = {s: P.get_f(s) for s in live}
+        for s in list(live)[1:3]:
+            P.remove(s)
+            del live[s]
+        for k, (nx, ny) in enumerate([(200, 110), (33, 47), (64, 64)]):
+            f = smooth_random_state(nx, ny, seed=80 + k)
+            s = P.add(nx, ny, 0.9, 0.25)
+            P.init(s, *f)
+            live[s] = (nx, ny, f, 0)
+        for s in (0, 3, 4):
+            assert np.array_equal(P.get_f(s), before[s])
+        P.step(list(live), 11)
+        got = {s: P.get_f(s) for s in live}
+    for s, (nx, ny, f, t0) in live.items():
+        tau, c2 = (0.7, 0.3) if t0 else (0.9, 0.25)
+        assert np.array_equal(got[s], run_alone(nx, ny, tau, c2, t0 + 11, "f32", f)), (s, nx, ny)
+
+
 def test_pool_errors():
     with lbm.Pool(1 << 28, "f32") as P:
         s = P.add(32, 32, 0.8, 0.3)
