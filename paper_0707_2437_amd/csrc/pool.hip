@@ -5,10 +5,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <map>
 #include <new>
 #include <vector>
 
+#include "arena.h"
 #include "host.h"
 #include "tune.h"
 
@@ -32,83 +32,14 @@ struct Slot {
     long long t = 0;
 };
 
-// Device memory of the slots: ranges of a few large allocations (chunks),
-// so that a pool of many small lattices lies in a handful of large mappings
-// whatever the process has allocated and freed before, and admitting or
-// retiring a lattice calls neither hipMalloc nor hipFree once the chunks
-// exist. Ranges are multiples of kAlign, taken first-fit and coalesced when
-// given back; a chunk is at most kChunk bytes unless one slot needs more, and
-// chunks stop growing by kChunk once they cover the budget (then a chunk is
-// exactly what the slot needs). Chunks are freed with the pool.
-struct Arena {
-    static constexpr size_t kAlign = size_t(64) << 10;
-    static constexpr size_t kChunk = size_t(2) << 30;
-    struct Chunk {
-        char* base = nullptr;
-        size_t size = 0;
-        std::map<size_t, size_t> free;  // offset -> length of each free range
-    };
-    std::vector<Chunk> chunks;
-    size_t total = 0;
-
-    static size_t round(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
-
-    void* take(size_t n, size_t budget, hipError_t* err)
-    {
-        *err = hipSuccess;
-        n = round(n);
-        for (auto& c : chunks)
-            for (auto it = c.free.begin(); it != c.free.end(); ++it)
-                if (it->second >= n) {
-                    const size_t off = it->first, len = it->second;
-                    c.free.erase(it);
-                    if (len > n) c.free[off + n] = len - n;
-                    return c.base + off;
-                }
-        const size_t room = round(budget) > total ? round(budget) - total : 0;
-        const size_t size = std::max(n, std::min(kChunk, room));
-        Chunk c;
-        *err = hipMalloc((void**)&c.base, size);
-        if (*err != hipSuccess) return nullptr;
-        c.size = size;
-        if (size > n) c.free[n] = size - n;
-        chunks.push_back(std::move(c));
-        total += size;
-        return chunks.back().base;
-    }
-
-    void give(void* p, size_t n)
-    {
-        n = round(n);
-        for (auto& c : chunks) {
-            if ((char*)p < c.base || (char*)p >= c.base + c.size) continue;
-            size_t off = (size_t)((char*)p - c.base);
-            auto next = c.free.lower_bound(off);
-            if (next != c.free.end() && next->first == off + n) {  // merge with the range after
-                n += next->second;
-                next = c.free.erase(next);
-            }
-            if (next != c.free.begin()) {  // merge with the range before
-                auto prev = std::prev(next);
-                if (prev->first + prev->second == off) {
-                    off = prev->first;
-                    n += prev->second;
-                    c.free.erase(prev);
-                }
-            }
-            c.free[off] = n;
-            return;
-        }
-    }
-
-    void release()
-    {
-        for (auto& c : chunks)
-            if (c.base) (void)hipFree(c.base);
-        chunks.clear();
-        total = 0;
-    }
+// Chunks of slot memory come from hipMalloc (see arena.h).
+struct DeviceAlloc {
+    using Err = hipError_t;
+    static constexpr hipError_t kOk = hipSuccess;
+    static hipError_t get(void** p, size_t n) { return hipMalloc(p, n); }
+    static void put(void* p) { (void)hipFree(p); }
 };
+using SlotArena = lbm::Arena<DeviceAlloc>;
 
 struct GraphEntry {
     int nsteps_max = 0, nitems = 0, vx = 0, nw = 0, nts = 0, ch = 0;
@@ -123,7 +54,7 @@ struct lbm_pool {
     int dtype = 0, esize = 0, device = 0;
     size_t budget = 0, used = 0;
     std::vector<Slot> slots;
-    Arena arena;                  // device memory of the slots
+    SlotArena arena;              // device memory of the slots
     hipStream_t own = nullptr, stream = nullptr;
     int vx = 2, nw = 16, nts = 1; // vertical-stack tile of the batched kernels
     int mode = LBM_POOL_GROUPED;
@@ -364,7 +295,7 @@ int lbm_pool_add(lbm_pool* P, int nx, int ny, double tau, double c2)
     S.bytes = bytes;
     const size_t fb = footprint(g, P->esize);
     const size_t red_at = (fb + 255) / 256 * 256;  // moments scratch after the buffers
-    S.span = Arena::round(red_at + red_doubles(g) * sizeof(double));
+    S.span = SlotArena::round(red_at + red_doubles(g) * sizeof(double));
     hipError_t e = hipSuccess;
     S.buf = P->arena.take(S.span, P->budget, &e);
     if (S.buf) {

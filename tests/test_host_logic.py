@@ -121,3 +121,21 @@ def test_committed_traffic_record_matches_the_kernel_sources():
     rec = json.load(open(os.path.join(ROOT, "profiles", "step_f32_4096_traffic.json")))
     assert rec["kernel_source_sha256"] == profiling.kernel_source_sha()
     assert bench.measured_traffic(rec["kernel"], 4096) == rec["traffic_bytes_per_launch"]
+
+
+def test_slot_arena_ranges(tmp_path):
+    """The pool's range allocator (csrc/arena.h), built with g++ against a
+    fake allocator: first-fit reuse, merging with free neighbours on both
+    sides, chunk sizes bounded by the budget and by 2 GiB, a range larger than
+    a chunk, a failed chunk allocation, alignment, and release."""
+    import shutil
+
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not found")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    exe = str(tmp_path / "arena_check")
+    subprocess.run([gxx, "-std=c++17", "-O1", "-Wall", "-I", os.path.join(root, "paper_0707_2437_amd", "csrc"),
+                    os.path.join(root, "tests", "arena_check.cpp"), "-o", exe], check=True)
+    r = subprocess.run([exe], capture_output=True, text=True)
+    assert r.returncode == 0 and r.stdout.strip() == "arena ok", r.stdout + r.stderr
