@@ -9,9 +9,10 @@
 
     # HBM traffic of one kernel from two `--pmc FETCH_SIZE` / `--pmc WRITE_SIZE`
     # runs, scaled by the same counters on a device copy of known size
+    # (--grid: only the dispatches of one launch shape)
     python -m paper_0707_2437_amd.profiling traffic --kernel REGEX \\
         --fetch F.csv --write W.csv --copy-fetch CF.csv --copy-write CW.csv \\
-        --copy-bytes 1073741824 --algorithmic-bytes B --out traffic.json
+        --copy-bytes 1073741824 --algorithmic-bytes B [--grid N] --out traffic.json
 
 The traffic record carries the SHA-256 of the kernel source it was measured
 on; a consumer reports it only while the source is unchanged.
@@ -67,19 +68,22 @@ def trace_summary(path, kernel_regex=None, top=20):
     return "\n".join(lines)
 
 
-def pmc_mean(path, kernel_regex, counter):
-    """Mean counter value per dispatch of the kernels whose name matches."""
+def pmc_mean(path, kernel_regex, counter, grid=None):
+    """Mean counter value per dispatch of the kernels whose name matches (and,
+    with `grid`, whose launch grid is that many work-items: one kernel
+    launched in several shapes shows one grid per shape)."""
     rx = re.compile(kernel_regex)
     vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(path))
-            if r["Counter_Name"] == counter and rx.search(r["Kernel_Name"])]
+            if r["Counter_Name"] == counter and rx.search(r["Kernel_Name"])
+            and (grid is None or int(r["Grid_Size"]) == grid)]
     if not vals:
         raise ValueError(f"no {counter} rows for /{kernel_regex}/ in {path}")
     return statistics.fmean(vals), len(vals)
 
 
-def traffic_record(kernel_regex, fetch, write, copy_fetch, copy_write, copy_bytes, algorithmic_bytes):
-    f_kib, nf = pmc_mean(fetch, kernel_regex, "FETCH_SIZE")
-    w_kib, nw = pmc_mean(write, kernel_regex, "WRITE_SIZE")
+def traffic_record(kernel_regex, fetch, write, copy_fetch, copy_write, copy_bytes, algorithmic_bytes, grid=None):
+    f_kib, nf = pmc_mean(fetch, kernel_regex, "FETCH_SIZE", grid)
+    w_kib, nw = pmc_mean(write, kernel_regex, "WRITE_SIZE", grid)
     cf_kib, _ = pmc_mean(copy_fetch, "copyBuffer|elementwise", "FETCH_SIZE")
     cw_kib, _ = pmc_mean(copy_write, "copyBuffer|elementwise", "WRITE_SIZE")
     # the copy reads and writes copy_bytes each: scale = true bytes / counter bytes
@@ -89,6 +93,7 @@ def traffic_record(kernel_regex, fetch, write, copy_fetch, copy_write, copy_byte
     write_b = w_kib * 1024.0 * sw
     return {
         "kernel_regex": kernel_regex,
+        "grid": grid,
         "kernel_source_sha256": kernel_source_sha(),
         "dispatches": {"fetch": nf, "write": nw},
         "counter_kib_per_dispatch": {"FETCH_SIZE": f_kib, "WRITE_SIZE": w_kib},
@@ -117,6 +122,7 @@ def main(argv=None):
         t.add_argument("--" + k, required=True)
     t.add_argument("--copy-bytes", type=float, default=float(1 << 30))
     t.add_argument("--algorithmic-bytes", type=float, required=True)
+    t.add_argument("--grid", type=int, default=None, help="only dispatches with this many work-items")
     a = p.parse_args(argv)
     if a.cmd == "stats":
         print(stats_summary(a.csv))
@@ -124,7 +130,7 @@ def main(argv=None):
         print(trace_summary(a.csv, a.kernel))
     else:
         rec = traffic_record(a.kernel, a.fetch, a.write, a.copy_fetch, a.copy_write, a.copy_bytes,
-                             a.algorithmic_bytes)
+                             a.algorithmic_bytes, a.grid)
         rec["kernel"] = a.name
         with open(a.out, "w") as f:
             json.dump(rec, f, indent=1)
