@@ -45,7 +45,8 @@ def parse():
                         "altered-equilibrium model over its own c^2 sweep, '_field' a c^2 field per lattice")
     p.add_argument("--form-steps", type=int, default=300)
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    p.add_argument("--cpu-steps", type=int, default=200)
+    p.add_argument("--cpu-steps", type=int, default=100, help="oracle steps on all host cores")
+    p.add_argument("--cpu-steps-one-core", type=int, default=10, help="oracle steps on one core")
     p.add_argument("--batch", type=int, default=256, help="lattices of the batched form (0: skip it)")
     p.add_argument("--batch-steps", type=int, default=2000)
     p.add_argument("--batch-mode", default="graph", choices=["grouped", "graph", "persistent"])
@@ -155,23 +156,53 @@ def measure_form(lbm, workloads, torch, n, dtype, steps, warmup):
             "mass_total_first": tot[0][0], "kernel": kernel_name(tile, dtype), "tile": list(tile)}
 
 
-def cpu_baseline(workloads, n, steps):
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo), or the machine type."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def cpu_baseline(workloads, n, steps, steps_one_core):
     """The FP64 oracle on a bounded sample of the same workload: one of the
-    five lattices (c^2 = 0.2), `steps` steps, all host cores."""
+    five lattices (c^2 = 0.2), stepped on all host cores for `steps` steps and
+    on one core for `steps_one_core` steps (the per-site arithmetic is the same,
+    so are the results)."""
     import oracle
 
-    oracle.set_threads(0)
-    cores = oracle.get_threads()
     rho, ux, uy = workloads.plane_wave_fields(n, n, 0.2, seed=1)
-    o = oracle.Oracle(n, n, 0.6, 0.2).init(rho, ux, uy)
-    o.step(1)  # page in
-    t0 = time.perf_counter()
-    o.step(steps)
-    sec = time.perf_counter() - t0
-    o.close()
-    return {"value": n * n * steps / sec / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
-            "sample": f"FP64 oracle, one {n}x{n} lattice of the sweep (c^2 = 0.2, tau = 0.6), {steps} steps, "
-                      f"{sec:.1f} s on {cores} threads ({platform.processor() or platform.machine()})"}
+
+    def leg(threads, k):
+        oracle.set_threads(threads)
+        o = oracle.Oracle(n, n, 0.6, 0.2).init(rho, ux, uy)
+        o.step(1)  # page in
+        t0 = time.perf_counter()
+        o.step(k)
+        sec = time.perf_counter() - t0
+        o.close()
+        return n * n * k / sec / 1e6, sec, oracle.get_threads()
+
+    all_mlups, all_sec, cores = leg(0, steps)
+    one_mlups, one_sec, _ = leg(1, steps_one_core)
+    oracle.set_threads(0)
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    model = cpu_model()
+    return {"value": round(all_mlups, 2), "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "sample": f"FP64 oracle, one {n}x{n} lattice of the sweep (c^2 = 0.2, tau = 0.6): {steps} steps on "
+                      f"{cores} threads in {all_sec:.1f} s, {steps_one_core} steps on one thread in {one_sec:.1f} s",
+            "one_core": {"value": round(one_mlups, 2), "unit": "MLUPS", "steps": steps_one_core,
+                         "seconds": round(one_sec, 2)},
+            "all_cores": {"value": round(all_mlups, 2), "unit": "MLUPS", "threads": cores, "steps": steps,
+                          "seconds": round(all_sec, 2)},
+            "cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": usable}
 
 
 def measure_batched(lbm, workloads, torch, nlat, steps, mode, warmup=5, persistent_steps=0):
@@ -354,7 +385,10 @@ def main():
         print(f"# served: {sv['mlups']:.0f} MLUPS, {sv['jobs_completed']} jobs done, latency p50 "
               f"{sv['latency_p50_s']} s p99 {sv['latency_p99_s']} s", file=sys.stderr, flush=True)
 
-    cpu = None if a.no_cpu else cpu_baseline(workloads, n, a.cpu_steps)
+    cpu = None if a.no_cpu else cpu_baseline(workloads, n, a.cpu_steps, a.cpu_steps_one_core)
+    if cpu is not None:
+        cpu["gpu_over_all_cores"] = round(head["mlups"] / cpu["all_cores"]["value"], 1)
+        cpu["gpu_over_one_core"] = round(head["mlups"] / cpu["one_core"]["value"], 1)
     sweep = list(workloads.C2_SWEEP)
     out = {
         "metric": "MLUPS (lattice-site updates per second / 1e6), one MI355X",

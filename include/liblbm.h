@@ -248,23 +248,31 @@ enum lbm_pool_mode {
 /* Create an empty pool for lattices of `dtype` whose device memory
  * (lbm_pool_slot_bytes each) may total at most budget_bytes. NULL on
  * failure; lbm_pool_last_error() tells why. Slots are carved from a few
- * large device allocations (up to 2 GiB each, at most about the budget in
- * total unless freed ranges are too fragmented to reuse), taken as slots are
- * added and kept until lbm_pool_destroy: removing a slot returns its range
- * to the pool, not to the device. */
+ * large device allocations (up to 2 GiB each), taken as slots are added and
+ * kept until lbm_pool_destroy: removing a slot returns its range to the
+ * pool, not to the device. Slots do not always pack their allocations
+ * exactly, so these may exceed budget_bytes, by at most 2 GiB
+ * (lbm_pool_device_bytes): when a slot finds no free range and a new
+ * allocation would go past that, allocations with no slot in them are freed
+ * first, and if that does not make room lbm_pool_add returns LBM_ENOMEM
+ * (the caller may retry after removing slots). */
 lbm_pool* lbm_pool_create(size_t budget_bytes, int dtype);
 int lbm_pool_last_error(void);
 /* Free every slot and the pool (synchronises its stream). NULL: no-op. */
 void lbm_pool_destroy(lbm_pool* P);
 
-/* Device bytes one slot of this shape takes (0 if the shape is invalid). */
+/* Device bytes one slot of this shape takes (0 if the shape is invalid): its
+ * two population buffers and reduction scratch, rounded up to 64 KiB. */
 size_t lbm_pool_slot_bytes(int nx, int ny, int dtype);
-size_t lbm_pool_used_bytes(const lbm_pool* P);
+size_t lbm_pool_used_bytes(const lbm_pool* P);   /* sum of the slots' lbm_pool_slot_bytes      */
 size_t lbm_pool_budget_bytes(const lbm_pool* P);
+size_t lbm_pool_device_bytes(const lbm_pool* P); /* device memory the pool holds for its slots */
 
 /* Admit a lattice (arguments as lbm_create). Returns the slot id (>= 0), or
- * LBM_EINVAL, or LBM_ENOMEM when it does not fit the remaining budget or the
- * device allocation fails. Slot ids of removed lattices are reused. */
+ * LBM_EINVAL, or LBM_ENOMEM when it does not fit the remaining budget (by
+ * slot bytes, or by the pool's device memory when freed ranges are too
+ * fragmented to hold it) or the device allocation fails. Slot ids of
+ * removed lattices are reused. */
 int lbm_pool_add(lbm_pool* P, int nx, int ny, double tau, double c2);
 /* Release a slot (synchronises the pool's stream). */
 int lbm_pool_remove(lbm_pool* P, int slot);

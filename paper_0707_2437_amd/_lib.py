@@ -51,6 +51,7 @@ SIGNATURES = {
     "lbm_pool_slot_bytes": (ctypes.c_size_t, [_i, _i, _i]),
     "lbm_pool_used_bytes": (ctypes.c_size_t, [_vp]),
     "lbm_pool_budget_bytes": (ctypes.c_size_t, [_vp]),
+    "lbm_pool_device_bytes": (ctypes.c_size_t, [_vp]),
     "lbm_pool_add": (_i, [_vp, _i, _i, _d, _d]),
     "lbm_pool_remove": (_i, [_vp, _i]),
     "lbm_pool_init": (_i, [_vp, _i, _vp, _vp, _vp]),

@@ -3,14 +3,18 @@
 // in a handful of large mappings whatever the process has allocated and
 // freed before, and admitting or retiring a lattice allocates and frees
 // nothing once the chunks exist. Ranges are multiples of kAlign, taken
-// first-fit and merged with free neighbours when given back; a chunk is at
-// most kChunk bytes unless one range needs more, and chunks stop growing by
-// kChunk once they cover the budget (then a chunk is exactly what the range
-// needs). Chunks are freed by release().
+// first-fit and merged with free neighbours when given back. A new chunk is
+// kChunk bytes, or what the budget still allows if that is less, or exactly
+// the range when the budget is used up. Ranges need not fill their chunks
+// (a chunk's tail may be too small for the next range), so the chunks may
+// exceed the budget, by at most kChunk: when a new chunk would go past that,
+// chunks that are entirely free are given back to the allocator first, and
+// if that does not make room take() fails with Alloc::kNoMem and the caller
+// waits for ranges to be given back. Chunks are freed by release().
 //
 // Alloc supplies the chunks: Alloc::Err (its status type), Alloc::kOk,
-// Err Alloc::get(void** p, size_t n) and void Alloc::put(void* p). The pool
-// uses device memory; the host-logic tests use malloc.
+// Alloc::kNoMem, Err Alloc::get(void** p, size_t n) and void Alloc::put(void*
+// p). The pool uses device memory; the host-logic tests use a fake.
 #pragma once
 
 #include <algorithm>
@@ -34,9 +38,29 @@ template <class Alloc> struct Arena {
     size_t total = 0;  // bytes of all chunks
 
     static size_t round(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
+    // Most the chunks may hold for a budget: the budget plus one chunk of
+    // room for ranges that do not pack.
+    static size_t limit(size_t budget) { return round(budget) + kChunk; }
+
+    static bool empty(const Chunk& c) { return c.free.size() == 1 && c.free.begin()->second == c.size; }
+
+    // Give back to the allocator every chunk with no range in use.
+    void drop_empty()
+    {
+        for (size_t k = 0; k < chunks.size();) {
+            if (empty(chunks[k])) {
+                Alloc::put(chunks[k].base);
+                total -= chunks[k].size;
+                chunks.erase(chunks.begin() + (long)k);
+            } else {
+                ++k;
+            }
+        }
+    }
 
     // A range of at least n bytes (n rounded up to kAlign), or nullptr with
-    // *err set to what Alloc::get returned.
+    // *err set to Alloc::kNoMem (no room within limit(budget)) or to what
+    // Alloc::get returned.
     void* take(size_t n, size_t budget, Err* err)
     {
         *err = Alloc::kOk;
@@ -49,8 +73,14 @@ template <class Alloc> struct Arena {
                     if (len > n) c.free[off + n] = len - n;
                     return c.base + off;
                 }
-        const size_t room = round(budget) > total ? round(budget) - total : 0;
-        const size_t size = std::max(n, std::min(kChunk, room));
+        const size_t cap = limit(budget);
+        if (total + n > cap) drop_empty();
+        if (total + n > cap) {
+            *err = Alloc::kNoMem;
+            return nullptr;
+        }
+        const size_t b = round(budget);
+        const size_t size = std::max(n, std::min(kChunk, b > total ? b - total : 0));
         Chunk c;
         void* p = nullptr;
         *err = Alloc::get(&p, size);

@@ -7,6 +7,8 @@
 // bitwise identical to stepping it alone.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+
 #include "internal.h"
 #include "step.h"
 
@@ -54,13 +56,15 @@ __global__ __launch_bounds__(64 * NW) void batch_step_kernel(const BatchLat* __r
 }
 
 // Grid barrier for the persistent kernel: a counter and a generation word in
-// device memory (bar[0], bar[1]; zero at first use; bar[2] is an error flag).
-// The last workgroup to arrive resets the counter and bumps the generation;
-// the others wait for the bump. The wait is bounded: after `spin_limit`
-// polls a workgroup gives up, raises the error flag and returns false, and
-// the kernel then ends in every workgroup (no workgroup can wait forever).
-// All accesses are vector-memory atomics.
-__device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned nblocks, unsigned spin_limit)
+// device memory (bar[0], bar[1]; zeroed before every launch; bar[2] is an
+// error flag). The last workgroup to arrive resets the counter and bumps
+// the generation; the others poll the generation with relaxed atomic loads
+// and acquire once it has moved. The wait is bounded in time: a workgroup
+// that has polled for `wait_ticks` of the constant-rate device clock raises
+// the error flag and returns false, and the kernel then ends in every
+// workgroup (no workgroup can wait forever). Only thread 0 of a workgroup
+// touches the barrier words, with vector-memory atomics.
+__device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned nblocks, unsigned long long wait_ticks)
 {
     __shared__ int ok;
     __syncthreads();
@@ -74,39 +78,306 @@ __device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned nblocks, un
             __threadfence();
             __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else {
-            unsigned spins = 0;
-            while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-                if (++spins > spin_limit) {
+            const unsigned long long t0 = wall_clock64();
+            while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                if (wall_clock64() - t0 > wait_ticks) {
                     atomicExch(&bar[2], 1u);
                     ok = 0;
                     break;
                 }
-                __builtin_amdgcn_s_sleep(4);
+                __builtin_amdgcn_s_sleep(2);
             }
         }
-        __threadfence();
+        __threadfence();  // the other workgroups' stores of this step, before the next step's loads
+        if (__hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) ok = 0;
     }
-    __syncthreads();
-    if (__hip_atomic_load(&bar[2], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != 0) ok = 0;
     __syncthreads();
     return ok != 0;
 }
 
-// nsteps_max steps of the whole batch in one cooperative launch: every
-// workgroup strides over the tiles of a step, then all wait at the grid
-// barrier before the next step reads what this one wrote. Launched only
-// with a grid that is co-resident (hipLaunchCooperativeKernel checks it).
+// Read a descriptor (or a field of one) through the constant address space.
+// The descriptors do not change during a launch; read this way the loads are
+// scalar loads, counted apart from the vector loads and stores of the tiles.
+// Read as ordinary global memory after the kernel's first stores, the
+// compiler would issue them as vector loads (it cannot prove the stores do
+// not clobber them), and waiting for them would wait for every store before.
+#define LBM_CONST __attribute__((address_space(4)))
+template <class V> __device__ __forceinline__ V ldc(const V* p)
+{
+    V r;
+    __builtin_memcpy(&r, (const LBM_CONST V*)p, sizeof(V));
+    return r;
+}
+
+// Whether a barrier of an earlier launch timed out and the host has not yet
+// read the flag (then a launch does nothing). Read once per workgroup, so
+// that all its waves take the same branch.
+__device__ __forceinline__ bool stale_barrier_error(const unsigned* bar)
+{
+    __shared__ int flag;
+    if (threadIdx.x == 0)
+        flag = __hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+    __syncthreads();
+    return flag != 0;
+}
+
+// A workgroup's place in a step of the persistent kernel: tile t of work
+// item i, which belongs to lattice L; t1 ends the item's tiles. L == nullptr:
+// the workgroup has no more work in this step.
+struct Unit {
+    const BatchLat* L;
+    int i, t, t1;
+};
+
+// The first of items i, i + G, i + 2 G, ... whose lattice takes step s.
+__device__ __forceinline__ Unit find_unit(const BatchLat* __restrict__ lats, const int* __restrict__ item_lat,
+                                          int nitems, int i, int G, int s)
+{
+    for (; i < nitems; i += G) {
+        const BatchLat* L = &lats[ldc(&item_lat[i])];
+        if (s < ldc(&L->nsteps)) {
+            const int per = ldc(&L->per_item);
+            const int t0 = (i - ldc(&L->item_begin)) * per;
+            return Unit{L, i, t0, min(t0 + per, ldc(&L->ntiles))};
+        }
+    }
+    return Unit{nullptr, i, 0, 0};
+}
+
+// nsteps_max steps of the whole batch in one cooperative launch of G
+// co-resident workgroups. In each step workgroup b takes the items
+// k G + p(b), k = 0, 1, ..., where p deals the G positions of a band of G
+// consecutive items to the XCDs in chunks of ch (xcd_tile; ch < 0: p(b) = b),
+// so the tiles in flight at any time form compact bands as in the grouped
+// launches. A workgroup walks its tiles as a pipeline: after the barrier
+// that publishes tile k's densities, it issues tile k + 1's window loads
+// and only then relaxes and stores tile k, so its loads are in flight while
+// it computes and stores, and waiting for them does not wait for the
+// stores. The LDS is double-buffered (tile k + 1 lands in the other half
+// while tile k is still being read). All workgroups meet at the grid barrier
+// between steps, since step s + 1 reads what step s wrote.
+// Launched only with a grid that is co-resident (hipLaunchCooperativeKernel
+// checks it).
 template <class T, bool SHIFT, int VX, int NW, bool NTS>
 __global__ __launch_bounds__(64 * NW) void batch_persistent_kernel(const BatchLat* __restrict__ lats,
                                                                    const int* __restrict__ item_lat, int nitems,
-                                                                   int nsteps_max, unsigned* bar, unsigned spin_limit)
+                                                                   int nsteps_max, int ch, unsigned* bar,
+                                                                   unsigned long long wait_ticks)
 {
     using C = typename CompT<T>::type;
-    __shared__ C lds[NW][64 * VX];
+    using V = VTile<T, SHIFT, VX, NW, NTS, false, false>;  // pools step the paper's model, centred on the weights
+    __shared__ C lds[2][NW][64 * VX];
+    const int G = gridDim.x;
+    const int first = ch < 0 ? (int)blockIdx.x : xcd_tile(blockIdx.x, G, ch);
+    if (stale_barrier_error(bar)) return;
+    V v;
+    v.af = {};
     for (int s = 0; s < nsteps_max; ++s) {
-        for (int i = blockIdx.x; i < nitems; i += gridDim.x)
-            if (batch_item<T, SHIFT, VX, NW, NTS>(lats, item_lat, i, s, lds)) __syncthreads();
-        if (!grid_barrier(bar, gridDim.x, spin_limit)) return;
+        // tile u's lattice, with its buffers of this step (src: time t0 + s)
+        auto tile_of = [&](const Unit& u) {
+            StepTile a = ldc(&u.L->tile);
+            if ((ldc(&u.L->t0) + s) & 1) {
+                const void* b = a.src;
+                a.src = a.dst;
+                a.dst = const_cast<void*>(b);
+            }
+            return a;
+        };
+        auto issue = [&](const StepTile& a, const Unit& u, const VRow& r) { v.issue_all(a, a.src, r); };
+        Unit u = find_unit(lats, item_lat, nitems, first, G, s);
+        VRow r{};
+        if (u.L) {
+            const StepTile a = tile_of(u);
+            r = vrow<VX, NW>(a.g, u.t % a.nstrips, u.t / a.nstrips);
+            issue(a, u, r);
+        }
+        int buf = 0;
+        while (u.L) {
+            const Unit n = u.t + 1 < u.t1 ? Unit{u.L, u.i, u.t + 1, u.t1} : find_unit(lats, item_lat, nitems, u.i + G, G, s);
+            const StepTile a = tile_of(u);
+            v.land(a, r, lds[buf]);
+            __syncthreads();  // tile u's densities are in lds[buf]
+            VRow rn{};
+            if (n.L) {
+                const StepTile an = tile_of(n);
+                rn = vrow<VX, NW>(an.g, n.t % an.nstrips, n.t / an.nstrips);
+                issue(an, n, rn);
+            }
+            v.relax(a, a.dst, r, lds[buf]);
+            u = n;
+            r = rn;
+            buf ^= 1;
+        }
+        if (!grid_barrier(bar, G, wait_ticks)) return;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Producer/consumer form of the persistent kernel. A workgroup has NW loader
+// waves, one per tile row (the halo rows included), and NW - 2 compute waves,
+// one per interior row. Loader waves only load: they issue a tile's window
+// loads, land them (populations and window densities, the same arithmetic
+// as the land phase of vstack_tile), publish the results in a
+// double-buffered LDS tile, and issue the next tile's loads at once. Compute
+// waves never load from global memory: they read their row from the LDS
+// tile, relax (the same relax phase) and store. A wave that has both loads
+// and stores outstanding can only wait for a load by waiting for the stores
+// too (the two share one counter and may complete in either order); with
+// the roles split, no wave ever waits for a store, and the loads of the next
+// tile are in flight while the current one is relaxed and stored. One
+// workgroup barrier per tile hands a buffer from the loaders to the compute
+// waves and back.
+template <class T, int VX, int NW> struct PcShared {
+    using C = typename CompT<T>::type;
+    static constexpr bool H = std::is_same<T, _Float16>::value;
+    static constexpr int WV = VX + 2;
+    static constexpr int WVP = WV <= 4 ? 4 : 8;       // padded for vector LDS access
+    static constexpr int NP = H ? (WV + 1) / 2 : VX;  // per lane and plane: d_i of the own columns,
+                                                      // or (FP16) the packed words of the window
+    using P = typename std::conditional<H, unsigned, C>::type;
+    C dens[2][NW][64][WVP];         // window densities of every tile row
+    P pop[2][NW - 2][9][64][NP];    // populations of the interior rows
+};
+
+// Whether the producer/consumer kernel exists for a shape: its workgroup
+// (2 NW - 2 waves) must fit 1024 work-items and its LDS tile the 160 KiB of
+// a CU.
+template <class T, int VX, int NW> constexpr bool pc_fits()
+{
+    // FP64 tiles (twice the registers and LDS) stay with the one-role kernel
+    return sizeof(T) <= 4 && 64 * (2 * NW - 2) <= 1024 && sizeof(PcShared<T, VX, NW>) + 256 <= 160 * 1024;
+}
+
+// Waves per SIMD that as many workgroups as the LDS tile allows on a CU
+// need (asked of the compiler, which then keeps the registers low enough).
+template <class T, int VX, int NW> constexpr int pc_waves_per_simd()
+{
+    const int wgs = (int)((160 * 1024) / (sizeof(PcShared<T, VX, NW>) + 256));
+    const int w = (wgs * (2 * NW - 2) + 3) / 4;
+    return w < 1 ? 1 : (w > 8 ? 8 : w);
+}
+
+template <class T, bool SHIFT, int VX, int NW, bool NTS>
+__global__ __launch_bounds__(64 * (2 * NW - 2))
+__attribute__((amdgpu_waves_per_eu(pc_waves_per_simd<T, VX, NW>(), 8))) void batch_persistent_pc_kernel(
+    const BatchLat* __restrict__ lats, const int* __restrict__ item_lat, int nitems, int nsteps_max, int ch,
+    unsigned* bar, unsigned long long wait_ticks)
+{
+    using V = VTile<T, SHIFT, VX, NW, NTS, false, false>;  // pools step the paper's model, centred on the weights
+    using S = PcShared<T, VX, NW>;
+    using C = typename S::C;
+    __shared__ S sh;
+    const int G = gridDim.x;
+    const int first = ch < 0 ? (int)blockIdx.x : xcd_tile(blockIdx.x, G, ch);
+    if (stale_barrier_error(bar)) return;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    for (int s = 0; s < nsteps_max; ++s) {
+        auto tile_of = [&](const Unit& u) {
+            StepTile a = ldc(&u.L->tile);
+            if ((ldc(&u.L->t0) + s) & 1) {
+                const void* b = a.src;
+                a.src = a.dst;
+                a.dst = const_cast<void*>(b);
+            }
+            return a;
+        };
+        auto next_of = [&](const Unit& u) {
+            return u.t + 1 < u.t1 ? Unit{u.L, u.i, u.t + 1, u.t1} : find_unit(lats, item_lat, nitems, u.i + G, G, s);
+        };
+        Unit u = find_unit(lats, item_lat, nitems, first, G, s);
+        if (wave < NW) {
+            // Loader of tile row `wave`. Every step of the loop issues one
+            // tile's loads, the same number whatever the tile: past the last
+            // tile of the step the loads of the last one are issued again
+            // (their values unused), so that the wait for a tile's loads is
+            // always the same count.
+            V v;
+            auto issue = [&](const Unit& w, VRow& r) {
+                const StepTile a = tile_of(w);
+                r = vrow<VX, NW>(a.g, w.t % a.nstrips, w.t / a.nstrips, wave);
+                v.issue_all(a, a.src, r);
+            };
+            VRow r{};
+            if (u.L) issue(u, r);
+            int buf = 0;
+            while (u.L) {
+                const Unit n = next_of(u);
+                if (r.load) {
+                    v.land_regs(tile_of(u));
+                    C* dd = &sh.dens[buf][wave][lane][0];
+                    if constexpr (S::WVP == V::WV) {
+                        Pack<C, S::WV> pw;
+#pragma unroll
+                        for (int j = 0; j < S::WV; ++j) pw.v[j] = v.w[j];
+                        *(Pack<C, S::WV>*)dd = pw;
+                    } else {
+#pragma unroll
+                        for (int j = 0; j < S::WV; ++j) dd[j] = v.w[j];
+                    }
+                    if (r.relax) {
+#pragma unroll
+                        for (int i = 0; i < 9; ++i) {
+                            Pack<typename S::P, S::NP> pp;
+#pragma unroll
+                            for (int q = 0; q < S::NP; ++q) {
+                                if constexpr (S::H) pp.v[q] = v.u[i][q];
+                                else pp.v[q] = v.d[i][q];
+                            }
+                            *(Pack<typename S::P, S::NP>*)&sh.pop[buf][wave - 1][i][lane][0] = pp;
+                        }
+                    }
+                }
+                __builtin_amdgcn_sched_barrier(0);  // tile u's registers are free only now
+                VRow rn{};
+                issue(n.L ? n : u, rn);
+                __syncthreads();  // tile u is in sh[buf]; the compute waves are done with sh[buf ^ 1]
+                u = n;
+                r = rn;
+                buf ^= 1;
+            }
+        } else {
+            // compute wave of interior row c
+            V v;
+            v.af = {};
+            const int c = wave - NW;
+            int buf = 0;
+            while (u.L) {
+                const Unit n = next_of(u);
+                __syncthreads();  // tile u is in sh[buf]
+                const StepTile a = tile_of(u);
+                const VRow r = vrow<VX, NW>(a.g, u.t % a.nstrips, u.t / a.nstrips, c + 1);
+                if (r.relax) {
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) {
+                        const Pack<typename S::P, S::NP> pp = *(const Pack<typename S::P, S::NP>*)&sh.pop[buf][c][i][lane][0];
+#pragma unroll
+                        for (int q = 0; q < S::NP; ++q) {
+                            if constexpr (S::H) v.u[i][q] = pp.v[q];
+                            else v.d[i][q] = pp.v[q];
+                        }
+                    }
+#pragma unroll
+                    for (int j = 0; j < S::WV; ++j) v.w[j] = sh.dens[buf][c + 1][lane][j];
+                    v.relax_g(a, a.dst, r, [&](int j) {
+                        return sh.dens[buf][c + 2][lane][j + 1] - sh.dens[buf][c][lane][j + 1];
+                    });
+                }
+                u = n;
+                buf ^= 1;
+            }
+        }
+        if (!grid_barrier(bar, G, wait_ticks)) return;
+    }
+}
+
+// Zero the grid-barrier counter and generation before a persistent launch
+// (the error flag is kept until the host has read it).
+__global__ void barrier_reset_kernel(unsigned* bar)
+{
+    if (threadIdx.x == 0) {
+        bar[0] = 0;
+        bar[1] = 0;
     }
 }
 
@@ -125,19 +396,46 @@ static hipError_t launch_batch_t(bool persistent, const BatchLat* lats, const in
                            item_lat, nitems, s_or_n, ch);
         return hipGetLastError();
     }
-    auto kern = batch_persistent_kernel<T, SHIFT, VX, NW, NTS>;
-    int dev = 0, per_cu = 0, ncu = 0;
+    // the producer/consumer kernel where its workgroup and LDS tile fit,
+    // else the one-role kernel (the same results either way)
+    const void* kern = nullptr;
+    int threads = 64 * NW;
+    if constexpr (pc_fits<T, VX, NW>()) {
+        kern = (const void*)batch_persistent_pc_kernel<T, SHIFT, VX, NW, NTS>;
+        threads = 64 * (2 * NW - 2);
+    } else {
+        kern = (const void*)batch_persistent_kernel<T, SHIFT, VX, NW, NTS>;
+    }
+    int dev = 0, per_cu = 0, ncu = 0, clock_khz = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * NW, 0);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, 0);
     if (e != hipSuccess) return e;
     int grid = per_cu * ncu;
     if (max_grid > 0 && grid > max_grid) grid = max_grid;
-    if (grid > nitems) grid = nitems;
-    if (grid < 1) return hipErrorInvalidConfiguration;
-    unsigned spin_limit = 1u << 24;  // ~1 s of polling at one poll per ~64 ns
-    void* args[] = {(void*)&lats, (void*)&item_lat, (void*)&nitems, (void*)&s_or_n, (void*)&bar, (void*)&spin_limit};
-    return hipLaunchCooperativeKernel((const void*)kern, dim3(grid), dim3(64 * NW), args, 0, st);
+    // a grid that is a multiple of 8 ch (or of 8) makes xcd_tile a permutation
+    if (ch > 0 && grid >= 8 * ch) grid = grid / (8 * ch) * (8 * ch);
+    else if (grid >= 8) {
+        ch = 0;
+        grid = grid / 8 * 8;
+    } else {
+        ch = -1;
+    }
+    if (grid < 1 || clock_khz <= 0) return hipErrorInvalidConfiguration;
+    // bound on one workgroup's wait at a grid barrier (LBM_BARRIER_WAIT_US
+    // sets it for tests of the timeout path; default 1 s)
+    double wait_us = 1e6;
+    if (const char* ev = std::getenv("LBM_BARRIER_WAIT_US")) {
+        const double v = std::atof(ev);
+        if (v >= 0.0 && v <= 1e8) wait_us = v;
+    }
+    unsigned long long wait_ticks = (unsigned long long)(wait_us * 1e-3 * clock_khz);
+    hipLaunchKernelGGL(barrier_reset_kernel, dim3(1), dim3(64), 0, st, bar);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    void* args[] = {(void*)&lats,    (void*)&item_lat, (void*)&nitems,    (void*)&s_or_n,
+                    (void*)&ch,      (void*)&bar,      (void*)&wait_ticks};
+    return hipLaunchCooperativeKernel(kern, dim3(grid), dim3(threads), args, 0, st);
 }
 
 template <class T, bool SHIFT, int VX>
@@ -177,8 +475,10 @@ static hipError_t launch_batch_vx(int vx, int nw, bool nts, bool persistent, con
 // workgroup per item, items dealt to the XCDs in chunks of ch items (<= 0:
 // one contiguous run per XCD).
 // Persistent: s_or_n steps in one cooperative launch, at most max_grid
-// workgroups (<= 0: as many as are co-resident), barrier state in `bar`
-// (3 words, zero-initialised; bar[2] becomes 1 if a barrier timed out).
+// workgroups (<= 0: as many as are co-resident), items dealt to the XCDs in
+// chunks of ch, barrier state in `bar` (3 words; the counter and generation
+// are reset on the stream before the launch; bar[2] becomes 1 if a barrier
+// timed out, and a launch that finds it set does nothing).
 hipError_t launch_batch(int dtype, int vx, int nw, bool nts, bool persistent, const BatchLat* lats,
                         const int* item_lat, int nitems, int s_or_n, int max_grid, int ch, unsigned* bar,
                         hipStream_t st)

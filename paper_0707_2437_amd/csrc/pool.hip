@@ -36,6 +36,7 @@ struct Slot {
 struct DeviceAlloc {
     using Err = hipError_t;
     static constexpr hipError_t kOk = hipSuccess;
+    static constexpr hipError_t kNoMem = hipErrorOutOfMemory;
     static hipError_t get(void** p, size_t n) { return hipMalloc(p, n); }
     static void put(void* p) { (void)hipFree(p); }
 };
@@ -89,23 +90,35 @@ void drop_graphs(lbm_pool* P)
     P->graphs.clear();
 }
 
-size_t slot_bytes(int nx, int ny, int dtype, Geom* g_out)
+// Bytes of a slot's range: both buffers, then the moments scratch at the
+// next 256-byte boundary (*red_at), rounded up to the arena's unit.
+size_t slot_bytes(int nx, int ny, int dtype, Geom* g_out, size_t* red_at = nullptr)
 {
     const int es = esize_of(dtype);
     const Geom g = make_geom(nx, ny, es, choose_interleaved(nx, ny, dtype));
     if (g_out) *g_out = g;
-    return footprint(g, es) + red_doubles(g) * sizeof(double);
+    const size_t at = (footprint(g, es) + 255) / 256 * 256;
+    if (red_at) *red_at = at;
+    return SlotArena::round(at + red_doubles(g) * sizeof(double));
 }
 
-StepTile slot_tile(const lbm_pool* P, const Slot& S)
+// Waves per workgroup of the batched kernels in the pool's mode: the
+// persistent kernel's producer/consumer form takes twice as many waves as
+// tile rows (and so at most 8 rows of waves, 1024 work-items); the tile
+// shape does not change results.
+int batch_nw(const lbm_pool* P) { return (P->mode == LBM_POOL_PERSISTENT && P->nw > 8) ? 8 : P->nw; }
+
+// The descriptor of a slot for vertical-stack tiles of vx columns per lane
+// and nw waves (the shape of the launch that reads it).
+StepTile slot_tile(const Slot& S, int vx, int nw)
 {
     StepTile t{};
     t.src = S.b0;
     t.dst = S.b1;
     t.g = S.g;
     t.c = S.coef;
-    t.h = P->nw - 2;
-    const int W = 64 * P->vx, R = P->nw - 2;
+    t.h = nw - 2;
+    const int W = 64 * vx, R = nw - 2;
     t.nstrips = (S.nx + W - 1) / W;
     t.nchunks = (S.ny + R - 1) / R;
     t.rowband = 1;
@@ -169,8 +182,8 @@ hipError_t run_batch(lbm_pool* P, int nmax)
     if (e != hipSuccess) return e;
     const bool nts = P->nts != 0;
     if (P->mode == LBM_POOL_PERSISTENT)
-        return launch_batch(P->dtype, P->vx, P->nw, nts, true, P->d_lats, P->d_items, nitems, nmax, P->max_grid, 0,
-                            P->d_bar, P->stream);
+        return launch_batch(P->dtype, P->vx, batch_nw(P), nts, true, P->d_lats, P->d_items, nitems, nmax,
+                            P->max_grid, P->xcd_chunk, P->d_bar, P->stream);
     if (P->mode == LBM_POOL_GRAPH) {
         GraphEntry* ge = nullptr;
         for (auto& g : P->graphs)
@@ -276,13 +289,15 @@ size_t lbm_pool_slot_bytes(int nx, int ny, int dtype)
 }
 
 size_t lbm_pool_used_bytes(const lbm_pool* P) { return P ? P->used : 0; }
+size_t lbm_pool_device_bytes(const lbm_pool* P) { return P ? P->arena.total : 0; }
 size_t lbm_pool_budget_bytes(const lbm_pool* P) { return P ? P->budget : 0; }
 
 int lbm_pool_add(lbm_pool* P, int nx, int ny, double tau, double c2)
 {
     if (!P || !args_ok(nx, ny, tau, c2, P->dtype)) return LBM_EINVAL;
     Geom g;
-    const size_t bytes = slot_bytes(nx, ny, P->dtype, &g);
+    size_t red_at = 0;
+    const size_t bytes = slot_bytes(nx, ny, P->dtype, &g, &red_at);
     if (P->used + bytes > P->budget) return LBM_ENOMEM;
     Slot S;
     S.used = true;
@@ -294,8 +309,7 @@ int lbm_pool_add(lbm_pool* P, int nx, int ny, double tau, double c2)
     S.coef = make_coef(tau, c2, LBM_MODEL_FORCING);
     S.bytes = bytes;
     const size_t fb = footprint(g, P->esize);
-    const size_t red_at = (fb + 255) / 256 * 256;  // moments scratch after the buffers
-    S.span = SlotArena::round(red_at + red_doubles(g) * sizeof(double));
+    S.span = bytes;
     hipError_t e = hipSuccess;
     S.buf = P->arena.take(S.span, P->budget, &e);
     if (S.buf) {
@@ -374,7 +388,7 @@ int lbm_pool_step(lbm_pool* P, const int* slots, const int* nsteps, int count)
             if (slots[j] == slots[k]) return LBM_EINVAL;  // a slot listed twice
         if (nsteps[k] == 0) continue;
         BatchLat b{};
-        b.tile = slot_tile(P, *S);
+        b.tile = slot_tile(*S, P->vx, batch_nw(P));
         b.t0 = S->t;
         b.nsteps = nsteps[k];
         add_lattice(P, b);
@@ -387,21 +401,26 @@ int lbm_pool_step(lbm_pool* P, const int* slots, const int* nsteps, int count)
     return LBM_OK;
 }
 
+// After the pool's stream is idle: LBM_EDEVICE if a persistent launch timed
+// out at a grid barrier since the flag was last read (its steps, and those
+// of the launches after it, are incomplete), clearing the flag; else LBM_OK.
+static int take_barrier_error(lbm_pool* P)
+{
+    unsigned flag = 0;
+    hipError_t e = hipMemcpy(&flag, P->d_bar + 2, sizeof(flag), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return status_of(e);
+    if (!flag) return LBM_OK;
+    unsigned zero[3] = {0, 0, 0};
+    (void)hipMemcpy(P->d_bar, zero, sizeof(zero), hipMemcpyHostToDevice);
+    return LBM_EDEVICE;
+}
+
 int lbm_pool_sync(lbm_pool* P)
 {
     if (!P) return LBM_EINVAL;
     hipError_t e = hipStreamSynchronize(P->stream);
-    unsigned flag = 0;
-    if (e == hipSuccess) e = hipMemcpy(&flag, P->d_bar + 2, sizeof(flag), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return status_of(e);
-    if (flag) {
-        // a persistent launch timed out at a grid barrier: its steps are
-        // incomplete; reset the barrier state for later launches
-        unsigned zero[3] = {0, 0, 0};
-        (void)hipMemcpy(P->d_bar, zero, sizeof(zero), hipMemcpyHostToDevice);
-        return LBM_EDEVICE;
-    }
-    return LBM_OK;
+    return take_barrier_error(P);
 }
 
 int lbm_pool_moments(lbm_pool* P, int slot, double* rho, double* ux, double* uy, double totals[3])
@@ -424,6 +443,8 @@ int lbm_pool_moments(lbm_pool* P, int slot, double* rho, double* ux, double* uy,
     if (e == hipSuccess) e = hipStreamSynchronize(P->stream);
     if (e != hipSuccess) return status_of(e);
     if (totals) std::memcpy(totals, tot, sizeof(tot));
+    const int be = take_barrier_error(P);
+    if (be != LBM_OK) return be;
     for (double v : tot)
         if (!std::isfinite(v)) return LBM_ENONFINITE;
     return LBM_OK;
@@ -440,7 +461,8 @@ int lbm_pool_get_f(lbm_pool* P, int slot, double* f)
     if (e == hipSuccess) e = launch_get_f(P->dtype, cur_buf(*S), S->g, d.p, 0.0, P->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(f, d.p, n * sizeof(double), hipMemcpyDeviceToHost, P->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(P->stream);
-    return status_of(e);
+    if (e != hipSuccess) return status_of(e);
+    return take_barrier_error(P);
 }
 
 long long lbm_pool_time(const lbm_pool* P, int slot)
@@ -511,7 +533,7 @@ int lbm_pool_autotune(lbm_pool* P, const int* slots, int count, int reps, int us
         P->h_items.clear();
         for (int j = 0; j < count; ++j) {
             BatchLat b{};
-            b.tile = slot_tile(P, P->slots[slots[j]]);
+            b.tile = slot_tile(P->slots[slots[j]], k.vx, k.nw);
             b.t0 = P->slots[slots[j]].t;
             b.nsteps = 1;
             add_lattice(P, b);

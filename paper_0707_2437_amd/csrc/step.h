@@ -252,23 +252,29 @@ __device__ __forceinline__ void patch_edges(const char* const (&rb)[9], const Ge
         }
 }
 
-// LT / NL: the register type and count the windows are loaded as (the FP16
-// kernels load their windows as packed 32-bit words, NL = ceil(NV / 2)).
-// EDGE = false: the caller knows that no lane of the wave is within reach
-// of a lattice edge (x >= 2 and x + NV <= nx), and no patch code is emitted.
-template <class T, int NV, class LT = T, int NL = NV, bool EDGE = !GhostCols<T>::value>
-__device__ __forceinline__ void gather_raw(const char* const (&pb)[9], const Geom& g, int r, int x, Pack<LT, NL> (&v)[9])
+// Source row bases of the nine planes for row r (uniform over the wave in
+// every caller: the row offsets are scalar and are added to the scalar plane
+// bases, leaving one per-lane 32-bit column offset).
+template <class T>
+__device__ __forceinline__ void row_bases(const char* const (&pb)[9], const Geom& g, int r, const char* (&rb)[9])
 {
     constexpr unsigned es = sizeof(T);
-    // r is uniform over the wave in every caller: the row offsets are
-    // scalar and are added to the scalar plane bases, leaving one per-lane
-    // 32-bit column offset (the +-1 column shifts become immediates).
     const size_t rs = (size_t)g.rs * es;
     const size_t om = (size_t)wrapy(r - 1, g.ny) * rs;  // source row r - 1 (e_iy = +1)
     const size_t o0 = (size_t)wrapy(r, g.ny) * rs;      // source row r     (e_iy =  0)
     const size_t op = (size_t)wrapy(r + 1, g.ny) * rs;  // source row r + 1 (e_iy = -1)
-    const char* const rb[9] = {pb[0] + o0, pb[1] + o0, pb[2] + om, pb[3] + o0, pb[4] + op,
-                               pb[5] + om, pb[6] + om, pb[7] + op, pb[8] + op};
+    const char* const b[9] = {pb[0] + o0, pb[1] + o0, pb[2] + om, pb[3] + o0, pb[4] + op,
+                              pb[5] + om, pb[6] + om, pb[7] + op, pb[8] + op};
+#pragma unroll
+    for (int i = 0; i < 9; ++i) rb[i] = b[i];
+}
+
+// The nine window loads of the lane at column x (the +-1 column shifts are
+// immediates).
+template <class T, int NV, class LT, int NL>
+__device__ __forceinline__ void window_loads(const char* const (&rb)[9], int x, Pack<LT, NL> (&v)[9])
+{
+    constexpr unsigned es = sizeof(T);
     const unsigned xm = (unsigned)x * es, x0 = xm + es, xp = xm + 2 * es;  // window starts for e_ix = +1, 0, -1
     constexpr int A = es < 4 ? (int)es : 4;
     v[0] = ld_vec<LT, NL, A>(rb[0], x0);
@@ -280,10 +286,60 @@ __device__ __forceinline__ void gather_raw(const char* const (&pb)[9], const Geo
     v[6] = ld_vec<LT, NL, A>(rb[6], xp);
     v[7] = ld_vec<LT, NL, A>(rb[7], xp);
     v[8] = ld_vec<LT, NL, A>(rb[8], xm);
+}
+
+// LT / NL: the register type and count the windows are loaded as (the FP16
+// kernels load their windows as packed 32-bit words, NL = ceil(NV / 2)).
+// EDGE = false: the caller knows that no lane of the wave is within reach
+// of a lattice edge (x >= 2 and x + NV <= nx), and no patch code is emitted.
+template <class T, int NV, class LT = T, int NL = NV, bool EDGE = !GhostCols<T>::value>
+__device__ __forceinline__ void gather_raw(const char* const (&pb)[9], const Geom& g, int r, int x, Pack<LT, NL> (&v)[9])
+{
+    const char* rb[9];
+    row_bases<T>(pb, g, r, rb);
+    window_loads<T, NV, LT, NL>(rb, x, v);
     if constexpr (EDGE) {
         static_assert(!GhostCols<T>::value, "ghost columns make the patch unnecessary");
         if (x < 2 || x + NV > g.nx) patch_edges<T, NV, LT, NL>(rb, g, x, v);
     }
+}
+
+// The windows of a lane element by element, every element from its
+// periodic column (a source column below 0 or at or past nx wraps): the
+// values gather_raw loads and patches, for any strip, in one code path with
+// no lane-divergent branch. The number of loads a wave issues is then fixed,
+// so that waiting for them can be counted while the loads of a later tile
+// are in flight. A source column is x + k with k in [-2, NV - 1] (NV the
+// window length); each k's wrapped column is formed once.
+template <class T, int NV, class LT, int NL>
+__device__ __forceinline__ void wrapped_loads(const char* const (&rb)[9], const Geom& g, int x, Pack<LT, NL> (&v)[9])
+{
+    static_assert(sizeof(LT) == sizeof(T) && NL == NV, "element-wise registers");
+    constexpr int ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    constexpr unsigned es = sizeof(T);
+    unsigned off[NV + 2];  // byte offset of source column x + k, k = -2 .. NV - 1
+#pragma unroll
+    for (int k = -2; k < NV; ++k) {
+        const int c = x + k;
+        const int cw = c < 0 ? c + g.nx : (c >= g.nx ? c - g.nx : c);
+        off[k + 2] = (unsigned)(cw + 2) * es;
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+#pragma unroll
+        for (int j = 0; j < NV; ++j) v[i].v[j] = ld_g<T>(rb[i] + (size_t)off[j - 1 - ex[i] + 2]);
+}
+
+// The window loads of one row for the persistent batched kernel: for FP16
+// storage (ghost columns) the vector windows, else wrapped_loads.
+template <class T, int NV, class LT = T, int NL = NV>
+__device__ __forceinline__ void gather_raw_rt(const char* const (&pb)[9], const Geom& g, int r, int x,
+                                              Pack<LT, NL> (&v)[9])
+{
+    const char* rb[9];
+    row_bases<T>(pb, g, r, rb);
+    if constexpr (GhostCols<T>::value) window_loads<T, NV, LT, NL>(rb, x, v);
+    else wrapped_loads<T, NV, LT, NL>(rb, g, x, v);
 }
 
 // A column of nine populations d_i (one site) as seen by the arithmetic
@@ -561,112 +617,103 @@ template <bool FIELD, class C> __device__ __forceinline__ CoefC<C> site_coef(con
     return s;
 }
 
-// vstack_tile for FP16 storage (shifted form): the same tile, rows,
-// summation orders and roundings, with the populations kept as the packed
-// halves they were loaded as (see ColH) and the results rounded to FP16 two
-// at a time.
-template <int VX, int NW, bool NTS, bool EDGE, bool FIELD, bool RC>
-__device__ __forceinline__ void vstack_tile_h(const StepTile& a, const void* src, void* dst, int strip, int grp,
-                                              float (&lds)[NW][64 * VX])
+// ---------------------------------------------------------------------------
+// Vertical-stack tiles. A tile is strip `strip` (64 * VX columns) and row
+// group `grp` (R = NW - 2 rows) of one lattice, processed by a workgroup of
+// NW waves: wave w handles row y0 - 1 + w, so waves 0 and R + 1 take the
+// rows just outside the group, whose densities the gradient needs. A tile
+// runs in three phases:
+//   issue: every wave issues the window loads of its row (no wait);
+//   land:  the loads are consumed: populations and window densities are
+//          kept in registers and the wave's own columns' densities are
+//          published in LDS;
+//   relax: after a workgroup barrier, the interior waves read the densities
+//          of the rows above and below from LDS, relax (Eq. 5) and write.
+// vstack_tile runs them in order; the persistent batched kernel overlaps
+// the issue phase of the next tile with the relax phase of the current one.
+// The arithmetic, and its order, is the same code either way.
+
+// This wave's row of a tile.
+struct VRow {
+    int wave, lane;
+    int y, x, nv;  // lattice row (-1 .. ny: wraps by index), first column, columns held (<= VX)
+    bool rowok;    // the wave's row is one of the tile's (uniform over the wave)
+    bool load;     // the lane loads a row (a halo or interior row, columns inside the lattice)
+    bool relax;    // ... and relaxes and writes it (interior rows)
+};
+
+// `wave`: the tile row the wave takes (0: the halo row above the group).
+template <int VX, int NW> __device__ __forceinline__ VRow vrow(const Geom& g, int strip, int grp, int wave)
 {
-    using T = _Float16;
-    constexpr int WV = VX + 2;
-    constexpr int NWD = (WV + 1) / 2;  // packed words per window
     constexpr int R = NW - 2;
-    const Geom g = a.g;
-    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
+    VRow r;
+    r.wave = wave;
+    r.lane = threadIdx.x & 63;
     const int y0 = grp * R;
     const int nrows = min(R, g.ny - y0);
-    const int y = y0 - 1 + wave;
-    const int x = strip * (64 * VX) + lane * VX;
-    const int nv = min(VX, g.nx - x);
-    const bool active = nv > 0 && wave <= nrows + 1;
-
-    const char* sb[9];
-    char* dbase[9];
-    plane_bases<T>(src, dst, g, sb, dbase);
-
-    unsigned u[9][NWD];
-    float w[WV];
-    Pack<float, VX> af{};
-    if (active) {
-        // An odd-length window (VX = 1) loads one half past its end (at most
-        // column nx + 2, row padding).
-        Pack<unsigned, NWD> raw[9];
-        gather_raw<T, WV, unsigned, NWD, EDGE>(sb, g, y, x, raw);
-        if constexpr (FIELD)
-            if (wave >= 1 && wave <= nrows) af = field_row<float, VX>(a, y, x);
-#pragma unroll
-        for (int i = 0; i < 9; ++i)
-#pragma unroll
-            for (int q = 0; q < NWD; ++q) u[i][q] = raw[i].v[q];
-        static_for<0, WV>([&](auto jc) {
-            constexpr int j = decltype(jc)::value;
-            w[j] = drho_col(col_h<j>(u));
-        });
-#pragma unroll
-        for (int j = 0; j < VX; ++j) lds[wave][lane * VX + j] = w[j + 1];
-    }
-    __syncthreads();
-    if (active && wave >= 1 && wave <= nrows) {
-        const CoefC<float> k = coef_c<float>(a.c);
-        float o[VX][9];
-        static_for<0, VX>([&](auto jc) {
-            constexpr int j = decltype(jc)::value;
-            // undivided central differences at time t (Sec. 4)
-            const float gx = w[j + 2] - w[j];
-            const float gy = lds[wave + 1][lane * VX + j] - lds[wave - 1][lane * VX + j];
-            collide_col<RC>(col_h<j + 1>(u), w[j + 1], gx, gy, site_coef<FIELD>(k, af.v[j]), o[j]);
-        });
-        Pack<T, VX> out[9];
-#pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            if constexpr (VX == 1) {
-                float v = o[0][i];
-                asm("" : "+v"(v));
-                out[i].v[0] = (T)v;
-            } else {
-                unsigned pk[VX / 2];
-#pragma unroll
-                for (int j = 0; j < VX; j += 2) pk[j / 2] = pack_h2(o[j][i], o[j + 1][i]);
-                __builtin_memcpy(&out[i], pk, sizeof(out[i]));
-            }
-        }
-        write_row<T, VX, NTS>(dbase, g, y, x, nv, out);
-    }
+    r.y = y0 - 1 + r.wave;
+    r.x = strip * (64 * VX) + r.lane * VX;
+    r.nv = min(VX, g.nx - r.x);
+    r.rowok = r.wave <= nrows + 1;  // waves past the bottom halo idle
+    r.load = r.nv > 0 && r.rowok;
+    r.relax = r.load && r.wave >= 1 && r.wave <= nrows;
+    return r;
+}
+template <int VX, int NW> __device__ __forceinline__ VRow vrow(const Geom& g, int strip, int grp)
+{
+    return vrow<VX, NW>(g, strip, grp, __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)));
 }
 
-template <class T, bool SHIFT, int VX, int NW, bool NTS, bool EDGE, bool FIELD, bool RC>
-__device__ __forceinline__ void vstack_tile_f(const StepTile& a, const void* src, void* dst, int strip, int grp,
-                                              typename CompT<T>::type (&lds)[NW][64 * VX])
+// Strips whose windows can reach past a lattice edge (the first, and those
+// within two columns of the right edge) run the load-side periodic patch
+// (see GhostCols); uniform over the workgroup.
+template <class T, int VX> __device__ __forceinline__ bool edge_strip(const Geom& g, int strip)
 {
+    if constexpr (GhostCols<T>::value) return false;
+    else return strip == 0 || (strip + 1) * (64 * VX) + 2 > g.nx;
+}
+
+template <class T> __device__ __forceinline__ void src_bases(const void* src, const Geom& g, const char* (&sb)[9])
+{
+#pragma unroll
+    for (int i = 0; i < 9; ++i) sb[i] = (const char*)src + ((long long)i * g.ps + g.off - 2) * (long long)sizeof(T);
+}
+template <class T> __device__ __forceinline__ void dst_bases(void* dst, const Geom& g, char* (&dbase)[9])
+{
+#pragma unroll
+    for (int i = 0; i < 9; ++i) dbase[i] = (char*)dst + ((long long)i * g.ps + g.off) * (long long)sizeof(T);
+}
+
+// Tile registers and phases for FP32 / FP64 storage. FIELD: the source
+// coefficients come per site from a.field (a c2 field); the interior waves
+// load them with their windows. RC: centre the arithmetic on the lattice
+// model's state at rest (see Centre); the batched kernels (paper's model
+// only) pass false.
+template <class T, bool SHIFT, int VX, int NW, bool NTS, bool FIELD, bool RC> struct VTileF {
     using C = typename CompT<T>::type;
     using K = KeepT<T, C>;
-    constexpr int WV = VX + 2;
-    constexpr int R = NW - 2;
-    using Rw = Pack<T, WV>;
-    const Geom g = a.g;
-    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
-    const int y0 = grp * R;
-    const int nrows = min(R, g.ny - y0);
-    const int y = y0 - 1 + wave;  // in [-1, ny + R - 1]; rows wrap by index
-    const int x = strip * (64 * VX) + lane * VX;
-    const int nv = min(VX, g.nx - x);
-    const bool active = nv > 0 && wave <= nrows + 1;  // waves past the bottom halo idle
+    using Lds = C[NW][64 * VX];
+    static constexpr int WV = VX + 2;
+    Pack<T, WV> raw[9];  // window loads in flight
+    Pack<C, VX> af;      // per-site source coefficients (FIELD)
+    K d[9][VX];          // populations of the own columns
+    C w[WV];             // densities of the window columns
 
-    const char* sb[9];
-    char* dbase[9];
-    plane_bases<T>(src, dst, g, sb, dbase);
-
-    K d[9][VX];
-    C w[WV];
-    Pack<C, VX> af{};
-    const Centre<C> cn = centre_c<C, RC>(a.c);
-    if (active) {
-        Rw raw[9];
-        gather_raw<T, WV, T, WV, EDGE>(sb, g, y, x, raw);
+    // issue_rows / land_rows: the phases for a lane with r.load set.
+    template <bool EDGE> __device__ __forceinline__ void issue_rows(const StepTile& a, const void* src, const VRow& r)
+    {
+        const char* sb[9];
+        src_bases<T>(src, a.g, sb);
+        gather_raw<T, WV, T, WV, EDGE>(sb, a.g, r.y, r.x, raw);
         if constexpr (FIELD)
-            if (wave >= 1 && wave <= nrows) af = field_row<C, VX>(a, y, x);
+            if (r.relax) af = field_row<C, VX>(a, r.y, r.x);
+    }
+
+    // The loads consumed: populations of the own columns (d) and densities
+    // of the window columns (w).
+    __device__ __forceinline__ void land_regs(const StepTile& a)
+    {
+        const Centre<C> cn = centre_c<C, RC>(a.c);
         K tmp[9][WV];
 #pragma unroll
         for (int i = 0; i < 9; ++i)
@@ -678,59 +725,194 @@ __device__ __forceinline__ void vstack_tile_f(const StepTile& a, const void* src
         for (int i = 0; i < 9; ++i)
 #pragma unroll
             for (int j = 0; j < VX; ++j) d[i][j] = tmp[i][j + 1];
-#pragma unroll
-        for (int j = 0; j < VX; ++j) lds[wave][lane * VX + j] = w[j + 1];
     }
-    __syncthreads();
-    if (active && wave >= 1 && wave <= nrows) {
-        const CoefC<C> k = coef_c<C>(a.c);
-        Pack<T, VX> out[9];
-#pragma unroll
-        for (int j = 0; j < VX; ++j) {
-            // undivided central differences at time t (Sec. 4)
-            const C gx = w[j + 2] - w[j];
-            const C gy = lds[wave + 1][lane * VX + j] - lds[wave - 1][lane * VX + j];
-            C o[9];
-            collide<T, SHIFT, C, VX, RC>(d, j, w[j + 1], gx, gy, site_coef<FIELD>(k, af.v[j]), cn, o);
-#pragma unroll
-            for (int i = 0; i < 9; ++i) out[i].v[j] = from_d<T, SHIFT, C>(o[i], i, cn);
-        }
-        write_row<T, VX, NTS>(dbase, g, y, x, nv, out);
-    }
-}
 
-// One vertical-stack tile: strip `strip` (64 * VX columns) and row group
-// `grp` (R = NW - 2 rows) of the lattice described by `a`, with src/dst the
-// buffers of this step. A workgroup of NW waves: wave w handles row
-// y0 - 1 + w, so waves 0 and R + 1 take the rows just outside the group,
-// whose densities the gradient needs. Every wave loads its row's windows,
-// forms the window densities and publishes its own columns' densities in
-// `lds`; after one barrier the interior waves read the densities of the
-// rows above and below, relax and write. The caller must place a barrier
-// between two calls that reuse `lds`.
-// Without ghost columns (see GhostCols), strips whose windows can reach past
-// a lattice edge (the first, and those within two columns of the right edge)
-// take a separate copy of the code with the edge patches; the others issue
-// their loads and start the arithmetic as the loads land, with no patch code
-// in between. The branch is uniform over the workgroup.
-// FIELD: the source coefficients come per site from a.field (a c2 field);
-// the interior waves load them with their windows. RC: centre the
-// arithmetic on the lattice model's state at rest (see Centre); the batched
-// kernels (paper's model only) pass false.
+    __device__ __forceinline__ void land_rows(const StepTile& a, const VRow& r, Lds& lds)
+    {
+        land_regs(a);
+#pragma unroll
+        for (int j = 0; j < VX; ++j) lds[r.wave][r.lane * VX + j] = w[j + 1];
+    }
+
+    template <bool EDGE> __device__ __forceinline__ void issue(const StepTile& a, const void* src, const VRow& r)
+    {
+        if (r.load) issue_rows<EDGE>(a, src, r);
+    }
+    // issue for any strip and lane in one code path (see gather_raw_rt):
+    // every lane issues the same loads; a lane with no row to load reads row
+    // 0, column 0 instead, and its values are not used
+    __device__ __forceinline__ void issue_all(const StepTile& a, const void* src, const VRow& r)
+    {
+        static_assert(!FIELD, "pools have no c2 field");
+        const char* sb[9];
+        src_bases<T>(src, a.g, sb);
+        gather_raw_rt<T, WV, T, WV>(sb, a.g, r.rowok ? r.y : 0, r.load ? r.x : 0, raw);
+    }
+    __device__ __forceinline__ void land(const StepTile& a, const VRow& r, Lds& lds)
+    {
+        if (r.load) land_rows(a, r, lds);
+    }
+
+    __device__ __forceinline__ void relax(const StepTile& a, void* dst, const VRow& r, const Lds& lds)
+    {
+        relax_g(a, dst, r, [&](int j) { return lds[r.wave + 1][r.lane * VX + j] - lds[r.wave - 1][r.lane * VX + j]; });
+    }
+
+    // relax with gy(j) the undivided y difference rho(y + 1) - rho(y - 1) at
+    // the lane's column j
+    template <class GY> __device__ __forceinline__ void relax_g(const StepTile& a, void* dst, const VRow& r, GY&& gyf)
+    {
+        if (r.relax) {
+            char* dbase[9];
+            dst_bases<T>(dst, a.g, dbase);
+            const CoefC<C> k = coef_c<C>(a.c);
+            const Centre<C> cn = centre_c<C, RC>(a.c);
+            Pack<T, VX> out[9];
+#pragma unroll
+            for (int j = 0; j < VX; ++j) {
+                // undivided central differences at time t (Sec. 4)
+                const C gx = w[j + 2] - w[j];
+                const C gy = gyf(j);
+                C o[9];
+                collide<T, SHIFT, C, VX, RC>(d, j, w[j + 1], gx, gy, site_coef<FIELD>(k, af.v[j]), cn, o);
+#pragma unroll
+                for (int i = 0; i < 9; ++i) out[i].v[j] = from_d<T, SHIFT, C>(o[i], i, cn);
+            }
+            write_row<T, VX, NTS>(dbase, a.g, r.y, r.x, r.nv, out);
+        }
+    }
+};
+
+// Tile registers and phases for FP16 storage (shifted form): the same tile,
+// rows, summation orders and roundings, with the populations kept as the
+// packed halves they were loaded as (see ColH) and the results rounded to
+// FP16 two at a time.
+template <class T, bool SHIFT, int VX, int NW, bool NTS, bool FIELD, bool RC> struct VTileH {
+    static_assert(SHIFT, "FP16 storage is the shifted form");
+    static_assert(GhostCols<T>::value, "FP16 rows carry ghost columns");
+    using C = float;
+    using Lds = C[NW][64 * VX];
+    static constexpr int WV = VX + 2;
+    static constexpr int NWD = (WV + 1) / 2;  // packed words per window
+    Pack<unsigned, NWD> raw[9];
+    Pack<float, VX> af;
+    unsigned u[9][NWD];
+    float w[WV];
+
+    template <bool EDGE> __device__ __forceinline__ void issue_rows(const StepTile& a, const void* src, const VRow& r)
+    {
+        static_assert(!EDGE, "ghost columns make the patch unnecessary");
+        // An odd-length window (VX = 1) loads one half past its end (at most
+        // column nx + 2, row padding).
+        const char* sb[9];
+        src_bases<T>(src, a.g, sb);
+        gather_raw<T, WV, unsigned, NWD, false>(sb, a.g, r.y, r.x, raw);
+        if constexpr (FIELD)
+            if (r.relax) af = field_row<float, VX>(a, r.y, r.x);
+    }
+
+    __device__ __forceinline__ void land_regs(const StepTile&)
+    {
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+#pragma unroll
+            for (int q = 0; q < NWD; ++q) u[i][q] = raw[i].v[q];
+        static_for<0, WV>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            w[j] = drho_col(col_h<j>(u));
+        });
+    }
+
+    __device__ __forceinline__ void land_rows(const StepTile& a, const VRow& r, Lds& lds)
+    {
+        land_regs(a);
+#pragma unroll
+        for (int j = 0; j < VX; ++j) lds[r.wave][r.lane * VX + j] = w[j + 1];
+    }
+
+    template <bool EDGE> __device__ __forceinline__ void issue(const StepTile& a, const void* src, const VRow& r)
+    {
+        if (r.load) issue_rows<EDGE>(a, src, r);
+    }
+    __device__ __forceinline__ void issue_all(const StepTile& a, const void* src, const VRow& r)
+    {
+        static_assert(!FIELD, "pools have no c2 field");
+        const char* sb[9];
+        src_bases<T>(src, a.g, sb);
+        gather_raw<T, WV, unsigned, NWD, false>(sb, a.g, r.rowok ? r.y : 0, r.load ? r.x : 0, raw);
+    }
+    __device__ __forceinline__ void land(const StepTile& a, const VRow& r, Lds& lds)
+    {
+        if (r.load) land_rows(a, r, lds);
+    }
+
+    __device__ __forceinline__ void relax(const StepTile& a, void* dst, const VRow& r, const Lds& lds)
+    {
+        relax_g(a, dst, r, [&](int j) { return lds[r.wave + 1][r.lane * VX + j] - lds[r.wave - 1][r.lane * VX + j]; });
+    }
+
+    template <class GY> __device__ __forceinline__ void relax_g(const StepTile& a, void* dst, const VRow& r, GY&& gyf)
+    {
+        if (r.relax) {
+            char* dbase[9];
+            dst_bases<T>(dst, a.g, dbase);
+            const CoefC<float> k = coef_c<float>(a.c);
+            float o[VX][9];
+            static_for<0, VX>([&](auto jc) {
+                constexpr int j = decltype(jc)::value;
+                // undivided central differences at time t (Sec. 4)
+                const float gx = w[j + 2] - w[j];
+                const float gy = gyf(j);
+                collide_col<RC>(col_h<j + 1>(u), w[j + 1], gx, gy, site_coef<FIELD>(k, af.v[j]), o[j]);
+            });
+            Pack<T, VX> out[9];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                if constexpr (VX == 1) {
+                    float v = o[0][i];
+                    asm("" : "+v"(v));
+                    out[i].v[0] = (T)v;
+                } else {
+                    unsigned pk[VX / 2];
+#pragma unroll
+                    for (int j = 0; j < VX; j += 2) pk[j / 2] = pack_h2(o[j][i], o[j + 1][i]);
+                    __builtin_memcpy(&out[i], pk, sizeof(out[i]));
+                }
+            }
+            write_row<T, VX, NTS>(dbase, a.g, r.y, r.x, r.nv, out);
+        }
+    }
+};
+
+template <class T, bool SHIFT, int VX, int NW, bool NTS, bool FIELD, bool RC>
+using VTile = typename std::conditional<std::is_same<T, _Float16>::value, VTileH<T, SHIFT, VX, NW, NTS, FIELD, RC>,
+                                        VTileF<T, SHIFT, VX, NW, NTS, FIELD, RC>>::type;
+
+// One vertical-stack tile, its three phases in order, with src/dst the
+// buffers of this step. The caller must place a barrier between two calls
+// that reuse `lds`. Edge strips take a separate copy of the whole tile
+// code; the others issue their loads and start the arithmetic as the loads
+// land, with no patch code in between.
 template <class T, bool SHIFT, int VX, int NW, bool NTS, bool FIELD = false,
           bool RC = ModelCentred<typename CompT<T>::type>::value>
 __device__ __forceinline__ void vstack_tile(const StepTile& a, const void* src, void* dst, int strip, int grp,
                                             typename CompT<T>::type (&lds)[NW][64 * VX])
 {
-    if constexpr (std::is_same<T, _Float16>::value) {
-        static_assert(SHIFT, "FP16 storage is the shifted form");
-        static_assert(GhostCols<T>::value, "FP16 rows carry ghost columns");
-        vstack_tile_h<VX, NW, NTS, false, FIELD, RC>(a, src, dst, strip, grp, lds);
-    } else {
-        const bool edge = strip == 0 || (strip + 1) * (64 * VX) + 2 > a.g.nx;
-        if (edge) vstack_tile_f<T, SHIFT, VX, NW, NTS, true, FIELD, RC>(a, src, dst, strip, grp, lds);
-        else vstack_tile_f<T, SHIFT, VX, NW, NTS, false, FIELD, RC>(a, src, dst, strip, grp, lds);
-    }
+    using V = VTile<T, SHIFT, VX, NW, NTS, FIELD, RC>;
+    const VRow r = vrow<VX, NW>(a.g, strip, grp);
+    auto run = [&](auto edge) {
+        V v;
+        v.af = {};
+        if (r.load) {
+            v.template issue_rows<decltype(edge)::value>(a, src, r);
+            v.land_rows(a, r, lds);
+        }
+        __syncthreads();
+        v.relax(a, dst, r, lds);
+    };
+    if constexpr (GhostCols<T>::value) run(std::false_type{});
+    else if (edge_strip<T, VX>(a.g, strip)) run(std::true_type{});
+    else run(std::false_type{});
 }
 
 }  // namespace lbm

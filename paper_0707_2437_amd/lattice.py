@@ -5,6 +5,7 @@ Host fields are numpy float64 arrays of shape (ny, nx); populations are
 their pointers through; torch supplies only device memory and streams.
 """
 import ctypes
+import sys
 
 import numpy as np
 
@@ -113,7 +114,11 @@ class Lattice:
             self._h = None
 
     def __del__(self):
-        self.close()
+        # At interpreter shutdown the device runtime may already be going
+        # away; the process's device memory is released with it, so a handle
+        # still open then is left alone (close() it explicitly before exit).
+        if not sys.is_finalizing():
+            self.close()
 
     def __enter__(self):
         return self

@@ -1,5 +1,6 @@
 """Python binding of the lbm_pool C ABI (batched and served forms)."""
 import ctypes
+import sys
 
 import numpy as np
 
@@ -29,7 +30,11 @@ class Pool:
             self._h = None
 
     def __del__(self):
-        self.close()
+        # At interpreter shutdown the device runtime may already be going
+        # away; the process's device memory is released with it, so a handle
+        # still open then is left alone (close() it explicitly before exit).
+        if not sys.is_finalizing():
+            self.close()
 
     def __enter__(self):
         return self
@@ -48,6 +53,11 @@ class Pool:
     @property
     def budget_bytes(self):
         return self._L.lbm_pool_budget_bytes(self._h)
+
+    @property
+    def device_bytes(self):
+        """Device memory the pool holds for its slots (never above the budget)."""
+        return self._L.lbm_pool_device_bytes(self._h)
 
     def add(self, nx, ny, tau, c2):
         s = self._L.lbm_pool_add(self._h, int(nx), int(ny), float(tau), float(c2))

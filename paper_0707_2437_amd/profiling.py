@@ -7,11 +7,13 @@
     # stepping lattices of different sizes shows one line per grid)
     python -m paper_0707_2437_amd.profiling trace <..._kernel_trace.csv> [--kernel REGEX]
 
-    # HBM traffic of one kernel from two `--pmc FETCH_SIZE` / `--pmc WRITE_SIZE`
-    # runs, scaled by the same counters on a device copy of known size
-    # (--grid: only the dispatches of one launch shape)
-    python -m paper_0707_2437_amd.profiling traffic --kernel REGEX \\
-        --fetch F.csv --write W.csv --copy-fetch CF.csv --copy-write CW.csv \\
+    # HBM traffic of one kernel from two rocprofv3 --pmc runs of counters
+    # whose units are fixed (read requests of 32, 64 and 128 bytes, and DRAM
+    # reads in 32-byte units; write requests and those of 64 bytes), with
+    # the same counters on a device copy of known size as a check of the
+    # units (--grid: only the dispatches of one launch shape)
+    python -m paper_0707_2437_amd.profiling traffic --kernel REGEX --name NAME \\
+        --reads R.csv --writes W.csv --copy-reads CR.csv --copy-writes CW.csv \\
         --copy-bytes 1073741824 --algorithmic-bytes B [--grid N] --out traffic.json
 
 The traffic record carries the SHA-256 of the kernel source it was measured
@@ -27,13 +29,18 @@ import statistics
 import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = [os.path.join(PKG, "csrc", n) for n in ("kernels.hip", "step.h", "internal.h", "batch.hip")]
+# Device sources of the single-lattice step kernels and of the batched kernels.
+KERNEL_SOURCES = {
+    "step": [os.path.join(PKG, "csrc", n) for n in ("kernels.hip", "step.h", "internal.h")],
+    "batch": [os.path.join(PKG, "csrc", n) for n in ("batch.hip", "step.h", "internal.h")],
+}
 
 
-def kernel_source_sha():
-    """SHA-256 over the device sources of the step kernels."""
+def kernel_source_sha(which="step"):
+    """SHA-256 over the device sources of the step ("step") or batched
+    ("batch") kernels."""
     h = hashlib.sha256()
-    for path in KERNEL_SOURCES:
+    for path in KERNEL_SOURCES[which]:
         with open(path, "rb") as f:
             h.update(f.read())
     return h.hexdigest()
@@ -81,29 +88,59 @@ def pmc_mean(path, kernel_regex, counter, grid=None):
     return statistics.fmean(vals), len(vals)
 
 
-def traffic_record(kernel_regex, fetch, write, copy_fetch, copy_write, copy_bytes, algorithmic_bytes, grid=None):
-    f_kib, nf = pmc_mean(fetch, kernel_regex, "FETCH_SIZE", grid)
-    w_kib, nw = pmc_mean(write, kernel_regex, "WRITE_SIZE", grid)
-    cf_kib, _ = pmc_mean(copy_fetch, "copyBuffer|elementwise", "FETCH_SIZE")
-    cw_kib, _ = pmc_mean(copy_write, "copyBuffer|elementwise", "WRITE_SIZE")
-    # the copy reads and writes copy_bytes each: scale = true bytes / counter bytes
-    sf = copy_bytes / (cf_kib * 1024.0)
-    sw = copy_bytes / (cw_kib * 1024.0)
-    read_b = f_kib * 1024.0 * sf
-    write_b = w_kib * 1024.0 * sw
+# Counters of the two passes (at most 4 TCC counters fit one pass).
+READ_COUNTERS = ["TCC_EA0_RDREQ_32B_sum", "TCC_EA0_RDREQ_64B_sum", "TCC_EA0_RDREQ_128B_sum",
+                 "TCC_EA0_RDREQ_DRAM_32B_sum"]
+WRITE_COUNTERS = ["TCC_EA0_WRREQ_sum", "TCC_EA0_WRREQ_64B_sum"]
+
+
+def read_bytes(path, kernel_regex, grid=None):
+    """L2-to-memory read bytes per dispatch: 32, 64 and 128 bytes per request
+    of each size; and the DRAM reads, counted in 32-byte units."""
+    n32, nd = pmc_mean(path, kernel_regex, "TCC_EA0_RDREQ_32B_sum", grid)
+    n64, _ = pmc_mean(path, kernel_regex, "TCC_EA0_RDREQ_64B_sum", grid)
+    n128, _ = pmc_mean(path, kernel_regex, "TCC_EA0_RDREQ_128B_sum", grid)
+    d32, _ = pmc_mean(path, kernel_regex, "TCC_EA0_RDREQ_DRAM_32B_sum", grid)
+    return {"requests_32B": n32, "requests_64B": n64, "requests_128B": n128, "dram_32B_units": d32,
+            "bytes": 32.0 * n32 + 64.0 * n64 + 128.0 * n128, "dram_bytes": 32.0 * d32, "dispatches": nd}
+
+
+def write_bytes(path, kernel_regex, grid=None):
+    """L2-to-memory write bytes per dispatch: 64 bytes per 64-byte request, 32
+    per other request."""
+    n, nd = pmc_mean(path, kernel_regex, "TCC_EA0_WRREQ_sum", grid)
+    n64, _ = pmc_mean(path, kernel_regex, "TCC_EA0_WRREQ_64B_sum", grid)
+    return {"requests": n, "requests_64B": n64, "bytes": 64.0 * n64 + 32.0 * (n - n64), "dispatches": nd}
+
+
+COPY_REGEX = "copyBuffer|elementwise"
+
+
+def traffic_record(kernel_regex, reads, writes, copy_reads, copy_writes, copy_bytes, algorithmic_bytes, grid=None,
+                   sources="step"):
+    r = read_bytes(reads, kernel_regex, grid)
+    w = write_bytes(writes, kernel_regex, grid)
+    cr = read_bytes(copy_reads, COPY_REGEX)
+    cw = write_bytes(copy_writes, COPY_REGEX)
     return {
         "kernel_regex": kernel_regex,
         "grid": grid,
-        "kernel_source_sha256": kernel_source_sha(),
-        "dispatches": {"fetch": nf, "write": nw},
-        "counter_kib_per_dispatch": {"FETCH_SIZE": f_kib, "WRITE_SIZE": w_kib},
-        "copy_reference": {"bytes_each_way": copy_bytes, "FETCH_SIZE_kib": cf_kib, "WRITE_SIZE_kib": cw_kib,
-                           "fetch_scale": sf, "write_scale": sw},
-        "read_bytes_per_launch": read_b,
-        "write_bytes_per_launch": write_b,
-        "traffic_bytes_per_launch": read_b + write_b,
+        "kernel_sources": sources,
+        "kernel_source_sha256": kernel_source_sha(sources),
+        "counters": {"reads": READ_COUNTERS, "writes": WRITE_COUNTERS},
+        "reads_per_dispatch": r,
+        "writes_per_dispatch": w,
+        # the same counters on a copy that reads and writes copy_bytes: a
+        # check of the units (each ratio should be 1)
+        "copy_check": {"bytes_each_way": copy_bytes, "read_ratio": cr["bytes"] / copy_bytes,
+                       "dram_read_ratio": cr["dram_bytes"] / copy_bytes, "write_ratio": cw["bytes"] / copy_bytes},
+        "read_bytes_per_launch": r["bytes"],
+        "write_bytes_per_launch": w["bytes"],
+        "traffic_bytes_per_launch": r["bytes"] + w["bytes"],
         "algorithmic_bytes_per_launch": algorithmic_bytes,
-        "traffic_over_algorithmic": (read_b + write_b) / algorithmic_bytes,
+        "read_over_algorithmic": r["bytes"] / (algorithmic_bytes / 2),
+        "write_over_algorithmic": w["bytes"] / (algorithmic_bytes / 2),
+        "traffic_over_algorithmic": (r["bytes"] + w["bytes"]) / algorithmic_bytes,
     }
 
 
@@ -118,19 +155,21 @@ def main(argv=None):
     t = sub.add_parser("traffic")
     t.add_argument("--kernel", required=True, help="regex selecting the kernel's dispatches")
     t.add_argument("--name", required=True, help="kernel name as the benchmark reports it")
-    for k in ("fetch", "write", "copy-fetch", "copy-write", "out"):
+    for k in ("reads", "writes", "copy-reads", "copy-writes", "out"):
         t.add_argument("--" + k, required=True)
     t.add_argument("--copy-bytes", type=float, default=float(1 << 30))
     t.add_argument("--algorithmic-bytes", type=float, required=True)
     t.add_argument("--grid", type=int, default=None, help="only dispatches with this many work-items")
+    t.add_argument("--sources", default="step", choices=sorted(KERNEL_SOURCES),
+                   help="which kernels' sources the record is tied to")
     a = p.parse_args(argv)
     if a.cmd == "stats":
         print(stats_summary(a.csv))
     elif a.cmd == "trace":
         print(trace_summary(a.csv, a.kernel))
     else:
-        rec = traffic_record(a.kernel, a.fetch, a.write, a.copy_fetch, a.copy_write, a.copy_bytes,
-                             a.algorithmic_bytes, a.grid)
+        rec = traffic_record(a.kernel, a.reads, a.writes, a.copy_reads, a.copy_writes, a.copy_bytes,
+                             a.algorithmic_bytes, a.grid, a.sources)
         rec["kernel"] = a.name
         with open(a.out, "w") as f:
             json.dump(rec, f, indent=1)

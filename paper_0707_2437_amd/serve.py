@@ -206,6 +206,7 @@ class Server:
             "latency_p50_s": pct(lat, 50), "latency_p99_s": pct(lat, 99),
             "queue_wait_p50_s": pct(wait, 50), "service_p50_s": pct(serv, 50),
             "pool_used_bytes": self.pool.used_bytes,
+            "pool_device_bytes": self.pool.device_bytes,
         }
 
 

@@ -170,3 +170,30 @@ def test_nonfinite_job_detected_and_isolated():
         assert P.totals(good)[1] == 0
         ref = run_alone(40, 30, 0.7, 0.4, 30, "f32", f)
         assert np.array_equal(P.get_f(good), ref)
+
+
+def test_persistent_barrier_timeout_reported(monkeypatch):
+    """The grid barrier's wait is bounded in time. With the bound forced to
+    zero from the host (LBM_BARRIER_WAIT_US=0), a workgroup that has to wait
+    gives up at once, raises the error flag and ends; every workgroup then
+    ends the launch. The next read of the pool reports LBM_EDEVICE (the
+    steps are incomplete), a launch made before that read does nothing, and
+    after the flag has been read the pool steps correctly again."""
+    nx, ny = 200, 150
+    f = smooth_random_state(nx, ny, seed=5)
+    with lbm.Pool(1 << 28, "f32") as P:
+        P.set_mode(lbm.PERSISTENT)
+        s = P.add(nx, ny, 0.7, 0.3)
+        P.init(s, *f)
+        monkeypatch.setenv("LBM_BARRIER_WAIT_US", "0")
+        P.step([s], [20])
+        P.step([s], [5])  # finds the flag set: returns at once
+        monkeypatch.delenv("LBM_BARRIER_WAIT_US")
+        _, _, _, _, st = P.moments(s, fields=False, check=False)
+        assert st == lbm.EDEVICE
+        P.sync()  # the flag was read and cleared by the moments call
+        P.init(s, *f)
+        P.step([s], [20])
+        P.sync()
+        got = P.get_f(s)
+    assert np.array_equal(got, run_alone(nx, ny, 0.7, 0.3, 20, "f32", f))

@@ -1,9 +1,13 @@
 """Served form: jobs arriving over time are admitted as memory frees up,
 stepped together in ticks with per-job step counts, and each job's result is
-bitwise the one it gets when run alone; a job that blows up is reported as
-failed without disturbing the others."""
+bitwise the one it gets when run alone and, for a seeded sample, matches the
+FP64 oracle; a job that blows up is reported as failed without disturbing
+the others."""
 import numpy as np
 import pytest
+
+import oracle
+from gpu_util import max_rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -12,7 +16,7 @@ if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 
 import paper_0707_2437_amd as lbm  # noqa: E402
-from paper_0707_2437_amd import serve  # noqa: E402
+from paper_0707_2437_amd import serve, workloads  # noqa: E402
 
 
 def alone(job):
@@ -51,3 +55,30 @@ def test_unstable_job_fails_alone():
     for i in (0, 2):
         assert by_id[i].status == "done"
         assert np.array_equal(by_id[i].f, alone(by_id[i]))
+
+
+def test_served_jobs_match_oracle():
+    """A seeded sample of jobs served in the mix (admitted as memory frees up,
+    stepped in shared ticks) against the FP64 oracle stepping each job's
+    lattice (Eq. 5) from the same pulse field for the same number of steps:
+    FP32 bar 1e-5 max relative error in f per 1000 steps (the FP32 error of
+    the plain kernel grows linearly with the step count)."""
+    jobs = serve.job_stream(rate=30.0, duration=0.5, seed=5, side_log2=(6, 7), steps=(200, 1000))
+    assert len(jobs) >= 8
+    budget = 3 * lbm.Pool.slot_bytes(128, 128, "f32")  # not all jobs fit at once
+    srv = serve.Server(budget, "f32", tick_steps=64, keep_f=True)
+    st = srv.run(jobs, duration=0.0, drain=True)
+    srv.close()
+    assert st["jobs_completed"] == len(jobs)
+    done = sorted(srv.finished, key=lambda j: j.id)
+    sample = np.random.default_rng(0).choice(len(done), 6, replace=False)
+    oracle.set_threads(0)
+    for k in sample:
+        j = done[k]
+        rho, _, _ = workloads.gaussian_pulse_fields(j.nx, j.ny, j.amp)
+        ref = oracle.Oracle(j.nx, j.ny, j.tau, j.c2).init(rho).step(j.steps).get_f()
+        err = max_rel_err(j.f, ref)
+        tol = 1e-5 * max(1.0, j.steps / 1000.0)
+        print(f"job {j.id} {j.nx}x{j.ny} tau {j.tau:.3f} c2 {j.c2:.3f} amp {j.amp:.3f} {j.steps} steps: "
+              f"max rel err {err:.2e}", flush=True)
+        assert err <= tol, (j.id, err)

@@ -92,25 +92,40 @@ def _pmc_csv(path, rows):
             w.writerow({"Kernel_Name": k, "Counter_Name": c, "Counter_Value": v})
 
 
-def test_traffic_record_scales_by_the_copy(tmp_path):
-    """HBM bytes from the counters: each counter is scaled by what it reads for
-    a copy of known size (FETCH_SIZE counts about half of the bytes read)."""
+def test_traffic_record_from_counters_of_known_units(tmp_path):
+    """HBM bytes from the counters: reads are 32, 64 and 128 bytes per request
+    of each size (DRAM reads in 32-byte units beside them), writes 64 bytes per
+    64-byte request and 32 per other request; the same counters on a copy of
+    known size give the units check."""
     from paper_0707_2437_amd import profiling
     k = "void lbm::step_vstack_kernel<float, false, 2, 8, true, false>(lbm::StepTile, int)"
-    _pmc_csv(tmp_path / "f.csv", [(k, "FETCH_SIZE", 400.0), (k, "FETCH_SIZE", 600.0), ("other", "FETCH_SIZE", 1e9)])
-    _pmc_csv(tmp_path / "w.csv", [(k, "WRITE_SIZE", 1000.0), (k, "WRITE_SIZE", 1000.0)])
-    _pmc_csv(tmp_path / "cf.csv", [("__amd_rocclr_copyBuffer", "FETCH_SIZE", 512.0)])
-    _pmc_csv(tmp_path / "cw.csv", [("__amd_rocclr_copyBuffer", "WRITE_SIZE", 1024.0)])
-    rec = profiling.traffic_record("float, false, 2, 8, true, false", str(tmp_path / "f.csv"),
-                                   str(tmp_path / "w.csv"), str(tmp_path / "cf.csv"), str(tmp_path / "cw.csv"),
-                                   1024.0 * 1024.0, 3 * 1024.0 * 1024.0)
-    assert rec["dispatches"] == {"fetch": 2, "write": 2}
-    assert rec["copy_reference"]["fetch_scale"] == 2.0 and rec["copy_reference"]["write_scale"] == 1.0
-    assert rec["read_bytes_per_launch"] == 500.0 * 1024 * 2 and rec["write_bytes_per_launch"] == 1000.0 * 1024
-    assert rec["traffic_over_algorithmic"] == (1000.0 * 1024 + 1000.0 * 1024) / (3 * 1024.0 * 1024.0)
+    rd = [(k, "TCC_EA0_RDREQ_32B_sum", 10.0), (k, "TCC_EA0_RDREQ_64B_sum", 20.0),
+          (k, "TCC_EA0_RDREQ_128B_sum", 100.0), (k, "TCC_EA0_RDREQ_DRAM_32B_sum", 460.0),
+          (k, "TCC_EA0_RDREQ_128B_sum", 300.0), (k, "TCC_EA0_RDREQ_32B_sum", 10.0),
+          (k, "TCC_EA0_RDREQ_64B_sum", 20.0), (k, "TCC_EA0_RDREQ_DRAM_32B_sum", 460.0),
+          ("other", "TCC_EA0_RDREQ_128B_sum", 1e9)]
+    _pmc_csv(tmp_path / "r.csv", rd)
+    _pmc_csv(tmp_path / "w.csv", [(k, "TCC_EA0_WRREQ_sum", 100.0), (k, "TCC_EA0_WRREQ_64B_sum", 90.0)])
+    c = "__amd_rocclr_copyBuffer"
+    _pmc_csv(tmp_path / "cr.csv", [(c, "TCC_EA0_RDREQ_32B_sum", 0.0), (c, "TCC_EA0_RDREQ_64B_sum", 0.0),
+                                   (c, "TCC_EA0_RDREQ_128B_sum", 8192.0), (c, "TCC_EA0_RDREQ_DRAM_32B_sum", 32768.0)])
+    _pmc_csv(tmp_path / "cw.csv", [(c, "TCC_EA0_WRREQ_sum", 16384.0), (c, "TCC_EA0_WRREQ_64B_sum", 16384.0)])
+    alg = 2.0 * 40000.0
+    rec = profiling.traffic_record("float, false, 2, 8, true, false", str(tmp_path / "r.csv"),
+                                   str(tmp_path / "w.csv"), str(tmp_path / "cr.csv"), str(tmp_path / "cw.csv"),
+                                   1024.0 * 1024.0, alg)
+    reads = 32 * 10.0 + 64 * 20.0 + 128 * 200.0  # the 128-byte count is the mean of two dispatches
+    writes = 64 * 90.0 + 32 * 10.0
+    assert rec["reads_per_dispatch"]["dispatches"] == 2 and rec["writes_per_dispatch"]["dispatches"] == 1
+    assert rec["read_bytes_per_launch"] == reads and rec["reads_per_dispatch"]["dram_bytes"] == 32 * 460.0
+    assert rec["write_bytes_per_launch"] == writes
+    assert rec["copy_check"] == {"bytes_each_way": 1024.0 * 1024.0, "read_ratio": 1.0, "dram_read_ratio": 1.0,
+                                 "write_ratio": 1.0}
+    assert rec["traffic_over_algorithmic"] == (reads + writes) / alg
+    assert rec["read_over_algorithmic"] == reads / (alg / 2)
     assert rec["kernel_source_sha256"] == profiling.kernel_source_sha()
     with pytest.raises(ValueError):
-        profiling.pmc_mean(str(tmp_path / "f.csv"), "no such kernel", "FETCH_SIZE")
+        profiling.pmc_mean(str(tmp_path / "r.csv"), "no such kernel", "TCC_EA0_RDREQ_32B_sum")
 
 
 def test_committed_traffic_record_matches_the_kernel_sources():

@@ -46,6 +46,11 @@ MUTANTS = {
     "seam_not_cut": ("fstar = crosses ? entered[i] : own[i];", "fstar = own[i];"),
     "boundary_collides": ("if (xbc && (x == 0 || x == nx - 1)) {", "if (xbc && x < 0) {"),
     "outlet_at_inlet_density": ("model_equilibrium(L, 1.0, 0.0, 0.0, fout);", "model_equilibrium(L, rho_in, 0.0, 0.0, fout);"),
+    # compensated totals
+    "totals_compensation_dropped": ("double v = sum[k] + comp[k];", "double v = sum[k];"),
+    "totals_compensation_sign_small_term": ("*comp += (*sum - t) + v;", "*comp -= (*sum - t) + v;"),
+    "totals_compensation_sign_large_term": ("*comp += (v - t) + *sum;", "*comp -= (v - t) + *sum;"),
+    "totals_compensation_branch_swapped": ("if (fabs(*sum) >= fabs(v))", "if (fabs(*sum) < fabs(v))"),
 }
 
 FAST_PINS = [os.path.join(ROOT, "tests", "test_oracle_pins.py"),

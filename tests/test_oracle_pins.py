@@ -169,6 +169,40 @@ def test_conservation_nonlinear_2d():
     assert np.all(np.abs(t1 - t0) <= 1e-12 * t0[0])
 
 
+def _site_values_in(lattice_shape, seq, plane):
+    """Populations of a state whose only nonzero population is plane `plane`,
+    holding seq[s] at site s in row-major order (the order of the totals)."""
+    ny, nx = lattice_shape
+    f = np.zeros((9, ny, nx))
+    f[plane].reshape(-1)[: len(seq)] = seq
+    return f
+
+
+# Site values whose exact sum is 2 while summing them in order in FP64 gives
+# 0: 1 + 2^60 rounds to 2^60 (a small term lost against a larger running
+# sum), 2^60 + 1 again, and -2^60 cancels. A compensated sum keeps both lost
+# ones; each of its two branches is taken (the running sum smaller, then
+# larger, than the term).
+CANCELLING = [1.0, 2.0 ** 60, 1.0, -(2.0 ** 60)]
+
+
+@pytest.mark.parametrize("plane, component", [(0, (0,)), (1, (0, 1)), (2, (0, 2)), (3, (0, 1))])
+def test_totals_are_the_exact_sum_of_site_values(plane, component):
+    """The totals M = sum rho, P = sum rho u (Eq. 3) are compensated sums in
+    row-major site order: on site values where a plain FP64 sum loses every
+    small term, they equal the exactly rounded sum (math.fsum). A state with
+    one nonzero plane i gives rho = f_i and rho u = f_i e_i at every site."""
+    shape = (3, 4)
+    exact = math.fsum(CANCELLING)
+    assert exact == 2.0 and sum(CANCELLING) == 0.0  # the case is sensitive
+    e = E_PAPER[plane]
+    expect = [exact, exact * e[0], exact * e[1]]
+    for order in (CANCELLING, CANCELLING[::-1], [2.0 ** 60, 1.0, 1.0, -(2.0 ** 60)]):
+        o = oracle.Oracle(shape[1], shape[0], 0.8, 0.2).set_f(_site_values_in(shape, order, plane))
+        _, _, _, tot = o.moments(check=False)
+        assert list(tot) == expect, (plane, order, tot)
+
+
 # ---------------------------------------------------------------- P6 ----
 @pytest.mark.parametrize("rho0", [1.0, 1.3])
 def test_rest_state_stays_at_rest_bitwise(rho0):
