@@ -274,7 +274,10 @@ size_t lbm_pool_device_bytes(const lbm_pool* P); /* device memory the pool holds
  * fragmented to hold it) or the device allocation fails. Slot ids of
  * removed lattices are reused. */
 int lbm_pool_add(lbm_pool* P, int nx, int ny, double tau, double c2);
-/* Release a slot (synchronises the pool's stream). */
+/* Release a slot. Its range may be given to a slot added later: work
+ * already queued on the pool's stream that reads this slot (a step, a
+ * lbm_pool_totals_device) runs before any later work on that range, since
+ * all pool work runs in order on the pool's stream. Does not wait. */
 int lbm_pool_remove(lbm_pool* P, int slot);
 
 /* As lbm_init / lbm_init_device for one slot; resets its time to 0. */
@@ -287,6 +290,13 @@ int lbm_pool_init_device(lbm_pool* P, int slot, const double* rho, const double*
 int lbm_pool_step(lbm_pool* P, const int* slots, const int* nsteps, int count);
 /* Wait for the pool's stream. */
 int lbm_pool_sync(lbm_pool* P);
+
+/* The totals {sum rho, sum rho u_x, sum rho u_y} of a slot's current state
+ * (as lbm_moments: FP64, fixed order) into a DEVICE array of 3 doubles,
+ * asynchronously on the pool's stream (no check of finiteness; a timed-out
+ * persistent launch is reported by the next lbm_pool_sync). The serving loop
+ * reads the totals of finished jobs this way while the next steps run. */
+int lbm_pool_totals_device(lbm_pool* P, int slot, double* totals);
 
 /* As lbm_moments / lbm_get_f for one slot (synchronous). */
 int lbm_pool_moments(lbm_pool* P, int slot, double* rho, double* ux, double* uy, double totals[3]);

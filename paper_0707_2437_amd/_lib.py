@@ -59,6 +59,7 @@ SIGNATURES = {
     "lbm_pool_step": (_i, [_vp, _vp, _vp, _i]),
     "lbm_pool_sync": (_i, [_vp]),
     "lbm_pool_moments": (_i, [_vp, _i, _vp, _vp, _vp, _vp]),
+    "lbm_pool_totals_device": (_i, [_vp, _i, _vp]),
     "lbm_pool_get_f": (_i, [_vp, _i, _vp]),
     "lbm_pool_time": (ctypes.c_longlong, [_vp, _i]),
     "lbm_pool_set_mode": (_i, [_vp, _i, _i]),

@@ -183,7 +183,9 @@ __global__ __launch_bounds__(64 * NW) void batch_persistent_kernel(const BatchLa
             }
             return a;
         };
-        auto issue = [&](const StepTile& a, const Unit& u, const VRow& r) { v.issue_all(a, a.src, r); };
+        auto issue = [&](const StepTile& a, const Unit& u, const VRow& r) {
+            v.issue_rt(a, a.src, r, edge_strip<T, VX>(a.g, u.t % a.nstrips));
+        };
         Unit u = find_unit(lats, item_lat, nitems, first, G, s);
         VRow r{};
         if (u.L) {
@@ -207,165 +209,6 @@ __global__ __launch_bounds__(64 * NW) void batch_persistent_kernel(const BatchLa
             u = n;
             r = rn;
             buf ^= 1;
-        }
-        if (!grid_barrier(bar, G, wait_ticks)) return;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Producer/consumer form of the persistent kernel. A workgroup has NW loader
-// waves, one per tile row (the halo rows included), and NW - 2 compute waves,
-// one per interior row. Loader waves only load: they issue a tile's window
-// loads, land them (populations and window densities, the same arithmetic
-// as the land phase of vstack_tile), publish the results in a
-// double-buffered LDS tile, and issue the next tile's loads at once. Compute
-// waves never load from global memory: they read their row from the LDS
-// tile, relax (the same relax phase) and store. A wave that has both loads
-// and stores outstanding can only wait for a load by waiting for the stores
-// too (the two share one counter and may complete in either order); with
-// the roles split, no wave ever waits for a store, and the loads of the next
-// tile are in flight while the current one is relaxed and stored. One
-// workgroup barrier per tile hands a buffer from the loaders to the compute
-// waves and back.
-template <class T, int VX, int NW> struct PcShared {
-    using C = typename CompT<T>::type;
-    static constexpr bool H = std::is_same<T, _Float16>::value;
-    static constexpr int WV = VX + 2;
-    static constexpr int WVP = WV <= 4 ? 4 : 8;       // padded for vector LDS access
-    static constexpr int NP = H ? (WV + 1) / 2 : VX;  // per lane and plane: d_i of the own columns,
-                                                      // or (FP16) the packed words of the window
-    using P = typename std::conditional<H, unsigned, C>::type;
-    C dens[2][NW][64][WVP];         // window densities of every tile row
-    P pop[2][NW - 2][9][64][NP];    // populations of the interior rows
-};
-
-// Whether the producer/consumer kernel exists for a shape: its workgroup
-// (2 NW - 2 waves) must fit 1024 work-items and its LDS tile the 160 KiB of
-// a CU.
-template <class T, int VX, int NW> constexpr bool pc_fits()
-{
-    // FP64 tiles (twice the registers and LDS) stay with the one-role kernel
-    return sizeof(T) <= 4 && 64 * (2 * NW - 2) <= 1024 && sizeof(PcShared<T, VX, NW>) + 256 <= 160 * 1024;
-}
-
-// Waves per SIMD that as many workgroups as the LDS tile allows on a CU
-// need (asked of the compiler, which then keeps the registers low enough).
-template <class T, int VX, int NW> constexpr int pc_waves_per_simd()
-{
-    const int wgs = (int)((160 * 1024) / (sizeof(PcShared<T, VX, NW>) + 256));
-    const int w = (wgs * (2 * NW - 2) + 3) / 4;
-    return w < 1 ? 1 : (w > 8 ? 8 : w);
-}
-
-template <class T, bool SHIFT, int VX, int NW, bool NTS>
-__global__ __launch_bounds__(64 * (2 * NW - 2))
-__attribute__((amdgpu_waves_per_eu(pc_waves_per_simd<T, VX, NW>(), 8))) void batch_persistent_pc_kernel(
-    const BatchLat* __restrict__ lats, const int* __restrict__ item_lat, int nitems, int nsteps_max, int ch,
-    unsigned* bar, unsigned long long wait_ticks)
-{
-    using V = VTile<T, SHIFT, VX, NW, NTS, false, false>;  // pools step the paper's model, centred on the weights
-    using S = PcShared<T, VX, NW>;
-    using C = typename S::C;
-    __shared__ S sh;
-    const int G = gridDim.x;
-    const int first = ch < 0 ? (int)blockIdx.x : xcd_tile(blockIdx.x, G, ch);
-    if (stale_barrier_error(bar)) return;
-    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int lane = threadIdx.x & 63;
-    for (int s = 0; s < nsteps_max; ++s) {
-        auto tile_of = [&](const Unit& u) {
-            StepTile a = ldc(&u.L->tile);
-            if ((ldc(&u.L->t0) + s) & 1) {
-                const void* b = a.src;
-                a.src = a.dst;
-                a.dst = const_cast<void*>(b);
-            }
-            return a;
-        };
-        auto next_of = [&](const Unit& u) {
-            return u.t + 1 < u.t1 ? Unit{u.L, u.i, u.t + 1, u.t1} : find_unit(lats, item_lat, nitems, u.i + G, G, s);
-        };
-        Unit u = find_unit(lats, item_lat, nitems, first, G, s);
-        if (wave < NW) {
-            // Loader of tile row `wave`. Every step of the loop issues one
-            // tile's loads, the same number whatever the tile: past the last
-            // tile of the step the loads of the last one are issued again
-            // (their values unused), so that the wait for a tile's loads is
-            // always the same count.
-            V v;
-            auto issue = [&](const Unit& w, VRow& r) {
-                const StepTile a = tile_of(w);
-                r = vrow<VX, NW>(a.g, w.t % a.nstrips, w.t / a.nstrips, wave);
-                v.issue_all(a, a.src, r);
-            };
-            VRow r{};
-            if (u.L) issue(u, r);
-            int buf = 0;
-            while (u.L) {
-                const Unit n = next_of(u);
-                if (r.load) {
-                    v.land_regs(tile_of(u));
-                    C* dd = &sh.dens[buf][wave][lane][0];
-                    if constexpr (S::WVP == V::WV) {
-                        Pack<C, S::WV> pw;
-#pragma unroll
-                        for (int j = 0; j < S::WV; ++j) pw.v[j] = v.w[j];
-                        *(Pack<C, S::WV>*)dd = pw;
-                    } else {
-#pragma unroll
-                        for (int j = 0; j < S::WV; ++j) dd[j] = v.w[j];
-                    }
-                    if (r.relax) {
-#pragma unroll
-                        for (int i = 0; i < 9; ++i) {
-                            Pack<typename S::P, S::NP> pp;
-#pragma unroll
-                            for (int q = 0; q < S::NP; ++q) {
-                                if constexpr (S::H) pp.v[q] = v.u[i][q];
-                                else pp.v[q] = v.d[i][q];
-                            }
-                            *(Pack<typename S::P, S::NP>*)&sh.pop[buf][wave - 1][i][lane][0] = pp;
-                        }
-                    }
-                }
-                __builtin_amdgcn_sched_barrier(0);  // tile u's registers are free only now
-                VRow rn{};
-                issue(n.L ? n : u, rn);
-                __syncthreads();  // tile u is in sh[buf]; the compute waves are done with sh[buf ^ 1]
-                u = n;
-                r = rn;
-                buf ^= 1;
-            }
-        } else {
-            // compute wave of interior row c
-            V v;
-            v.af = {};
-            const int c = wave - NW;
-            int buf = 0;
-            while (u.L) {
-                const Unit n = next_of(u);
-                __syncthreads();  // tile u is in sh[buf]
-                const StepTile a = tile_of(u);
-                const VRow r = vrow<VX, NW>(a.g, u.t % a.nstrips, u.t / a.nstrips, c + 1);
-                if (r.relax) {
-#pragma unroll
-                    for (int i = 0; i < 9; ++i) {
-                        const Pack<typename S::P, S::NP> pp = *(const Pack<typename S::P, S::NP>*)&sh.pop[buf][c][i][lane][0];
-#pragma unroll
-                        for (int q = 0; q < S::NP; ++q) {
-                            if constexpr (S::H) v.u[i][q] = pp.v[q];
-                            else v.d[i][q] = pp.v[q];
-                        }
-                    }
-#pragma unroll
-                    for (int j = 0; j < S::WV; ++j) v.w[j] = sh.dens[buf][c + 1][lane][j];
-                    v.relax_g(a, a.dst, r, [&](int j) {
-                        return sh.dens[buf][c + 2][lane][j + 1] - sh.dens[buf][c][lane][j + 1];
-                    });
-                }
-                u = n;
-                buf ^= 1;
-            }
         }
         if (!grid_barrier(bar, G, wait_ticks)) return;
     }
@@ -396,22 +239,20 @@ static hipError_t launch_batch_t(bool persistent, const BatchLat* lats, const in
                            item_lat, nitems, s_or_n, ch);
         return hipGetLastError();
     }
-    // the producer/consumer kernel where its workgroup and LDS tile fit,
-    // else the one-role kernel (the same results either way)
-    const void* kern = nullptr;
-    int threads = 64 * NW;
-    if constexpr (pc_fits<T, VX, NW>()) {
-        kern = (const void*)batch_persistent_pc_kernel<T, SHIFT, VX, NW, NTS>;
-        threads = 64 * (2 * NW - 2);
-    } else {
-        kern = (const void*)batch_persistent_kernel<T, SHIFT, VX, NW, NTS>;
-    }
+    const void* kern = (const void*)batch_persistent_kernel<T, SHIFT, VX, NW, NTS>;
+    const int threads = 64 * NW;
     int dev = 0, per_cu = 0, ncu = 0, clock_khz = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, dev);
     if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, 0);
     if (e != hipSuccess) return e;
+    // A kernel that needs scratch memory can have its waves held back by the
+    // scratch the runtime provides, so that not every workgroup is resident
+    // and the grid barrier cannot complete: refuse rather than launch.
+    hipFuncAttributes fa{};
+    if ((e = hipFuncGetAttributes(&fa, kern)) != hipSuccess) return e;
+    if (fa.localSizeBytes > 0) return hipErrorInvalidConfiguration;
     int grid = per_cu * ncu;
     if (max_grid > 0 && grid > max_grid) grid = max_grid;
     // a grid that is a multiple of 8 ch (or of 8) makes xcd_tile a permutation

@@ -102,12 +102,6 @@ size_t slot_bytes(int nx, int ny, int dtype, Geom* g_out, size_t* red_at = nullp
     return SlotArena::round(at + red_doubles(g) * sizeof(double));
 }
 
-// Waves per workgroup of the batched kernels in the pool's mode: the
-// persistent kernel's producer/consumer form takes twice as many waves as
-// tile rows (and so at most 8 rows of waves, 1024 work-items); the tile
-// shape does not change results.
-int batch_nw(const lbm_pool* P) { return (P->mode == LBM_POOL_PERSISTENT && P->nw > 8) ? 8 : P->nw; }
-
 // The descriptor of a slot for vertical-stack tiles of vx columns per lane
 // and nw waves (the shape of the launch that reads it).
 StepTile slot_tile(const Slot& S, int vx, int nw)
@@ -182,7 +176,7 @@ hipError_t run_batch(lbm_pool* P, int nmax)
     if (e != hipSuccess) return e;
     const bool nts = P->nts != 0;
     if (P->mode == LBM_POOL_PERSISTENT)
-        return launch_batch(P->dtype, P->vx, batch_nw(P), nts, true, P->d_lats, P->d_items, nitems, nmax,
+        return launch_batch(P->dtype, P->vx, P->nw, nts, true, P->d_lats, P->d_items, nitems, nmax,
                             P->max_grid, P->xcd_chunk, P->d_bar, P->stream);
     if (P->mode == LBM_POOL_GRAPH) {
         GraphEntry* ge = nullptr;
@@ -334,11 +328,13 @@ int lbm_pool_remove(lbm_pool* P, int slot)
 {
     Slot* S = slot_of(P, slot);
     if (!S) return LBM_EINVAL;
-    hipError_t e = hipStreamSynchronize(P->stream);
+    // No wait: all pool work runs in order on the pool's stream, so work
+    // queued on a later slot in the same range runs after the work already
+    // queued on this one.
     if (S->buf) P->arena.give(S->buf, S->span);
     P->used -= S->bytes;
     *S = Slot();
-    return status_of(e);
+    return LBM_OK;
 }
 
 int lbm_pool_init(lbm_pool* P, int slot, const double* rho, const double* ux, const double* uy)
@@ -388,7 +384,7 @@ int lbm_pool_step(lbm_pool* P, const int* slots, const int* nsteps, int count)
             if (slots[j] == slots[k]) return LBM_EINVAL;  // a slot listed twice
         if (nsteps[k] == 0) continue;
         BatchLat b{};
-        b.tile = slot_tile(*S, P->vx, batch_nw(P));
+        b.tile = slot_tile(*S, P->vx, P->nw);
         b.t0 = S->t;
         b.nsteps = nsteps[k];
         add_lattice(P, b);
@@ -448,6 +444,14 @@ int lbm_pool_moments(lbm_pool* P, int slot, double* rho, double* ux, double* uy,
     for (double v : tot)
         if (!std::isfinite(v)) return LBM_ENONFINITE;
     return LBM_OK;
+}
+
+int lbm_pool_totals_device(lbm_pool* P, int slot, double* totals)
+{
+    Slot* S = slot_of(P, slot);
+    if (!S || !totals) return LBM_EINVAL;
+    if (!S->ready) return LBM_ESTATE;
+    return status_of(launch_moments(P->dtype, cur_buf(*S), S->g, nullptr, nullptr, nullptr, S->red, totals, P->stream));
 }
 
 int lbm_pool_get_f(lbm_pool* P, int slot, double* f)

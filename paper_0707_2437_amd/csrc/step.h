@@ -304,42 +304,21 @@ __device__ __forceinline__ void gather_raw(const char* const (&pb)[9], const Geo
     }
 }
 
-// The windows of a lane element by element, every element from its
-// periodic column (a source column below 0 or at or past nx wraps): the
-// values gather_raw loads and patches, for any strip, in one code path with
-// no lane-divergent branch. The number of loads a wave issues is then fixed,
-// so that waiting for them can be counted while the loads of a later tile
-// are in flight. A source column is x + k with k in [-2, NV - 1] (NV the
-// window length); each k's wrapped column is formed once.
-template <class T, int NV, class LT, int NL>
-__device__ __forceinline__ void wrapped_loads(const char* const (&rb)[9], const Geom& g, int x, Pack<LT, NL> (&v)[9])
-{
-    static_assert(sizeof(LT) == sizeof(T) && NL == NV, "element-wise registers");
-    constexpr int ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
-    constexpr unsigned es = sizeof(T);
-    unsigned off[NV + 2];  // byte offset of source column x + k, k = -2 .. NV - 1
-#pragma unroll
-    for (int k = -2; k < NV; ++k) {
-        const int c = x + k;
-        const int cw = c < 0 ? c + g.nx : (c >= g.nx ? c - g.nx : c);
-        off[k + 2] = (unsigned)(cw + 2) * es;
-    }
-#pragma unroll
-    for (int i = 0; i < 9; ++i)
-#pragma unroll
-        for (int j = 0; j < NV; ++j) v[i].v[j] = ld_g<T>(rb[i] + (size_t)off[j - 1 - ex[i] + 2]);
-}
-
-// The window loads of one row for the persistent batched kernel: for FP16
-// storage (ghost columns) the vector windows, else wrapped_loads.
+// As gather_raw, with the edge patch chosen at run time (`edge`, uniform over
+// the workgroup): the window loads are one code path for every tile, and an
+// edge strip adds the patch loads, which write the wrapped elements into the
+// same registers.
 template <class T, int NV, class LT = T, int NL = NV>
-__device__ __forceinline__ void gather_raw_rt(const char* const (&pb)[9], const Geom& g, int r, int x,
+__device__ __forceinline__ void gather_raw_rt(const char* const (&pb)[9], const Geom& g, int r, int x, bool edge,
                                               Pack<LT, NL> (&v)[9])
 {
     const char* rb[9];
     row_bases<T>(pb, g, r, rb);
-    if constexpr (GhostCols<T>::value) window_loads<T, NV, LT, NL>(rb, x, v);
-    else wrapped_loads<T, NV, LT, NL>(rb, g, x, v);
+    window_loads<T, NV, LT, NL>(rb, x, v);
+    if constexpr (!GhostCols<T>::value) {
+        if (edge)
+            if (x < 2 || x + NV > g.nx) patch_edges<T, NV, LT, NL>(rb, g, x, v);
+    }
 }
 
 // A column of nine populations d_i (one site) as seen by the arithmetic
@@ -637,7 +616,6 @@ template <bool FIELD, class C> __device__ __forceinline__ CoefC<C> site_coef(con
 struct VRow {
     int wave, lane;
     int y, x, nv;  // lattice row (-1 .. ny: wraps by index), first column, columns held (<= VX)
-    bool rowok;    // the wave's row is one of the tile's (uniform over the wave)
     bool load;     // the lane loads a row (a halo or interior row, columns inside the lattice)
     bool relax;    // ... and relaxes and writes it (interior rows)
 };
@@ -654,8 +632,7 @@ template <int VX, int NW> __device__ __forceinline__ VRow vrow(const Geom& g, in
     r.y = y0 - 1 + r.wave;
     r.x = strip * (64 * VX) + r.lane * VX;
     r.nv = min(VX, g.nx - r.x);
-    r.rowok = r.wave <= nrows + 1;  // waves past the bottom halo idle
-    r.load = r.nv > 0 && r.rowok;
+    r.load = r.nv > 0 && r.wave <= nrows + 1;  // waves past the bottom halo idle
     r.relax = r.load && r.wave >= 1 && r.wave <= nrows;
     return r;
 }
@@ -738,15 +715,16 @@ template <class T, bool SHIFT, int VX, int NW, bool NTS, bool FIELD, bool RC> st
     {
         if (r.load) issue_rows<EDGE>(a, src, r);
     }
-    // issue for any strip and lane in one code path (see gather_raw_rt):
-    // every lane issues the same loads; a lane with no row to load reads row
-    // 0, column 0 instead, and its values are not used
-    __device__ __forceinline__ void issue_all(const StepTile& a, const void* src, const VRow& r)
+    // issue with the edge patch chosen at run time (see gather_raw_rt)
+    __device__ __forceinline__ void issue_rt(const StepTile& a, const void* src, const VRow& r, bool edge)
     {
-        static_assert(!FIELD, "pools have no c2 field");
-        const char* sb[9];
-        src_bases<T>(src, a.g, sb);
-        gather_raw_rt<T, WV, T, WV>(sb, a.g, r.rowok ? r.y : 0, r.load ? r.x : 0, raw);
+        if (r.load) {
+            const char* sb[9];
+            src_bases<T>(src, a.g, sb);
+            gather_raw_rt<T, WV, T, WV>(sb, a.g, r.y, r.x, edge, raw);
+            if constexpr (FIELD)
+                if (r.relax) af = field_row<C, VX>(a, r.y, r.x);
+        }
     }
     __device__ __forceinline__ void land(const StepTile& a, const VRow& r, Lds& lds)
     {
@@ -834,12 +812,9 @@ template <class T, bool SHIFT, int VX, int NW, bool NTS, bool FIELD, bool RC> st
     {
         if (r.load) issue_rows<EDGE>(a, src, r);
     }
-    __device__ __forceinline__ void issue_all(const StepTile& a, const void* src, const VRow& r)
+    __device__ __forceinline__ void issue_rt(const StepTile& a, const void* src, const VRow& r, bool)
     {
-        static_assert(!FIELD, "pools have no c2 field");
-        const char* sb[9];
-        src_bases<T>(src, a.g, sb);
-        gather_raw<T, WV, unsigned, NWD, false>(sb, a.g, r.rowok ? r.y : 0, r.load ? r.x : 0, raw);
+        if (r.load) issue_rows<false>(a, src, r);
     }
     __device__ __forceinline__ void land(const StepTile& a, const VRow& r, Lds& lds)
     {

@@ -119,6 +119,11 @@ class Pool:
             raise LBMError(st, "lbm_pool_moments")
         return tot, st
 
+    def totals_device(self, slot, out):
+        """lbm_pool_totals_device: the slot's totals into `out`, a float64 CUDA
+        tensor of 3 elements (or a view of 3), asynchronously on the pool's stream."""
+        _check(self._L.lbm_pool_totals_device(self._h, int(slot), _dptr(out, 3)), "lbm_pool_totals_device")
+
     def get_f(self, slot):
         ny, nx = self.shapes[slot]
         f = np.empty((9, ny, nx))

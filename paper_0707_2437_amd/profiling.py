@@ -75,6 +75,15 @@ def trace_summary(path, kernel_regex=None, top=20):
     return "\n".join(lines)
 
 
+def most_common_grid(path, kernel_regex):
+    """The launch grid (work-items) of most dispatches of the matching kernels."""
+    rx = re.compile(kernel_regex)
+    grids = [int(r["Grid_Size"]) for r in csv.DictReader(open(path)) if rx.search(r["Kernel_Name"])]
+    if not grids:
+        raise ValueError(f"no dispatches of /{kernel_regex}/ in {path}")
+    return max(set(grids), key=grids.count)
+
+
 def pmc_mean(path, kernel_regex, counter, grid=None):
     """Mean counter value per dispatch of the kernels whose name matches (and,
     with `grid`, whose launch grid is that many work-items: one kernel
@@ -113,7 +122,7 @@ def write_bytes(path, kernel_regex, grid=None):
     return {"requests": n, "requests_64B": n64, "bytes": 64.0 * n64 + 32.0 * (n - n64), "dispatches": nd}
 
 
-COPY_REGEX = "copyBuffer|elementwise"
+COPY_REGEX = "copyBuffer"
 
 
 def traffic_record(kernel_regex, reads, writes, copy_reads, copy_writes, copy_bytes, algorithmic_bytes, grid=None,
@@ -159,7 +168,8 @@ def main(argv=None):
         t.add_argument("--" + k, required=True)
     t.add_argument("--copy-bytes", type=float, default=float(1 << 30))
     t.add_argument("--algorithmic-bytes", type=float, required=True)
-    t.add_argument("--grid", type=int, default=None, help="only dispatches with this many work-items")
+    t.add_argument("--grid", default=None,
+                   help="only dispatches with this many work-items ('auto': the most common grid)")
     t.add_argument("--sources", default="step", choices=sorted(KERNEL_SOURCES),
                    help="which kernels' sources the record is tied to")
     a = p.parse_args(argv)
@@ -168,8 +178,13 @@ def main(argv=None):
     elif a.cmd == "trace":
         print(trace_summary(a.csv, a.kernel))
     else:
+        grid = a.grid
+        if grid == "auto":
+            grid = most_common_grid(a.reads, a.kernel)
+        elif grid is not None:
+            grid = int(grid)
         rec = traffic_record(a.kernel, a.reads, a.writes, a.copy_reads, a.copy_writes, a.copy_bytes,
-                             a.algorithmic_bytes, a.grid, a.sources)
+                             a.algorithmic_bytes, grid, a.sources)
         rec["kernel"] = a.name
         with open(a.out, "w") as f:
             json.dump(rec, f, indent=1)

@@ -6,9 +6,12 @@ slots whenever the pool's device-memory budget has room, keeps their
 lattices resident, and in every tick advances all resident jobs together by
 up to `tick_steps` steps each in one batched pool call (each job by exactly
 what it still needs), so jobs that arrive while others run join the next
-tick and their work overlaps on the device. Finished jobs have their
-conservation totals read (a non-finite total marks the job failed), their
-slot freed, and their latency (arrival to completion) recorded.
+tick and their work overlaps on the device. The host does not wait for a
+tick before queueing the next: the jobs a tick finishes have their
+conservation totals queued on the device behind it and their slots released
+at once (all pool work runs in order on one stream), and the totals are read
+back one tick later, while the next tick runs. A non-finite total marks a
+job failed; completion time is when the host reads its totals.
 
     python -m paper_0707_2437_amd.serve --rate 50 --duration 600 --budget-gb 200
 
@@ -80,7 +83,7 @@ def pulse_field_device(torch, nx, ny, amp, device="cuda"):
 
 
 class Server:
-    def __init__(self, budget_bytes, dtype="f32", tick_steps=100, stream=None, keep_f=False):
+    def __init__(self, budget_bytes, dtype="f32", tick_steps=100, stream=None, keep_f=False, progress_every=0.0):
         import torch
 
         self.torch = torch
@@ -91,14 +94,33 @@ class Server:
         self.stream = stream if stream is not None else torch.cuda.Stream()
         self.pool.set_stream(self.stream)
         self.keep_f = keep_f
+        self.progress_every = float(progress_every)
         self.queue = []       # admitted order: FIFO
         self.running = {}     # slot -> job
         self.finished = []
+        self.pending = []     # queued ticks not yet read back
         self.site_updates = 0
         self.gpu_seconds = 0.0
         self.ticks = 0
+        # ring of rows for the totals of finishing jobs: device rows written
+        # by lbm_pool_totals_device, copied to pinned host rows
+        self._ring = 0
+        self._ring_dev = None
+        self._ring_host = None
+        self._ensure_ring(1024)
+
+    def _ensure_ring(self, rows):
+        if self._ring_dev is not None and self._ring_dev.shape[0] >= rows:
+            return
+        torch = self.torch
+        self.drain(keep=0)  # no queued tick still writes the old ring
+        with torch.cuda.stream(self.stream):
+            self._ring_dev = torch.empty((rows, 3), dtype=torch.float64, device="cuda")
+        self._ring_host = torch.empty((rows, 3), dtype=torch.float64, pin_memory=True)
+        self._ring = 0
 
     def close(self):
+        self.drain(keep=0)
         self.pool.close()
 
     def submit(self, job):
@@ -127,43 +149,68 @@ class Server:
             job.slot, job.remaining, job.t_admit, job.status = slot, job.steps, now, "running"
             self.running[slot] = job
 
-    def _complete(self, job, now):
-        tot, st = self.pool.totals(job.slot)
-        job.totals = [float(v) for v in tot]
-        job.status = "done" if st == 0 else "failed"
-        if self.keep_f:
-            job.f = self.pool.get_f(job.slot)
-        self.pool.remove(job.slot)
-        del self.running[job.slot]
-        job.t_done = now
-        self.finished.append(job)
-
     def tick(self, now):
-        """Admit, advance every resident job by up to tick_steps, retire the
-        finished ones. Returns the GPU time of the step in seconds."""
+        """Admit, queue the next steps of every resident job (one batched pool
+        call), and queue the totals of the jobs these steps finish, releasing
+        their slots. Nothing here waits for the device (keep_f aside)."""
+        torch = self.torch
         self._admit(now)
         if not self.running:
-            return 0.0
+            return
         slots = list(self.running)
         nsteps = [min(self.tick_steps, self.running[s].remaining) for s in slots]
-        ev0 = self.torch.cuda.Event(enable_timing=True)
-        ev1 = self.torch.cuda.Event(enable_timing=True)
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
         ev0.record(self.stream)
         self.pool.step(slots, nsteps)
         ev1.record(self.stream)
-        ev1.synchronize()
-        dt = ev0.elapsed_time(ev1) / 1e3
-        self.gpu_seconds += dt
         self.ticks += 1
+        done = []
         for s, n in zip(slots, nsteps):
             job = self.running[s]
             job.remaining -= n
             self.site_updates += n * job.sites
-        return dt
+            if job.remaining == 0:
+                done.append(job)
+        entry = {"ev0": ev0, "ev1": ev1, "jobs": done}
+        if done:
+            if self._ring + len(done) > self._ring_dev.shape[0]:
+                self._ensure_ring(max(2 * self._ring_dev.shape[0], len(done)))
+                if self._ring + len(done) > self._ring_dev.shape[0]:
+                    self.drain(keep=0)
+                    self._ring = 0
+            r0 = self._ring
+            for k, job in enumerate(done):
+                self.pool.totals_device(job.slot, self._ring_dev[r0 + k])
+                if self.keep_f:
+                    job.f = self.pool.get_f(job.slot)
+                self.pool.remove(job.slot)
+                del self.running[job.slot]
+                job.status = "retiring"
+            rows = slice(r0, r0 + len(done))
+            with torch.cuda.stream(self.stream):
+                self._ring_host[rows].copy_(self._ring_dev[rows], non_blocking=True)
+            evd = torch.cuda.Event()
+            evd.record(self.stream)
+            entry.update({"rows": rows, "done_ev": evd})
+            self._ring = (r0 + len(done)) % self._ring_dev.shape[0]
+        self.pending.append(entry)
 
-    def retire(self, now):
-        for s in [s for s, j in self.running.items() if j.remaining == 0]:
-            self._complete(self.running[s], now)
+    def drain(self, keep=1):
+        """Read back every queued tick but the last `keep`: GPU time, and the
+        totals of the jobs they finished (which completes those jobs)."""
+        while len(self.pending) > keep:
+            e = self.pending.pop(0)
+            (e.get("done_ev") or e["ev1"]).synchronize()
+            now = time.perf_counter() - self._t0
+            self.gpu_seconds += e["ev0"].elapsed_time(e["ev1"]) / 1e3
+            if e["jobs"]:
+                tot = self._ring_host[e["rows"]].tolist()
+                for job, t in zip(e["jobs"], tot):
+                    job.totals = [float(v) for v in t]
+                    job.status = "done" if all(math.isfinite(v) for v in t) else "failed"
+                    job.t_done = now
+                    self.finished.append(job)
 
     def run(self, jobs, duration, drain=False):
         """Serve `jobs` (arrival times in seconds from now, honoured in real
@@ -171,21 +218,31 @@ class Server:
         keep going until every job has arrived and finished."""
         pending = sorted(jobs, key=lambda j: j.arrival)
         k = 0
-        t0 = time.perf_counter()
+        self._t0 = t0 = time.perf_counter()
+        next_report = self.progress_every if self.progress_every > 0 else math.inf
         while True:
             now = time.perf_counter() - t0
             while k < len(pending) and pending[k].arrival <= now:
                 self.submit(pending[k])
                 k += 1
+            if now >= next_report:
+                print(f"# served t={now:.0f}s arrived {k} completed {len(self.finished)} running "
+                      f"{len(self.running)} waiting {len(self.queue)} MLUPS {self.site_updates / now / 1e6:.0f}",
+                      file=sys.stderr, flush=True)
+                next_report += self.progress_every
             if now >= duration and not drain:
                 break
             if not self.running and not self.queue:
+                if self.pending:
+                    self.drain(keep=0)
+                    continue
                 if k >= len(pending):
                     break
                 time.sleep(min(0.01, max(0.0, pending[k].arrival - now)))
                 continue
             self.tick(now)
-            self.retire(time.perf_counter() - t0)
+            self.drain(keep=1)  # the tick before this one, while this one runs
+        self.drain(keep=0)
         elapsed = time.perf_counter() - t0
         return self.stats(len(pending), k, elapsed)
 
@@ -204,7 +261,8 @@ class Server:
             "site_updates": self.site_updates, "mlups": self.site_updates / elapsed / 1e6 if elapsed > 0 else None,
             "mlups_while_busy": self.site_updates / self.gpu_seconds / 1e6 if self.gpu_seconds > 0 else None,
             "latency_p50_s": pct(lat, 50), "latency_p99_s": pct(lat, 99),
-            "queue_wait_p50_s": pct(wait, 50), "service_p50_s": pct(serv, 50),
+            "queue_wait_p50_s": pct(wait, 50), "queue_wait_p99_s": pct(wait, 99),
+            "service_p50_s": pct(serv, 50), "service_p99_s": pct(serv, 99),
             "pool_used_bytes": self.pool.used_bytes,
             "pool_device_bytes": self.pool.device_bytes,
         }
@@ -222,17 +280,23 @@ def main(argv=None):
     p.add_argument("--dtype", default="f32", choices=list(_lattice.DTYPES))
     p.add_argument("--tick-steps", type=int, default=100)
     p.add_argument("--seed", type=int, default=0)
+    p.add_argument("--progress-every", type=float, default=30.0, help="seconds between progress lines (stderr)")
+    p.add_argument("--out", default=None, help="also write the JSON statistics to this file")
     a = p.parse_args(argv)
     import torch
 
     torch.cuda.set_device(0)
     jobs = job_stream(a.rate, a.duration, seed=a.seed)
-    srv = Server(int(a.budget_gb * 1e9), a.dtype, a.tick_steps)
+    srv = Server(int(a.budget_gb * 1e9), a.dtype, a.tick_steps, progress_every=a.progress_every)
     st = srv.run(jobs, a.duration)
     st.update({"rate_per_s": a.rate, "duration_s": a.duration, "budget_gb": a.budget_gb, "dtype": a.dtype,
-               "tick_steps": a.tick_steps, "offered_mlups": offered_mlups(jobs, a.duration)})
+               "tick_steps": a.tick_steps, "offered_mlups": offered_mlups(jobs, a.duration),
+               "command": "python -m paper_0707_2437_amd.serve " + " ".join(argv if argv is not None else sys.argv[1:])})
     srv.close()
     print(json.dumps(st), flush=True)
+    if a.out:
+        with open(a.out, "w") as fh:
+            json.dump(st, fh, indent=1)
 
 
 if __name__ == "__main__":
