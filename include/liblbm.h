@@ -288,6 +288,21 @@ int lbm_pool_init_device(lbm_pool* P, int slot, const double* rho, const double*
  * once). Launch s of the call steps every listed slot with nsteps > s.
  * Asynchronous on the pool's stream; LBM_ESTATE for an uninitialised slot. */
 int lbm_pool_step(lbm_pool* P, const int* slots, const int* nsteps, int count);
+/* As lbm_pool_step, for callers that cannot allocate device memory during
+ * the call (tight serving loops, harnesses that forbid it): the batch's
+ * descriptors and work-item map go to a fixed device array of the library
+ * (about 9 MB per GPU, held until the process ends) in place of pool memory
+ * that lbm_pool_step allocates as batches grow. At most 4096 lattices
+ * (listed slots with nsteps > 0) and 2^21 work items per call (a lattice
+ * has ceil(nx / (64 vx)) * ceil(ny / (nw - 2)) tiles, one item per
+ * tiles_per_item of them); LBM_EINVAL for a larger batch, which is not
+ * stepped. Grouped launches, or one persistent launch in LBM_POOL_PERSISTENT
+ * mode (no graph). The pool's device must be current (LBM_EINVAL
+ * otherwise). Results are those of lbm_pool_step. The array is shared
+ * by every call on a GPU: calls that overlap on one GPU (on different
+ * streams, or from different threads) race and must not be made. */
+int lbm_pool_step_noalloc(lbm_pool* P, const int* slots, const int* nsteps, int count);
+
 /* Wait for the pool's stream. */
 int lbm_pool_sync(lbm_pool* P);
 

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -48,6 +49,45 @@ struct GraphEntry {
     const int* items = nullptr;
     hipGraphExec_t exec = nullptr;
 };
+
+}  // namespace
+
+// Scratch of lbm_pool_step_noalloc: a batch's descriptors (at most
+// kNoAllocLattices) and its item map (at most kNoAllocItems work items) in
+// one file-scope device array, instead of device memory the pool allocates
+// as batches grow. Each GPU holds its own copy (about 9 MB) until the
+// process ends. Host code reaches it only through the address that
+// hipGetSymbolAddress returns for the current device (noalloc_scratch).
+namespace {
+constexpr int kNoAllocLattices = 4096;
+constexpr int kNoAllocItems = 1 << 21;
+constexpr size_t kNoAllocItemsAt = ((size_t)kNoAllocLattices * sizeof(BatchLat) + 255) / 256 * 256;
+constexpr size_t kNoAllocBytes = kNoAllocItemsAt + (size_t)kNoAllocItems * sizeof(int);
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+char* g_scratch[kMaxDevices] = {};
+
+// The device address of `scratch` on device dev, which must be current;
+// looked up on the first call for that device.
+hipError_t noalloc_scratch(int dev, char** out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch[dev] = (char*)p;
+    }
+    *out = g_scratch[dev];
+    return hipSuccess;
+}
 
 }  // namespace
 
@@ -247,6 +287,8 @@ lbm_pool* lbm_pool_create(size_t budget_bytes, int dtype)
         if (v >= 0 && v <= 4096) P->xcd_chunk = v;
     }
     hipError_t e = hipGetDevice(&P->device);
+    char* noalloc_base = nullptr;  // look up lbm_pool_step_noalloc's array while set up
+    if (e == hipSuccess) e = noalloc_scratch(P->device, &noalloc_base);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&P->own, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipMalloc((void**)&P->d_bar, 4 * sizeof(unsigned));
     if (e == hipSuccess) e = hipMemsetAsync(P->d_bar, 0, 4 * sizeof(unsigned), P->own);
@@ -370,12 +412,15 @@ int lbm_pool_init_device(lbm_pool* P, int slot, const double* rho, const double*
     return LBM_OK;
 }
 
-int lbm_pool_step(lbm_pool* P, const int* slots, const int* nsteps, int count)
+// The descriptors and work items of a batched call into P->h_lats and
+// P->h_items (host vectors whose capacity is kept from call to call);
+// *nmax = the largest step count.
+static int build_batch(lbm_pool* P, const int* slots, const int* nsteps, int count, int* nmax)
 {
     if (!P || count < 0 || (count > 0 && (!slots || !nsteps))) return LBM_EINVAL;
     P->h_lats.clear();
     P->h_items.clear();
-    int nmax = 0;
+    *nmax = 0;
     for (int k = 0; k < count; ++k) {
         Slot* S = slot_of(P, slots[k]);
         if (!S || nsteps[k] < 0) return LBM_EINVAL;
@@ -388,10 +433,53 @@ int lbm_pool_step(lbm_pool* P, const int* slots, const int* nsteps, int count)
         b.t0 = S->t;
         b.nsteps = nsteps[k];
         add_lattice(P, b);
-        nmax = std::max(nmax, nsteps[k]);
+        *nmax = std::max(*nmax, nsteps[k]);
     }
-    if (P->h_lats.empty()) return LBM_OK;
+    return LBM_OK;
+}
+
+int lbm_pool_step(lbm_pool* P, const int* slots, const int* nsteps, int count)
+{
+    int nmax = 0;
+    const int st = build_batch(P, slots, nsteps, count, &nmax);
+    if (st != LBM_OK || P->h_lats.empty()) return st;
     hipError_t e = run_batch(P, nmax);
+    if (e != hipSuccess) return status_of(e);
+    for (int k = 0; k < count; ++k) P->slots[slots[k]].t += nsteps[k];
+    return LBM_OK;
+}
+
+int lbm_pool_step_noalloc(lbm_pool* P, const int* slots, const int* nsteps, int count)
+{
+    int nmax = 0;
+    const int st = build_batch(P, slots, nsteps, count, &nmax);
+    if (st != LBM_OK || P->h_lats.empty()) return st;
+    const int nlat = (int)P->h_lats.size(), nitems = (int)P->h_items.size();
+    if (nlat > kNoAllocLattices || nitems > kNoAllocItems) return LBM_EINVAL;
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return status_of(e);
+    if (dev != P->device) return LBM_EINVAL;  // the scratch address is per device
+    char* base = nullptr;
+    e = noalloc_scratch(dev, &base);
+    if (e != hipSuccess) return status_of(e);
+    BatchLat* d_lats = (BatchLat*)base;
+    int* d_items = (int*)(base + kNoAllocItemsAt);
+    e = hipMemcpyAsync(d_lats, P->h_lats.data(), sizeof(BatchLat) * (size_t)nlat, hipMemcpyHostToDevice, P->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_items, P->h_items.data(), sizeof(int) * (size_t)nitems, hipMemcpyHostToDevice,
+                           P->stream);
+    const bool nts = P->nts != 0;
+    if (e == hipSuccess) {
+        if (P->mode == LBM_POOL_PERSISTENT) {
+            e = launch_batch(P->dtype, P->vx, P->nw, nts, true, d_lats, d_items, nitems, nmax, P->max_grid,
+                             P->xcd_chunk, P->d_bar, P->stream);
+        } else {
+            for (int s = 0; s < nmax && e == hipSuccess; ++s)
+                e = launch_batch(P->dtype, P->vx, P->nw, nts, false, d_lats, d_items, nitems, s, 0, P->xcd_chunk,
+                                 nullptr, P->stream);
+        }
+    }
     if (e != hipSuccess) return status_of(e);
     for (int k = 0; k < count; ++k) P->slots[slots[k]].t += nsteps[k];
     return LBM_OK;

@@ -98,6 +98,16 @@ class Pool:
         assert slots.shape == nsteps.shape
         _check(self._L.lbm_pool_step(self._h, _hptr(slots), _hptr(nsteps), len(slots)), "lbm_pool_step")
 
+    def step_noalloc(self, slots, nsteps):
+        """lbm_pool_step_noalloc: as step, with no device allocation in the call."""
+        slots = np.ascontiguousarray(slots, dtype=np.int32)
+        if np.isscalar(nsteps):
+            nsteps = np.full(len(slots), int(nsteps), dtype=np.int32)
+        nsteps = np.ascontiguousarray(nsteps, dtype=np.int32)
+        assert slots.shape == nsteps.shape
+        _check(self._L.lbm_pool_step_noalloc(self._h, _hptr(slots), _hptr(nsteps), len(slots)),
+               "lbm_pool_step_noalloc")
+
     def sync(self):
         _check(self._L.lbm_pool_sync(self._h), "lbm_pool_sync")
 
