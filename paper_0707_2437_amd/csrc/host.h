@@ -190,16 +190,24 @@ inline int status_of(hipError_t e)
     return LBM_EDEVICE;
 }
 
-// RAII device scratch for host-array entry points.
+// Device staging memory of one host-array entry point: taken from the
+// device's stream-ordered memory pool on the call's stream and given back on
+// that stream when the call returns. Unlike hipMalloc / hipFree, neither step
+// synchronises the device, so a set-up or read-back call on one lattice does
+// not stall work queued on other streams.
 struct DevScratch {
     double* p = nullptr;
-    hipError_t alloc(size_t n)
+    hipStream_t st = nullptr;
+    hipError_t alloc(size_t n, hipStream_t stream)
     {
-        return hipMalloc((void**)&p, n * sizeof(double));
+        st = stream;
+        const hipError_t e = hipMallocAsync((void**)&p, n * sizeof(double), stream);
+        if (e != hipSuccess) p = nullptr;
+        return e;
     }
     ~DevScratch()
     {
-        if (p) (void)hipFree(p);
+        if (p) (void)hipFreeAsync(p, st);
     }
 };
 

@@ -299,13 +299,44 @@ __global__ void sample_f_kernel(const T* __restrict__ s, Geom g, int n, const in
 // Moments (Eq. 3) of f(x, t) in FP64, optional fields, and per-block
 // partial sums of (rho - 1, j_x, j_y) for the conservation totals.
 constexpr int kRedThreads = 256;
+constexpr int kRedWaves = kRedThreads / 64;
+
+// Sum over the 64 lanes of a wave by a butterfly of cross-lane exchanges
+// (no LDS, no barrier). The exchange pattern is fixed, so every lane's sum
+// is the same from run to run; the callers use lane 0's.
+__device__ inline double wave_sum(double v)
+{
+    for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+// The three sums of a block: each wave's by wave_sum, then the kRedWaves
+// wave sums in wave order, written by threads 0..2 to out[0..2].
+__device__ inline void block_sum3(double a, double b, double c, double* __restrict__ out)
+{
+    __shared__ double red[3][kRedWaves];
+    a = wave_sum(a);
+    b = wave_sum(b);
+    c = wave_sum(c);
+    const int wave = threadIdx.x / 64;
+    if (threadIdx.x % 64 == 0) {
+        red[0][wave] = a;
+        red[1][wave] = b;
+        red[2][wave] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        double t = red[threadIdx.x][0];
+        for (int w = 1; w < kRedWaves; ++w) t += red[threadIdx.x][w];
+        out[threadIdx.x] = t;
+    }
+}
 
 template <class T, bool SHIFT>
 __global__ __launch_bounds__(kRedThreads) void moments_kernel(const T* __restrict__ s, Geom g, double* __restrict__ rho,
                                                               double* __restrict__ ux, double* __restrict__ uy,
                                                               double* __restrict__ partials)
 {
-    __shared__ double red[3][kRedThreads];
     const long long n = (long long)g.nx * g.ny;
     double dr = 0.0, jx = 0.0, jy = 0.0;
     // grid-stride over sites, fixed order per thread (the block count depends
@@ -331,37 +362,23 @@ __global__ __launch_bounds__(kRedThreads) void moments_kernel(const T* __restric
         if (ux) ux[q] = sx / r;
         if (uy) uy[q] = sy2 / r;
     }
-    red[0][threadIdx.x] = dr;
-    red[1][threadIdx.x] = jx;
-    red[2][threadIdx.x] = jy;
-    __syncthreads();
-    for (int w = kRedThreads / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w)
-            for (int c = 0; c < 3; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x < 3) partials[(long long)blockIdx.x * 3 + threadIdx.x] = red[threadIdx.x][0];
+    block_sum3(dr, jx, jy, partials + (long long)blockIdx.x * 3);
 }
 
 // Fixed-order reduction of nparts partial triples; out = {N + sum drho, sum jx, sum jy}.
 __global__ __launch_bounds__(kRedThreads) void reduce_partials_kernel(const double* __restrict__ partials, int nparts,
                                                                       double nsites, double* __restrict__ out)
 {
-    __shared__ double red[3][kRedThreads];
+    __shared__ double sums[3];
     double acc[3] = {0.0, 0.0, 0.0};
     for (int p = threadIdx.x; p < nparts; p += kRedThreads)
         for (int c = 0; c < 3; ++c) acc[c] += partials[(long long)p * 3 + c];
-    for (int c = 0; c < 3; ++c) red[c][threadIdx.x] = acc[c];
+    block_sum3(acc[0], acc[1], acc[2], sums);
     __syncthreads();
-    for (int w = kRedThreads / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w)
-            for (int c = 0; c < 3; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + w];
-        __syncthreads();
-    }
     if (threadIdx.x == 0) {
-        out[0] = nsites + red[0][0];
-        out[1] = red[1][0];
-        out[2] = red[2][0];
+        out[0] = nsites + sums[0];
+        out[1] = sums[1];
+        out[2] = sums[2];
     }
 }
 

@@ -385,7 +385,7 @@ int lbm_pool_init(lbm_pool* P, int slot, const double* rho, const double* ux, co
     if (!S) return LBM_EINVAL;
     const size_t n = (size_t)S->nx * S->ny;
     DevScratch d;
-    hipError_t e = d.alloc(3 * n);
+    hipError_t e = d.alloc(3 * n, P->stream);
     const double* src[3] = {rho, ux, uy};
     const double* dp[3] = {nullptr, nullptr, nullptr};
     for (int c = 0; c < 3 && e == hipSuccess; ++c) {
@@ -514,7 +514,7 @@ int lbm_pool_moments(lbm_pool* P, int slot, double* rho, double* ux, double* uy,
     if (!S->ready) return LBM_ESTATE;
     const size_t n = (size_t)S->nx * S->ny;
     DevScratch d;
-    hipError_t e = (rho || ux || uy) ? d.alloc(3 * n) : hipSuccess;
+    hipError_t e = (rho || ux || uy) ? d.alloc(3 * n, P->stream) : hipSuccess;
     double* dp[3] = {rho ? d.p : nullptr, ux ? d.p + n : nullptr, uy ? d.p + 2 * n : nullptr};
     double* tot_dev = S->red + (size_t)3 * moments_blocks(S->g);
     double tot[3] = {0, 0, 0};
@@ -549,7 +549,7 @@ int lbm_pool_get_f(lbm_pool* P, int slot, double* f)
     if (!S->ready) return LBM_ESTATE;
     const size_t n = (size_t)9 * S->nx * S->ny;
     DevScratch d;
-    hipError_t e = d.alloc(n);
+    hipError_t e = d.alloc(n, P->stream);
     if (e == hipSuccess) e = launch_get_f(P->dtype, cur_buf(*S), S->g, d.p, 0.0, P->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(f, d.p, n * sizeof(double), hipMemcpyDeviceToHost, P->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(P->stream);

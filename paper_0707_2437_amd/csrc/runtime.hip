@@ -317,7 +317,7 @@ int lbm_set_model(lbm_lattice* L, int model)
         // The shifted storage is centred on the model's state at rest: keep
         // f by reading it with the old centre and storing it with the new.
         DevScratch d;
-        hipError_t e = d.alloc((size_t)9 * L->nx * L->ny);
+        hipError_t e = d.alloc((size_t)9 * L->nx * L->ny, L->stream);
         if (e == hipSuccess) e = launch_get_f(L->dtype, L->cur, L->g, d.p, old_shift, L->stream);
         if (e == hipSuccess) e = launch_set_f(L->dtype, L->cur, L->g, d.p, new_shift, L->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
@@ -354,7 +354,7 @@ int lbm_set_c2_field(lbm_lattice* L, const double* c2)
     int st = ensure_field(L);
     if (st != LBM_OK) return st;
     DevScratch d;
-    hipError_t e = d.alloc(n);
+    hipError_t e = d.alloc(n, L->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(d.p, c2, n * sizeof(double), hipMemcpyHostToDevice, L->stream);
     if (e == hipSuccess) e = launch_field(L->dtype, L->field, L->nx, L->ny, L->fpitch, d.p, L->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
@@ -380,7 +380,7 @@ int lbm_init(lbm_lattice* L, const double* rho, const double* ux, const double* 
     if (!L) return LBM_EINVAL;
     const size_t n = (size_t)L->nx * L->ny;
     DevScratch d;
-    hipError_t e = d.alloc(3 * n);
+    hipError_t e = d.alloc(3 * n, L->stream);
     const double* src[3] = {rho, ux, uy};
     const double* dp[3] = {nullptr, nullptr, nullptr};
     for (int c = 0; c < 3 && e == hipSuccess; ++c) {
@@ -436,7 +436,7 @@ int lbm_moments(lbm_lattice* L, double* rho, double* ux, double* uy, double tota
     if (!L->ready) return LBM_ESTATE;
     const size_t n = (size_t)L->nx * L->ny;
     DevScratch d;
-    hipError_t e = (rho || ux || uy) ? d.alloc(3 * n) : hipSuccess;
+    hipError_t e = (rho || ux || uy) ? d.alloc(3 * n, L->stream) : hipSuccess;
     if (e != hipSuccess) return status_of(e);
     double* dp[3] = {rho ? d.p : nullptr, ux ? d.p + n : nullptr, uy ? d.p + 2 * n : nullptr};
     int st = lbm_moments_device(L, dp[0], dp[1], dp[2], totals);
@@ -454,7 +454,7 @@ int lbm_get_f(lbm_lattice* L, double* f)
     if (!L->ready) return LBM_ESTATE;
     const size_t n = (size_t)9 * L->nx * L->ny;
     DevScratch d;
-    hipError_t e = d.alloc(n);
+    hipError_t e = d.alloc(n, L->stream);
     if (e == hipSuccess) e = launch_get_f(L->dtype, L->cur, L->g, d.p, eq_shift(L->c2, L->model), L->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(f, d.p, n * sizeof(double), hipMemcpyDeviceToHost, L->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
@@ -475,7 +475,7 @@ int lbm_sample_f(lbm_lattice* L, int n, const int* xs, const int* ys, double* f)
         hxy[2 * k + 1] = ys[k];
     }
     DevScratch d;  // 9 n doubles of output, then 2 n ints of sites
-    hipError_t e = d.alloc((size_t)9 * n + (size_t)n);
+    hipError_t e = d.alloc((size_t)9 * n + (size_t)n, L->stream);
     int* dxy = (int*)(d.p + (size_t)9 * n);
     if (e == hipSuccess)
         e = hipMemcpyAsync(dxy, hxy, sizeof(int) * 2 * (size_t)n, hipMemcpyHostToDevice, L->stream);
@@ -491,7 +491,7 @@ int lbm_set_f(lbm_lattice* L, const double* f)
     if (!L || !f) return LBM_EINVAL;
     const size_t n = (size_t)9 * L->nx * L->ny;
     DevScratch d;
-    hipError_t e = d.alloc(n);
+    hipError_t e = d.alloc(n, L->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(d.p, f, n * sizeof(double), hipMemcpyHostToDevice, L->stream);
     if (e == hipSuccess) e = launch_set_f(L->dtype, L->cur, L->g, d.p, eq_shift(L->c2, L->model), L->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(L->stream);

@@ -47,11 +47,48 @@ def test_pool_autotune_keeps_state(tmp_path, monkeypatch):
         assert tile[1] in (4, 8, 16)
 
 
-def test_tune_cache_file_is_written():
-    """LBM_TUNE_CACHE is read by the library at its first tuning, so this test
-    only checks the in-process cache path: a cached lookup is consistent."""
-    with lbm.Lattice(96, 96, 0.7, 0.4, "f32") as L:
-        L.init()
-        t1 = L.autotune(reps=2, use_cache=True)
-        t2 = L.autotune(reps=2, use_cache=True)
-        assert t1 == t2
+_TUNE_CHILD = """
+import json, sys
+import numpy as np
+import paper_0707_2437_amd as lbm
+from paper_0707_2437_amd import workloads
+with lbm.Lattice(96, 96, 0.7, 0.4, "f32") as L:
+    L.init(*workloads.plane_wave_fields(96, 96, 0.4, seed=1))
+    tile = L.autotune(reps=2, use_cache=True)
+    np.save(sys.argv[1], L.step(5).get_f())
+print(json.dumps(list(tile)))
+"""
+
+
+def _tune_child(cache, out):
+    import subprocess
+    import sys
+    env = dict(os.environ, LBM_TUNE_CACHE=str(cache))
+    r = subprocess.run([sys.executable, "-c", _TUNE_CHILD, str(out)], env=env, capture_output=True, text=True,
+                       timeout=300, cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    assert r.returncode == 0, r.stderr
+    return tuple(json.loads(r.stdout.strip().splitlines()[-1]))
+
+
+def test_tune_cache_file_round_trip(tmp_path):
+    """LBM_TUNE_CACHE names a file of tuned shapes, one JSON object per line,
+    read at a process's first tuning, later lines overriding earlier ones.
+    A fresh process tunes a 96² FP32 lattice and appends its pick; a second
+    fresh process, given the file with a later line naming another shape for
+    the same key, applies that shape without timing anything (no line is
+    added), and its state after 5 steps is bitwise the first process's."""
+    cache = tmp_path / "tune.jsonl"
+    t1 = _tune_child(cache, tmp_path / "f1.npy")
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 1
+    rec = json.loads(lines[0])
+    assert rec["key"].split("|")[1:] == ["lattice", "1", "96x96"] and rec["key"].startswith("gfx")
+    assert (rec["vx"], rec["nw"], rec["h"], rec["flags"]) == t1 and rec["us"] > 0
+    other = (4, 16, 8, 16) if t1[:2] != (4, 16) else (1, 4, 8, 16)  # vertical stack, plain stores
+    with open(cache, "a") as fh:
+        fh.write(json.dumps({"key": rec["key"], "vx": other[0], "nw": other[1], "h": other[2], "flags": other[3],
+                             "ch": 0, "us": 1.0}) + "\n")
+    t2 = _tune_child(cache, tmp_path / "f2.npy")
+    assert t2 == other
+    assert len(cache.read_text().splitlines()) == 2
+    assert np.array_equal(np.load(tmp_path / "f1.npy"), np.load(tmp_path / "f2.npy"))
