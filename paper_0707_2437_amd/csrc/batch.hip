@@ -55,15 +55,105 @@ __global__ __launch_bounds__(64 * NW) void batch_step_kernel(const BatchLat* __r
     batch_item<T, SHIFT, VX, NW, NTS>(lats, item_lat, i, s, lds);
 }
 
-// Grid barrier for the persistent kernel: a counter and a generation word in
-// device memory (bar[0], bar[1]; zeroed before every launch; bar[2] is an
-// error flag). The last workgroup to arrive resets the counter and bumps
-// the generation; the others poll the generation with relaxed atomic loads
-// and acquire once it has moved. The wait is bounded in time: a workgroup
-// that has polled for `wait_ticks` of the constant-rate device clock raises
-// the error flag and returns false, and the kernel then ends in every
-// workgroup (no workgroup can wait forever). Only thread 0 of a workgroup
-// touches the barrier words, with vector-memory atomics.
+// Barrier state of the persistent kernel, in device memory (kBarWords
+// 32-bit words, all but the error flag zeroed before every launch):
+//   bar[0] arrivals at the current grid barrier, bar[1] its generation,
+//   bar[2] error flag (a bounded wait timed out; kept until the host reads it),
+//   bar[3] the number of member workgroups, fixed when membership closes,
+//   bar[4..5] the membership word (64-bit): bit 63 closed, bits 32..62
+//   workgroups joined, bits 0..31 joined workgroups that have arrived at the
+//   closing barrier.
+constexpr int kBarWords = kPoolBarWords;
+constexpr unsigned long long kClosed = 1ull << 63;
+
+__device__ __forceinline__ unsigned long long* member_word(unsigned* bar)
+{
+    return reinterpret_cast<unsigned long long*>(bar + 4);
+}
+
+// Wait (thread 0) until the generation word moves past gen, for at most
+// wait_ticks of the constant-rate device clock; on timeout raise the error
+// flag and return false.
+__device__ __forceinline__ bool wait_generation(unsigned* bar, unsigned gen, unsigned long long wait_ticks)
+{
+    const unsigned long long t0 = wall_clock64();
+    while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+        if (wall_clock64() - t0 > wait_ticks) {
+            atomicExch(&bar[2], 1u);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+    return true;
+}
+
+// Membership: the workgroups that take part in the launch's grid barriers
+// are those that have started when the first of them closes membership, so
+// the kernel does not depend on every workgroup of the grid being resident
+// at once (the occupancy the runtime reports for a launch can exceed what
+// the hardware holds, e.g. when scalar registers are the limit). Each
+// workgroup joins with one compare-and-swap on the membership word unless it
+// is closed; joined workgroups then meet at a first barrier, and the arrival
+// that completes it (all joined have arrived) closes membership in the same
+// compare-and-swap, so no workgroup can join after the count is fixed. A
+// workgroup that starts after closing (it was not resident) takes no part
+// and ends. Returns the member count (0: not a member, or a bounded wait
+// timed out) and the workgroup's rank in joining order.
+__device__ __forceinline__ int join_members(unsigned* bar, unsigned long long wait_ticks, int* rank)
+{
+    __shared__ int sh_count, sh_rank;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long* m = member_word(bar);
+        sh_count = 0;
+        unsigned long long old = __hip_atomic_load(m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        bool joined = false;
+        while (!(old & kClosed)) {
+            if (__hip_atomic_compare_exchange_weak(m, &old, old + (1ull << 32), __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT)) {
+                joined = true;
+                sh_rank = (int)((old >> 32) & 0x7fffffffu);
+                break;
+            }
+        }
+        if (joined) {
+            const unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+            old = __hip_atomic_load(m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            unsigned long long nw;
+            bool last;
+            do {
+                const unsigned arrived = (unsigned)(old & 0xffffffffu) + 1u;
+                const unsigned members = (unsigned)((old >> 32) & 0x7fffffffu);
+                last = arrived == members;
+                nw = (old + 1u) | (last ? kClosed : 0ull);
+            } while (!__hip_atomic_compare_exchange_weak(m, &old, nw, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT));
+            bool ok = true;
+            if (last) {
+                __hip_atomic_store(&bar[3], (unsigned)((nw >> 32) & 0x7fffffffu), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                ok = wait_generation(bar, gen, wait_ticks);
+            }
+            if (ok) {
+                __threadfence();
+                sh_count = (int)__hip_atomic_load(&bar[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+    }
+    __syncthreads();
+    *rank = sh_rank;
+    return sh_count;
+}
+
+// Grid barrier among the nblocks members: the last to arrive resets the
+// counter (bar[0]) and bumps the generation (bar[1]); the others poll the
+// generation with relaxed atomic loads and acquire once it has moved. The
+// wait is bounded (wait_generation): on a timeout the workgroup returns
+// false, and the kernel then ends in every workgroup (no workgroup can wait
+// forever). Only thread 0 of a workgroup touches the barrier words, with
+// vector-memory atomics.
 __device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned nblocks, unsigned long long wait_ticks)
 {
     __shared__ int ok;
@@ -77,16 +167,8 @@ __device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned nblocks, un
             atomicExch(&bar[0], 0u);
             __threadfence();
             __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            const unsigned long long t0 = wall_clock64();
-            while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-                if (wall_clock64() - t0 > wait_ticks) {
-                    atomicExch(&bar[2], 1u);
-                    ok = 0;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(2);
-            }
+        } else if (!wait_generation(bar, gen, wait_ticks)) {
+            ok = 0;
         }
         __threadfence();  // the other workgroups' stores of this step, before the next step's loads
         if (__hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) ok = 0;
@@ -144,20 +226,20 @@ __device__ __forceinline__ Unit find_unit(const BatchLat* __restrict__ lats, con
     return Unit{nullptr, i, 0, 0};
 }
 
-// nsteps_max steps of the whole batch in one cooperative launch of G
-// co-resident workgroups. In each step workgroup b takes the items
-// k G + p(b), k = 0, 1, ..., where p deals the G positions of a band of G
-// consecutive items to the XCDs in chunks of ch (xcd_tile; ch < 0: p(b) = b),
-// so the tiles in flight at any time form compact bands as in the grouped
-// launches. A workgroup walks its tiles as a pipeline: after the barrier
-// that publishes tile k's densities, it issues tile k + 1's window loads
-// and only then relaxes and stores tile k, so its loads are in flight while
-// it computes and stores, and waiting for them does not wait for the
-// stores. The LDS is double-buffered (tile k + 1 lands in the other half
-// while tile k is still being read). All workgroups meet at the grid barrier
+// nsteps_max steps of the whole batch in one launch whose G member
+// workgroups (join_members; all of the grid when it is resident at once,
+// as the cooperative launch intends) meet at a grid barrier between steps.
+// In each step member b takes the items k G + p(b), k = 0, 1, ..., where,
+// when every workgroup of the grid is a member, p deals the G positions of a
+// band of G consecutive items to the XCDs in chunks of ch (xcd_tile; ch < 0:
+// p(b) = b), so the tiles in flight at any time form compact bands as in the
+// grouped launches; otherwise p(b) is the member's joining rank. A
+// workgroup walks its tiles as a pipeline: after the barrier that publishes
+// tile k's densities, it issues tile k + 1's window loads and only then
+// relaxes and stores tile k, so its loads are in flight while it computes
+// and stores, and waiting for them does not wait for the stores. The LDS is double-buffered (tile k + 1 lands in the other half
+// while tile k is still being read). All members meet at the grid barrier
 // between steps, since step s + 1 reads what step s wrote.
-// Launched only with a grid that is co-resident (hipLaunchCooperativeKernel
-// checks it).
 template <class T, bool SHIFT, int VX, int NW, bool NTS>
 __global__ __launch_bounds__(64 * NW) void batch_persistent_kernel(const BatchLat* __restrict__ lats,
                                                                    const int* __restrict__ item_lat, int nitems,
@@ -167,9 +249,11 @@ __global__ __launch_bounds__(64 * NW) void batch_persistent_kernel(const BatchLa
     using C = typename CompT<T>::type;
     using V = VTile<T, SHIFT, VX, NW, NTS, false, false>;  // pools step the paper's model, centred on the weights
     __shared__ C lds[2][NW][64 * VX];
-    const int G = gridDim.x;
-    const int first = ch < 0 ? (int)blockIdx.x : xcd_tile(blockIdx.x, G, ch);
     if (stale_barrier_error(bar)) return;
+    int rank = 0;
+    const int G = join_members(bar, wait_ticks, &rank);
+    if (G == 0) return;
+    const int first = G != (int)gridDim.x ? rank : (ch < 0 ? (int)blockIdx.x : xcd_tile(blockIdx.x, G, ch));
     V v;
     v.af = {};
     for (int s = 0; s < nsteps_max; ++s) {
@@ -214,14 +298,12 @@ __global__ __launch_bounds__(64 * NW) void batch_persistent_kernel(const BatchLa
     }
 }
 
-// Zero the grid-barrier counter and generation before a persistent launch
-// (the error flag is kept until the host has read it).
+// Zero the barrier state before a persistent launch, all but the error
+// flag (bar[2]), which is kept until the host has read it.
 __global__ void barrier_reset_kernel(unsigned* bar)
 {
-    if (threadIdx.x == 0) {
-        bar[0] = 0;
-        bar[1] = 0;
-    }
+    const int w = threadIdx.x;
+    if (w < kBarWords && w != 2) bar[w] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -247,12 +329,8 @@ static hipError_t launch_batch_t(bool persistent, const BatchLat* lats, const in
     if (e == hipSuccess) e = hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, dev);
     if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, 0);
     if (e != hipSuccess) return e;
-    // A kernel that needs scratch memory can have its waves held back by the
-    // scratch the runtime provides, so that not every workgroup is resident
-    // and the grid barrier cannot complete: refuse rather than launch.
-    hipFuncAttributes fa{};
-    if ((e = hipFuncGetAttributes(&fa, kern)) != hipSuccess) return e;
-    if (fa.localSizeBytes > 0) return hipErrorInvalidConfiguration;
+    // The grid the runtime reports as resident at once; the workgroups that
+    // are not (if the report is high) take no part (join_members).
     int grid = per_cu * ncu;
     if (max_grid > 0 && grid > max_grid) grid = max_grid;
     // a grid that is a multiple of 8 ch (or of 8) makes xcd_tile a permutation

@@ -27,6 +27,8 @@ hipError_t launch_sample_f(int dtype, const void* s, const Geom& g, int n, const
                            hipStream_t st);
 hipError_t launch_moments(int dtype, const void* s, const Geom& g, double* rho, double* ux, double* uy,
                           double* partials, double* totals, hipStream_t st);
+// bar: the persistent kernel's barrier state, kPoolBarWords zeroed words
+// (device memory of the caller; unused by grouped launches).
 hipError_t launch_batch(int dtype, int vx, int nw, bool nts, bool persistent, const BatchLat* lats,
                         const int* item_lat, int nitems, int s_or_n, int max_grid, int ch, unsigned* bar,
                         hipStream_t st);

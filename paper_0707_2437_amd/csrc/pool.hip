@@ -102,7 +102,7 @@ struct lbm_pool {
     int max_grid = 0;             // persistent mode: workgroup cap (0 = all co-resident)
     BatchLat* d_lats = nullptr;   // device descriptor array
     int* d_items = nullptr;       // device item -> lattice map
-    unsigned* d_bar = nullptr;    // grid-barrier state of the persistent kernel (3 words)
+    unsigned* d_bar = nullptr;    // barrier state of the persistent kernel (kPoolBarWords words)
     int cap = 0, item_cap = 0;
     int per_item = 1;             // tiles per work item
     int xcd_chunk = 8;            // items per XCD chunk of the grouped launches (see xcd_tile)
@@ -290,8 +290,8 @@ lbm_pool* lbm_pool_create(size_t budget_bytes, int dtype)
     char* noalloc_base = nullptr;  // look up lbm_pool_step_noalloc's array while set up
     if (e == hipSuccess) e = noalloc_scratch(P->device, &noalloc_base);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&P->own, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipMalloc((void**)&P->d_bar, 4 * sizeof(unsigned));
-    if (e == hipSuccess) e = hipMemsetAsync(P->d_bar, 0, 4 * sizeof(unsigned), P->own);
+    if (e == hipSuccess) e = hipMalloc((void**)&P->d_bar, kPoolBarWords * sizeof(unsigned));
+    if (e == hipSuccess) e = hipMemsetAsync(P->d_bar, 0, kPoolBarWords * sizeof(unsigned), P->own);
     if (e == hipSuccess) e = hipStreamSynchronize(P->own);
     if (e != hipSuccess) {
         g_pool_error = LBM_EDEVICE;

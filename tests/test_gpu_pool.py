@@ -60,6 +60,29 @@ def test_persistent_with_few_workgroups_bitwise():
         assert np.array_equal(g, run_alone(nx, ny, tau, c2, n, "f32", f))
 
 
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("vx,nw", [(1, 4), (1, 8), (2, 4), (2, 16), (4, 16)])
+def test_persistent_every_shape_bitwise(dtype, vx, nw):
+    """A persistent launch in every tile shape. The runtime's report of how
+    many workgroups a CU holds at once can be too high (the FP32 (1, 4)
+    kernel's scalar registers allow 7 waves per SIMD, and a launch sized by
+    the report timed out at its first grid barrier); the workgroups that are
+    not resident when the launch starts take no part, and every lattice is
+    still bitwise the plain kernel's."""
+    fields = [smooth_random_state(nx, ny, seed=5 * k + 2) for k, (nx, ny, *_) in enumerate(CASES)]
+    with lbm.Pool(1 << 30, dtype) as P:
+        P.set_tile(vx, nw, 2)
+        P.set_mode(lbm.PERSISTENT)
+        slots = [P.add(nx, ny, tau, c2) for (nx, ny, tau, c2, _) in CASES]
+        for s, f in zip(slots, fields):
+            P.init(s, *f)
+        P.step(slots, [c[4] for c in CASES])
+        P.sync()
+        got = [P.get_f(s) for s in slots]
+    for (nx, ny, tau, c2, n), f, g in zip(CASES, fields, got):
+        assert np.array_equal(g, run_alone(nx, ny, tau, c2, n, dtype, f)), (nx, ny)
+
+
 @pytest.mark.parametrize("tile,per_item", [((1, 4, 0), 1), ((2, 16, 2), 3), ((4, 8, 0), 8), ((2, 8, 2), 64)])
 def test_pool_tile_does_not_change_results(tile, per_item):
     fields = [smooth_random_state(nx, ny, seed=k) for k, (nx, ny, *_) in enumerate(CASES)]
