@@ -244,8 +244,10 @@ def measure_batched(lbm, workloads, torch, nlat, steps, mode, warmup=5, persiste
     sec = e0.elapsed_time(e1) / 1e3
     nonfinite = sum(1 for s in slots if P.totals(s)[1] != 0)
     pers = None
+    pers_tile = None
     if persistent_steps > 0 and mode != "persistent":
         P.set_mode(lbm.PERSISTENT)
+        pers_tile = P.autotune(slots, reps=5)  # the persistent kernel's own best shape
         P.step(slots, 2)
         torch.cuda.synchronize()
         e0.record(stream)
@@ -280,7 +282,7 @@ def measure_batched(lbm, workloads, torch, nlat, steps, mode, warmup=5, persiste
     return {"mlups": mlups, "frac": mlups * 1e6 * BYTES_PER_SITE["f32"] / 1e9 / PEAK_HBM_GBS,
             "lattices": nlat, "sites": sites, "steps": steps, "mode": mode, "tile": list(tile),
             "seconds": sec, "plain_mlups": plain, "vs_plain": mlups / plain, "nonfinite_lattices": nonfinite,
-            "persistent_mlups": pers,
+            "persistent_mlups": pers, "persistent_tile": None if pers_tile is None else list(pers_tile),
             "graph_capture_s": None if capture is None else max(0.0, capture - sec)}
 
 

@@ -333,9 +333,11 @@ int lbm_pool_get_tile(const lbm_pool* P, int* vx, int* nw, int* flags);
 int lbm_pool_set_items(lbm_pool* P, int tiles_per_item);
 /* Autotuner for the batched kernels (see lbm_autotune): shape, stores,
  * tiles per item and the order in which items are dealt to the GPU's
- * chiplets, timed on one batched launch over the listed slots; cached
- * per architecture, dtype, and the batch's lattice count and total sites
- * rounded up to powers of two. */
+ * chiplets, timed on one batched launch over the listed slots (in
+ * LBM_POOL_PERSISTENT mode, on one-step persistent launches, whose best
+ * shape differs); cached per architecture, mode, dtype, and the batch's
+ * lattice count and total sites rounded up to powers of two. Call it after
+ * lbm_pool_set_mode. */
 int lbm_pool_autotune(lbm_pool* P, const int* slots, int count, int reps, int use_cache);
 /* Use an existing (non-null) HIP stream for the pool's work; NULL selects
  * the pool's own non-blocking stream (the default). Synchronises the

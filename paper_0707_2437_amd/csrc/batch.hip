@@ -9,6 +9,7 @@
 
 #include <cstdlib>
 
+#include "host.h"
 #include "internal.h"
 #include "step.h"
 
@@ -64,6 +65,7 @@ __global__ __launch_bounds__(64 * NW) void batch_step_kernel(const BatchLat* __r
 //   workgroups joined, bits 0..31 joined workgroups that have arrived at the
 //   closing barrier.
 constexpr int kBarWords = kPoolBarWords;
+constexpr int kBarCtr = 8;  // bar[8..23]: the per-XCD item counters of two consecutive steps
 constexpr unsigned long long kClosed = 1ull << 63;
 
 __device__ __forceinline__ unsigned long long* member_word(unsigned* bar)
@@ -154,7 +156,8 @@ __device__ __forceinline__ int join_members(unsigned* bar, unsigned long long wa
 // false, and the kernel then ends in every workgroup (no workgroup can wait
 // forever). Only thread 0 of a workgroup touches the barrier words, with
 // vector-memory atomics.
-__device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned nblocks, unsigned long long wait_ticks)
+__device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned nblocks, unsigned long long wait_ticks,
+                                             unsigned* zero_words = nullptr, int nzero = 0)
 {
     __shared__ int ok;
     __syncthreads();
@@ -165,6 +168,7 @@ __device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned nblocks, un
         const unsigned arrived = atomicAdd(&bar[0], 1u);
         if (arrived == nblocks - 1) {
             atomicExch(&bar[0], 0u);
+            for (int k = 0; k < nzero; ++k) atomicExch(&zero_words[k], 0u);  // before the release
             __threadfence();
             __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else if (!wait_generation(bar, gen, wait_ticks)) {
@@ -226,22 +230,34 @@ __device__ __forceinline__ Unit find_unit(const BatchLat* __restrict__ lats, con
     return Unit{nullptr, i, 0, 0};
 }
 
+// The k-th item of part `part` of a step's items, dealt to nparts parts in
+// chunks of ch consecutive items (chunk c to part c mod nparts). With one
+// part per XCD, as in the grouped launches, horizontally adjacent tiles,
+// which share the cache lines at their common edge, are stepped by the same
+// XCD.
+__device__ __forceinline__ int part_item(int k, int part, int nparts, int ch)
+{
+    return ((k / ch) * nparts + part) * ch + k % ch;
+}
+
 // nsteps_max steps of the whole batch in one launch whose G member
 // workgroups (join_members; all of the grid when it is resident at once,
 // as the cooperative launch intends) meet at a grid barrier between steps.
-// In each step member b takes the items k G + p(b), k = 0, 1, ..., where,
-// when every workgroup of the grid is a member, p deals the G positions of a
-// band of G consecutive items to the XCDs in chunks of ch (xcd_tile; ch < 0:
-// p(b) = b), so the tiles in flight at any time form compact bands as in the
-// grouped launches; otherwise p(b) is the member's joining rank. A
-// workgroup walks its tiles as a pipeline: after the barrier that publishes
-// tile k's densities, it issues tile k + 1's window loads and only then
-// relaxes and stores tile k, so its loads are in flight while it computes
-// and stores, and waiting for them does not wait for the stores. The LDS is double-buffered (tile k + 1 lands in the other half
-// while tile k is still being read). All members meet at the grid barrier
-// between steps, since step s + 1 reads what step s wrote.
+// Work is taken dynamically: the items are split into parts, one per XCD
+// when the whole grid joined and is a multiple of 8 workgroups (workgroup b
+// runs on XCD b mod 8), else a single part; each part has a counter per
+// step (two steps' sets alternate; the barrier's last arriver zeroes the
+// set of the next step), and a member takes its part's next item
+// (part_item) with one atomic add, issued with the window loads of its
+// current item's last tile, so the wait for those loads also covers it.
+// Members that finish early take more items, so a step ends when the work
+// does, whatever the speed of each workgroup. Each tile is processed as in
+// the grouped kernel (issue, land, barrier, relax); the LDS holding the
+// densities is double-buffered, so consecutive tiles need one workgroup
+// barrier each. All members meet at the grid barrier between steps, since
+// step s + 1 reads what step s wrote.
 template <class T, bool SHIFT, int VX, int NW, bool NTS>
-__global__ __launch_bounds__(64 * NW) void batch_persistent_kernel(const BatchLat* __restrict__ lats,
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(sizeof(T) <= 4 && VX <= 2 ? 8 : 1, 8))) void batch_persistent_kernel(const BatchLat* __restrict__ lats,
                                                                    const int* __restrict__ item_lat, int nitems,
                                                                    int nsteps_max, int ch, unsigned* bar,
                                                                    unsigned long long wait_ticks)
@@ -249,52 +265,68 @@ __global__ __launch_bounds__(64 * NW) void batch_persistent_kernel(const BatchLa
     using C = typename CompT<T>::type;
     using V = VTile<T, SHIFT, VX, NW, NTS, false, false>;  // pools step the paper's model, centred on the weights
     __shared__ C lds[2][NW][64 * VX];
+    __shared__ int next_item[2];
     if (stale_barrier_error(bar)) return;
     int rank = 0;
     const int G = join_members(bar, wait_ticks, &rank);
     if (G == 0) return;
-    const int first = G != (int)gridDim.x ? rank : (ch < 0 ? (int)blockIdx.x : xcd_tile(blockIdx.x, G, ch));
-    V v;
-    v.af = {};
+    const bool by_xcd = G == (int)gridDim.x && G % 8 == 0;
+    const int nparts = by_xcd ? 8 : 1;
+    const int part = by_xcd ? (int)(blockIdx.x & 7u) : 0;
+    const int chunk = ch > 0 ? ch : 1;
+    int buf = 0;
     for (int s = 0; s < nsteps_max; ++s) {
-        // tile u's lattice, with its buffers of this step (src: time t0 + s)
-        auto tile_of = [&](const Unit& u) {
-            StepTile a = ldc(&u.L->tile);
-            if ((ldc(&u.L->t0) + s) & 1) {
+        unsigned* ctr = bar + kBarCtr + (s & 1) * 8 + part;
+        // the item of counter value k (nitems: none left)
+        auto take = [&](unsigned k) { return min(part_item((int)k, part, nparts, chunk), nitems); };
+        if (threadIdx.x == 0) next_item[buf] = take(atomicAdd(ctr, 1u));
+        __syncthreads();
+        int i = next_item[buf];
+        buf ^= 1;  // the slot just read is not written again before the next barrier
+        while (i < nitems) {
+            const BatchLat* L = &lats[ldc(&item_lat[i])];
+            if (s >= ldc(&L->nsteps)) {  // this lattice takes fewer steps: the next item
+                if (threadIdx.x == 0) next_item[buf] = take(atomicAdd(ctr, 1u));
+                __syncthreads();
+                i = next_item[buf];
+                buf ^= 1;
+                continue;
+            }
+            StepTile a = ldc(&L->tile);
+            if ((ldc(&L->t0) + s) & 1) {
                 const void* b = a.src;
                 a.src = a.dst;
                 a.dst = const_cast<void*>(b);
             }
-            return a;
-        };
-        auto issue = [&](const StepTile& a, const Unit& u, const VRow& r) {
-            v.issue_rt(a, a.src, r, edge_strip<T, VX>(a.g, u.t % a.nstrips));
-        };
-        Unit u = find_unit(lats, item_lat, nitems, first, G, s);
-        VRow r{};
-        if (u.L) {
-            const StepTile a = tile_of(u);
-            r = vrow<VX, NW>(a.g, u.t % a.nstrips, u.t / a.nstrips);
-            issue(a, u, r);
-        }
-        int buf = 0;
-        while (u.L) {
-            const Unit n = u.t + 1 < u.t1 ? Unit{u.L, u.i, u.t + 1, u.t1} : find_unit(lats, item_lat, nitems, u.i + G, G, s);
-            const StepTile a = tile_of(u);
-            v.land(a, r, lds[buf]);
-            __syncthreads();  // tile u's densities are in lds[buf]
-            VRow rn{};
-            if (n.L) {
-                const StepTile an = tile_of(n);
-                rn = vrow<VX, NW>(an.g, n.t % an.nstrips, n.t / an.nstrips);
-                issue(an, n, rn);
+            const int per = ldc(&L->per_item);
+            const int t0 = (i - ldc(&L->item_begin)) * per;
+            const int t1 = min(t0 + per, ldc(&L->ntiles));
+            for (int t = t0; t < t1; ++t) {
+                const bool last = t + 1 == t1;
+                const int strip = t % a.nstrips;
+                const VRow r = vrow<VX, NW>(a.g, strip, t / a.nstrips);
+                unsigned k = 0;
+                if (last && threadIdx.x == 0) k = atomicAdd(ctr, 1u);
+                // as vstack_tile, with the next item published before the barrier
+                auto run = [&](auto edge) {
+                    V v;
+                    v.af = {};
+                    if (r.load) {
+                        v.template issue_rows<decltype(edge)::value>(a, a.src, r);
+                        v.land_rows(a, r, lds[buf]);
+                    }
+                    if (last && threadIdx.x == 0) next_item[buf] = take(k);
+                    __syncthreads();  // the tile's densities are in lds[buf]
+                    v.relax(a, a.dst, r, lds[buf]);
+                };
+                if constexpr (GhostCols<T>::value) run(std::false_type{});
+                else if (edge_strip<T, VX>(a.g, strip)) run(std::true_type{});
+                else run(std::false_type{});
+                if (last) i = next_item[buf];
+                buf ^= 1;
             }
-            v.relax(a, a.dst, r, lds[buf]);
-            u = n;
-            r = rn;
-            buf ^= 1;
         }
-        if (!grid_barrier(bar, G, wait_ticks)) return;
+        if (!grid_barrier(bar, G, wait_ticks, bar + kBarCtr + ((s + 1) & 1) * 8, s + 1 < nsteps_max ? 8 : 0)) return;
     }
 }
 

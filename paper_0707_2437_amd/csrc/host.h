@@ -27,6 +27,9 @@ hipError_t launch_sample_f(int dtype, const void* s, const Geom& g, int n, const
                            hipStream_t st);
 hipError_t launch_moments(int dtype, const void* s, const Geom& g, double* rho, double* ux, double* uy,
                           double* partials, double* totals, hipStream_t st);
+// Words of barrier and work-counter state a persistent batched launch
+// needs (device memory the pool allocates once; see the persistent kernel).
+constexpr int kPoolBarWords = 24;
 // bar: the persistent kernel's barrier state, kPoolBarWords zeroed words
 // (device memory of the caller; unused by grouped launches).
 hipError_t launch_batch(int dtype, int vx, int nw, bool nts, bool persistent, const BatchLat* lats,

@@ -80,10 +80,6 @@ __host__ __device__ inline double source_as1(double c2)
     return 1.5 * (1.0 / 9.0) * alpha;
 }
 
-// Words of barrier state a persistent batched launch needs (device memory
-// the pool allocates once; see the persistent kernel).
-constexpr int kPoolBarWords = 8;
-
 // One lattice of a batched launch (device array, read by every workgroup).
 // tile.src holds the buffer of even times and tile.dst the buffer of odd
 // times: at step s of the call the lattice is at time t0 + s, reads buffer

@@ -595,8 +595,11 @@ int lbm_pool_autotune(lbm_pool* P, const int* slots, int count, int reps, int us
     int lc = 0, ls = 0;
     while ((1 << lc) < count) ++lc;
     while ((1LL << ls) < sites) ++ls;
+    // the persistent kernel is tuned on its own launches (its best shape differs)
+    const bool pers = P->mode == LBM_POOL_PERSISTENT;
     char key[160];
-    std::snprintf(key, sizeof(key), "%s|pool|%d|n2^%d|s2^%d", device_arch().c_str(), P->dtype, lc, ls);
+    std::snprintf(key, sizeof(key), "%s|%s|%d|n2^%d|s2^%d", device_arch().c_str(), pers ? "pool-persistent" : "pool",
+                  P->dtype, lc, ls);
     TileCand c{};
     if (use_cache && tune_cache_get(key, &c)) {
         P->per_item = c.h;
@@ -604,8 +607,9 @@ int lbm_pool_autotune(lbm_pool* P, const int* slots, int count, int reps, int us
         return lbm_pool_set_tile(P, c.vx, c.nw, c.flags);
     }
     const std::vector<TileCand> cands = pool_candidates(P->dtype);
-    // one batched launch at step 0 of a 1-step call: reads each slot's
-    // current buffer and writes the other, without advancing any slot. The
+    // one batched launch at step 0 of a 1-step call (a persistent launch of
+    // one step in persistent mode): reads each slot's current buffer and
+    // writes the other, without advancing any slot. The
     // descriptors and the item map of a shape are built and uploaded by its
     // first (untimed) launch only, so that the timed launches measure the
     // kernel and not the host work, which grows with the number of items.
@@ -613,9 +617,12 @@ int lbm_pool_autotune(lbm_pool* P, const int* slots, int count, int reps, int us
     bool have_built = false;
     int nitems = 0;
     auto launch = [&](const TileCand& k) -> hipError_t {
-        if (have_built && built.vx == k.vx && built.nw == k.nw && built.h == k.h)
-            return launch_batch(P->dtype, k.vx, k.nw, (k.flags & LBM_TILE_NT_STORE) != 0, false, P->d_lats,
-                                P->d_items, nitems, 0, 0, k.ch, nullptr, P->stream);
+        auto go = [&]() {
+            return launch_batch(P->dtype, k.vx, k.nw, (k.flags & LBM_TILE_NT_STORE) != 0, pers, P->d_lats,
+                                P->d_items, nitems, pers ? 1 : 0, pers ? P->max_grid : 0, k.ch,
+                                pers ? P->d_bar : nullptr, P->stream);
+        };
+        if (have_built && built.vx == k.vx && built.nw == k.nw && built.h == k.h) return go();
         have_built = false;
         const int ovx = P->vx, onw = P->nw, opi = P->per_item;
         P->vx = k.vx;
@@ -641,9 +648,7 @@ int lbm_pool_autotune(lbm_pool* P, const int* slots, int count, int reps, int us
         if (le == hipSuccess)
             le = hipMemcpyAsync(P->d_items, P->h_items.data(), sizeof(int) * (size_t)nitems, hipMemcpyHostToDevice,
                                 P->stream);
-        if (le == hipSuccess)
-            le = launch_batch(P->dtype, k.vx, k.nw, (k.flags & LBM_TILE_NT_STORE) != 0, false, P->d_lats,
-                              P->d_items, nitems, 0, 0, k.ch, nullptr, P->stream);
+        if (le == hipSuccess) le = go();
         if (le == hipSuccess) {
             built = k;
             have_built = true;
