@@ -51,7 +51,7 @@ def parse():
     p.add_argument("--batch-steps", type=int, default=2000)
     p.add_argument("--batch-mode", default="graph", choices=["grouped", "graph", "persistent"])
     p.add_argument("--batch-persistent-steps", type=int, default=200,
-                   help="also time the persistent cooperative form for this many steps (0: skip)")
+                   help="also time the persistent form for this many steps (0: skip)")
     p.add_argument("--precision-steps", type=int, default=300,
                    help="steps of the precision workload (8192^2 shear wave, shifted FP32 / FP16; 0: skip)")
     p.add_argument("--serve-seconds", type=float, default=30.0,
@@ -208,7 +208,7 @@ def cpu_baseline(workloads, n, steps, steps_one_core):
 def measure_batched(lbm, workloads, torch, nlat, steps, mode, warmup=5, persistent_steps=0):
     """The batching workload: nlat seeded lattices of uneven size, tau and c^2
     (FP32) in one pool, stepped `steps` times by one call (in persistent mode
-    one cooperative launch); compared with the plain single-lattice kernel
+    one persistent launch); compared with the plain single-lattice kernel
     stepping the same lattices one launch each."""
     specs = workloads.batch_specs(nlat, seed=0)
     sites = sum(s["nx"] * s["ny"] for s in specs)

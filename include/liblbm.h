@@ -241,7 +241,8 @@ enum lbm_pool_mode {
     LBM_POOL_GROUPED = 0,   /* one launch per step                                     */
     LBM_POOL_GRAPH = 1,     /* the launches of a call captured once in a hipGraph and
                                replayed by later calls with the same shape             */
-    LBM_POOL_PERSISTENT = 2 /* one cooperative launch for all steps of a call, with a
+    LBM_POOL_PERSISTENT = 2 /* one launch for all steps of a call: the workgroups
+                               resident when it starts take items dynamically, with a
                                grid barrier between steps                              */
 };
 
@@ -320,7 +321,8 @@ int lbm_pool_get_f(lbm_pool* P, int slot, double* f);
 long long lbm_pool_time(const lbm_pool* P, int slot);
 
 /* Launch mode (lbm_pool_mode) and, for LBM_POOL_PERSISTENT, a cap on the
- * workgroups of the cooperative launch (0: as many as are co-resident). */
+ * workgroups of the persistent launch (0: as many as the runtime reports a
+ * CU can hold at once; those not resident when it starts take no part). */
 int lbm_pool_set_mode(lbm_pool* P, int mode, int max_grid);
 /* Vertical-stack tile of the batched kernels: vx in {1, 2, 4}, nw in
  * {4, 8, 16}, flags 0 or LBM_TILE_NT_STORE (default: non-temporal stores,

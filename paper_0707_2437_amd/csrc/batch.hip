@@ -1,7 +1,7 @@
 // batch.hip -- batched forms of the variable-speed-of-sound D2Q9 step
 // (Buick & Cosgrove, Sec. 3 Eq. 5): many independent lattices of uneven
 // size, tau and c^2 stepped by one launch per step (grouped), or by one
-// persistent cooperative launch for many steps with a grid barrier between
+// persistent launch for many steps with a grid barrier between
 // steps. Every tile is processed by vstack_tile (step.h), the same code as
 // the single-lattice vertical-stack kernel, so each lattice's result is
 // bitwise identical to stepping it alone.
@@ -241,8 +241,8 @@ __device__ __forceinline__ int part_item(int k, int part, int nparts, int ch)
 }
 
 // nsteps_max steps of the whole batch in one launch whose G member
-// workgroups (join_members; all of the grid when it is resident at once,
-// as the cooperative launch intends) meet at a grid barrier between steps.
+// workgroups (join_members; all of the grid when it is resident at once)
+// meet at a grid barrier between steps.
 // Work is taken dynamically: the items are split into parts, one per XCD
 // when the whole grid joined and is a multiple of 8 workgroups (workgroup b
 // runs on XCD b mod 8), else a single part; each part has a counter per
@@ -384,9 +384,12 @@ static hipError_t launch_batch_t(bool persistent, const BatchLat* lats, const in
     unsigned long long wait_ticks = (unsigned long long)(wait_us * 1e-3 * clock_khz);
     hipLaunchKernelGGL(barrier_reset_kernel, dim3(1), dim3(64), 0, st, bar);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    void* args[] = {(void*)&lats,    (void*)&item_lat, (void*)&nitems,    (void*)&s_or_n,
-                    (void*)&ch,      (void*)&bar,      (void*)&wait_ticks};
-    return hipLaunchCooperativeKernel(kern, dim3(grid), dim3(threads), args, 0, st);
+    // An ordinary launch: the membership (join_members) makes the kernel
+    // correct whether or not every workgroup is resident at once, so the
+    // cooperative-launch guarantee is not needed.
+    hipLaunchKernelGGL((batch_persistent_kernel<T, SHIFT, VX, NW, NTS>), dim3(grid), dim3(threads), 0, st, lats,
+                       item_lat, nitems, s_or_n, ch, bar, wait_ticks);
+    return hipGetLastError();
 }
 
 template <class T, bool SHIFT, int VX>
@@ -425,11 +428,12 @@ static hipError_t launch_batch_vx(int vx, int nw, bool nts, bool persistent, con
 // Grouped (persistent = false): step s_or_n of the batch, one launch, one
 // workgroup per item, items dealt to the XCDs in chunks of ch items (<= 0:
 // one contiguous run per XCD).
-// Persistent: s_or_n steps in one cooperative launch, at most max_grid
-// workgroups (<= 0: as many as are co-resident), items dealt to the XCDs in
-// chunks of ch, barrier state in `bar` (3 words; the counter and generation
-// are reset on the stream before the launch; bar[2] becomes 1 if a barrier
-// timed out, and a launch that finds it set does nothing).
+// Persistent: s_or_n steps in one launch, at most max_grid
+// workgroups (<= 0: as many as the runtime reports resident), items taken
+// dynamically in chunks of ch per XCD, barrier and counter state in `bar`
+// (kPoolBarWords words, all but bar[2] reset on the stream before the
+// launch; bar[2] becomes 1 if a barrier timed out, and a launch that finds
+// it set does nothing).
 hipError_t launch_batch(int dtype, int vx, int nw, bool nts, bool persistent, const BatchLat* lats,
                         const int* item_lat, int nitems, int s_or_n, int max_grid, int ch, unsigned* bar,
                         hipStream_t st)

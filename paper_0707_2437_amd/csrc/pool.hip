@@ -1,7 +1,7 @@
 // pool.hip -- host side of the batched and served forms: a pool of resident
 // lattices (slots) of one storage dtype under a device-memory budget, stepped
 // together by batched launches (grouped, grouped under a captured hipGraph,
-// or one persistent cooperative launch). C ABI in include/liblbm.h.
+// or one persistent launch). C ABI in include/liblbm.h.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

@@ -1,5 +1,5 @@
 """Batched form: a pool of lattices of uneven size, tau and c^2 stepped by
-batched launches (grouped, captured hipGraph, persistent cooperative) gives
+batched launches (grouped, captured hipGraph, persistent) gives
 every lattice bitwise the result of stepping it alone; the pool enforces its
 memory budget; errors are reported."""
 import numpy as np
