@@ -244,7 +244,7 @@ def measure_batched(lbm, workloads, torch, nlat, steps, mode, warmup=5, persiste
     sec = e0.elapsed_time(e1) / 1e3
     nonfinite = sum(1 for s in slots if P.totals(s)[1] != 0)
     pers = None
-    pers_tile = None
+    pers_tile = pers_members = None
     if persistent_steps > 0 and mode != "persistent":
         P.set_mode(lbm.PERSISTENT)
         pers_tile = P.autotune(slots, reps=5)  # the persistent kernel's own best shape
@@ -256,6 +256,7 @@ def measure_batched(lbm, workloads, torch, nlat, steps, mode, warmup=5, persiste
         torch.cuda.synchronize()
         P.sync()
         pers = sites * persistent_steps / (e0.elapsed_time(e1) / 1e3) / 1e6
+        pers_members = P.persistent_members()
     P.close()
     # plain kernel, one launch per lattice per step (same lattices, fewer steps)
     psteps = max(1, steps // 10)
@@ -283,6 +284,7 @@ def measure_batched(lbm, workloads, torch, nlat, steps, mode, warmup=5, persiste
             "lattices": nlat, "sites": sites, "steps": steps, "mode": mode, "tile": list(tile),
             "seconds": sec, "plain_mlups": plain, "vs_plain": mlups / plain, "nonfinite_lattices": nonfinite,
             "persistent_mlups": pers, "persistent_tile": None if pers_tile is None else list(pers_tile),
+            "persistent_members": pers_members,
             "graph_capture_s": None if capture is None else max(0.0, capture - sec)}
 
 

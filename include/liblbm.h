@@ -307,6 +307,11 @@ int lbm_pool_step_noalloc(lbm_pool* P, const int* slots, const int* nsteps, int 
 /* Wait for the pool's stream. */
 int lbm_pool_sync(lbm_pool* P);
 
+/* Diagnostics of LBM_POOL_PERSISTENT: the number of workgroups that took
+ * part in the last persistent launch (those resident when it started; 0
+ * before any). Synchronises the pool's stream. Negative: an error status. */
+int lbm_pool_persistent_members(lbm_pool* P);
+
 /* The totals {sum rho, sum rho u_x, sum rho u_y} of a slot's current state
  * (as lbm_moments: FP64, fixed order) into a DEVICE array of 3 doubles,
  * asynchronously on the pool's stream (no check of finiteness; a timed-out

@@ -59,6 +59,7 @@ SIGNATURES = {
     "lbm_pool_step": (_i, [_vp, _vp, _vp, _i]),
     "lbm_pool_step_noalloc": (_i, [_vp, _vp, _vp, _i]),
     "lbm_pool_sync": (_i, [_vp]),
+    "lbm_pool_persistent_members": (_i, [_vp]),
     "lbm_pool_moments": (_i, [_vp, _i, _vp, _vp, _vp, _vp]),
     "lbm_pool_totals_device": (_i, [_vp, _i, _vp]),
     "lbm_pool_get_f": (_i, [_vp, _i, _vp]),

@@ -90,18 +90,23 @@ __device__ __forceinline__ bool wait_generation(unsigned* bar, unsigned gen, uns
 }
 
 // Membership: the workgroups that take part in the launch's grid barriers
-// are those that have started when the first of them closes membership, so
-// the kernel does not depend on every workgroup of the grid being resident
-// at once (the occupancy the runtime reports for a launch can exceed what
-// the hardware holds, e.g. when scalar registers are the limit). Each
-// workgroup joins with one compare-and-swap on the membership word unless it
-// is closed; joined workgroups then meet at a first barrier, and the arrival
-// that completes it (all joined have arrived) closes membership in the same
+// are those that have started when membership closes, so the kernel does
+// not depend on every workgroup of the grid being resident at once (the
+// occupancy the runtime reports for a launch can exceed what the hardware
+// holds, e.g. when scalar registers are the limit). Each workgroup joins
+// with one compare-and-swap on the membership word unless it is closed, and
+// waits until the whole grid has joined or `grace_ticks` have passed since
+// its own join (the resident workgroups start within microseconds of each
+// other; without the wait, the first to arrive could close membership
+// before the others have joined, which is correct but leaves them idle).
+// Joined workgroups then meet at a first barrier, and the arrival that
+// completes it (all joined have arrived) closes membership in the same
 // compare-and-swap, so no workgroup can join after the count is fixed. A
 // workgroup that starts after closing (it was not resident) takes no part
 // and ends. Returns the member count (0: not a member, or a bounded wait
 // timed out) and the workgroup's rank in joining order.
-__device__ __forceinline__ int join_members(unsigned* bar, unsigned long long wait_ticks, int* rank)
+__device__ __forceinline__ int join_members(unsigned* bar, unsigned long long wait_ticks,
+                                            unsigned long long grace_ticks, int* rank)
 {
     __shared__ int sh_count, sh_rank;
     __syncthreads();
@@ -120,7 +125,12 @@ __device__ __forceinline__ int join_members(unsigned* bar, unsigned long long wa
         }
         if (joined) {
             const unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned long long t0 = wall_clock64();
             old = __hip_atomic_load(m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            while (((old >> 32) & 0x7fffffffu) < gridDim.x && wall_clock64() - t0 < grace_ticks) {
+                __builtin_amdgcn_s_sleep(2);
+                old = __hip_atomic_load(m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
             unsigned long long nw;
             bool last;
             do {
@@ -260,7 +270,8 @@ template <class T, bool SHIFT, int VX, int NW, bool NTS>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(sizeof(T) <= 4 && VX <= 2 ? 8 : 1, 8))) void batch_persistent_kernel(const BatchLat* __restrict__ lats,
                                                                    const int* __restrict__ item_lat, int nitems,
                                                                    int nsteps_max, int ch, unsigned* bar,
-                                                                   unsigned long long wait_ticks)
+                                                                   unsigned long long wait_ticks,
+                                                                   unsigned long long grace_ticks)
 {
     using C = typename CompT<T>::type;
     using V = VTile<T, SHIFT, VX, NW, NTS, false, false>;  // pools step the paper's model, centred on the weights
@@ -268,7 +279,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(sizeof(
     __shared__ int next_item[2];
     if (stale_barrier_error(bar)) return;
     int rank = 0;
-    const int G = join_members(bar, wait_ticks, &rank);
+    const int G = join_members(bar, wait_ticks, grace_ticks, &rank);
     if (G == 0) return;
     const bool by_xcd = G == (int)gridDim.x && G % 8 == 0;
     const int nparts = by_xcd ? 8 : 1;
@@ -381,14 +392,16 @@ static hipError_t launch_batch_t(bool persistent, const BatchLat* lats, const in
         const double v = std::atof(ev);
         if (v >= 0.0 && v <= 1e8) wait_us = v;
     }
-    unsigned long long wait_ticks = (unsigned long long)(wait_us * 1e-3 * clock_khz);
+    const unsigned long long wait_ticks = (unsigned long long)(wait_us * 1e-3 * clock_khz);
+    // how long a workgroup waits for the rest of the grid to join (20 us)
+    const unsigned long long grace_ticks = (unsigned long long)(20.0 * 1e-3 * clock_khz);
     hipLaunchKernelGGL(barrier_reset_kernel, dim3(1), dim3(64), 0, st, bar);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // An ordinary launch: the membership (join_members) makes the kernel
     // correct whether or not every workgroup is resident at once, so the
     // cooperative-launch guarantee is not needed.
     hipLaunchKernelGGL((batch_persistent_kernel<T, SHIFT, VX, NW, NTS>), dim3(grid), dim3(threads), 0, st, lats,
-                       item_lat, nitems, s_or_n, ch, bar, wait_ticks);
+                       item_lat, nitems, s_or_n, ch, bar, wait_ticks, grace_ticks);
     return hipGetLastError();
 }
 

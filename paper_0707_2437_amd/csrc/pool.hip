@@ -507,6 +507,15 @@ int lbm_pool_sync(lbm_pool* P)
     return take_barrier_error(P);
 }
 
+int lbm_pool_persistent_members(lbm_pool* P)
+{
+    if (!P) return LBM_EINVAL;
+    hipError_t e = hipStreamSynchronize(P->stream);
+    unsigned members = 0;
+    if (e == hipSuccess) e = hipMemcpy(&members, P->d_bar + 3, sizeof(members), hipMemcpyDeviceToHost);
+    return e != hipSuccess ? status_of(e) : (int)members;
+}
+
 int lbm_pool_moments(lbm_pool* P, int slot, double* rho, double* ux, double* uy, double totals[3])
 {
     Slot* S = slot_of(P, slot);

@@ -111,6 +111,13 @@ class Pool:
     def sync(self):
         _check(self._L.lbm_pool_sync(self._h), "lbm_pool_sync")
 
+    def persistent_members(self):
+        """Workgroups that took part in the last persistent launch."""
+        n = self._L.lbm_pool_persistent_members(self._h)
+        if n < 0:
+            raise LBMError(n, "lbm_pool_persistent_members")
+        return n
+
     def moments(self, slot, fields=True, check=True):
         shape = self.shapes[slot]
         rho = np.empty(shape) if fields else None

@@ -55,6 +55,7 @@ def test_persistent_with_few_workgroups_bitwise():
         for s, f in zip(slots, fields):
             P.init(s, *f)
         P.step(slots, [c[4] for c in CASES])
+        assert 1 <= P.persistent_members() <= 4
         got = [P.get_f(s) for s in slots]
     for (nx, ny, tau, c2, n), f, g in zip(CASES, fields, got):
         assert np.array_equal(g, run_alone(nx, ny, tau, c2, n, "f32", f))
@@ -78,6 +79,9 @@ def test_persistent_every_shape_bitwise(dtype, vx, nw):
             P.init(s, *f)
         P.step(slots, [c[4] for c in CASES])
         P.sync()
+        # every CU holds at least one workgroup of these shapes, and the
+        # resident workgroups all join before membership closes
+        assert P.persistent_members() >= torch.cuda.get_device_properties(0).multi_processor_count
         got = [P.get_f(s) for s in slots]
     for (nx, ny, tau, c2, n), f, g in zip(CASES, fields, got):
         assert np.array_equal(g, run_alone(nx, ny, tau, c2, n, dtype, f)), (nx, ny)
