@@ -615,7 +615,10 @@ int lbm_pool_autotune(lbm_pool* P, const int* slots, int count, int reps, int us
         P->xcd_chunk = c.ch;
         return lbm_pool_set_tile(P, c.vx, c.nw, c.flags);
     }
-    const std::vector<TileCand> cands = pool_candidates(P->dtype);
+    std::vector<TileCand> cands = pool_candidates(P->dtype);
+    if (pers)  // 4-wave tiles (2 rows each) take one atomic per 2 rows: far slower persistent, and slow to time
+        cands.erase(std::remove_if(cands.begin(), cands.end(), [](const TileCand& k) { return k.nw < 8; }),
+                    cands.end());
     // one batched launch at step 0 of a 1-step call (a persistent launch of
     // one step in persistent mode): reads each slot's current buffer and
     // writes the other, without advancing any slot. The
