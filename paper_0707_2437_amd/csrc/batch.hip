@@ -94,16 +94,16 @@ __device__ __forceinline__ bool wait_generation(unsigned* bar, unsigned gen, uns
 // not depend on every workgroup of the grid being resident at once (the
 // occupancy the runtime reports for a launch can exceed what the hardware
 // holds, e.g. when scalar registers are the limit). Each workgroup joins
-// with one compare-and-swap on the membership word unless it is closed, and
+// with one atomic add on the membership word unless it is closed, and
 // waits until the whole grid has joined or `grace_ticks` have passed since
 // its own join (the resident workgroups start within microseconds of each
 // other; without the wait, the first to arrive could close membership
 // before the others have joined, which is correct but leaves them idle).
 // Joined workgroups then meet at a first barrier, and the arrival that
-// completes it (all joined have arrived) closes membership in the same
-// compare-and-swap, so no workgroup can join after the count is fixed. A
-// workgroup that starts after closing (it was not resident) takes no part
-// and ends. Returns the member count (0: not a member, or a bounded wait
+// completes it (all joined have arrived) closes membership with a
+// compare-and-swap that fails if anyone joined meanwhile, so no workgroup
+// can join after the count is fixed. A workgroup that starts after closing
+// (it was not resident) takes no part and ends. Returns the member count (0: not a member, or a bounded wait
 // timed out) and the workgroup's rank in joining order.
 __device__ __forceinline__ int join_members(unsigned* bar, unsigned long long wait_ticks,
                                             unsigned long long grace_ticks, int* rank)
@@ -113,17 +113,12 @@ __device__ __forceinline__ int join_members(unsigned* bar, unsigned long long wa
     if (threadIdx.x == 0) {
         unsigned long long* m = member_word(bar);
         sh_count = 0;
-        unsigned long long old = __hip_atomic_load(m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        bool joined = false;
-        while (!(old & kClosed)) {
-            if (__hip_atomic_compare_exchange_weak(m, &old, old + (1ull << 32), __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                    __HIP_MEMORY_SCOPE_AGENT)) {
-                joined = true;
-                sh_rank = (int)((old >> 32) & 0x7fffffffu);
-                break;
-            }
-        }
-        if (joined) {
+        // join: one fetch-and-add of the joined count; a workgroup that
+        // finds membership closed is not a member (its increment after the
+        // close is never read)
+        unsigned long long old = __hip_atomic_fetch_add(m, 1ull << 32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (!(old & kClosed)) {
+            sh_rank = (int)((old >> 32) & 0x7fffffffu);
             const unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
             const unsigned long long t0 = wall_clock64();
             old = __hip_atomic_load(m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -131,18 +126,22 @@ __device__ __forceinline__ int join_members(unsigned* bar, unsigned long long wa
                 __builtin_amdgcn_s_sleep(2);
                 old = __hip_atomic_load(m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
-            unsigned long long nw;
-            bool last;
-            do {
-                const unsigned arrived = (unsigned)(old & 0xffffffffu) + 1u;
-                const unsigned members = (unsigned)((old >> 32) & 0x7fffffffu);
-                last = arrived == members;
-                nw = (old + 1u) | (last ? kClosed : 0ull);
-            } while (!__hip_atomic_compare_exchange_weak(m, &old, nw, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                          __HIP_MEMORY_SCOPE_AGENT));
+            // arrive: one fetch-and-add of the arrived count. The arrival that
+            // finds every joined workgroup arrived tries once to close with a
+            // compare-and-swap from the value it produced; if the word has
+            // changed since, a workgroup joined meanwhile, and its own arrival
+            // will find the counts equal and close.
+            old = __hip_atomic_fetch_add(m, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned long long now = old + 1ull;
+            bool closed = false;
+            if ((unsigned)(now & 0xffffffffu) == (unsigned)((now >> 32) & 0x7fffffffu)) {
+                unsigned long long expect = now;
+                closed = __hip_atomic_compare_exchange_strong(m, &expect, now | kClosed, __ATOMIC_RELAXED,
+                                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
             bool ok = true;
-            if (last) {
-                __hip_atomic_store(&bar[3], (unsigned)((nw >> 32) & 0x7fffffffu), __ATOMIC_RELAXED,
+            if (closed) {
+                __hip_atomic_store(&bar[3], (unsigned)((now >> 32) & 0x7fffffffu), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
                 __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             } else {
