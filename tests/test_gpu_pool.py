@@ -87,6 +87,34 @@ def test_persistent_every_shape_bitwise(dtype, vx, nw):
         assert np.array_equal(g, run_alone(nx, ny, tau, c2, n, dtype, f)), (nx, ny)
 
 
+def test_persistent_beside_a_running_kernel_bitwise():
+    """A persistent launch made while another stream's kernels hold part of
+    the GPU (a 4096^2 lattice stepping on a second stream): the workgroups
+    that are resident when it starts take part, the others end, and every
+    lattice is still bitwise the plain kernel's."""
+    fields = [smooth_random_state(nx, ny, seed=3 * k + 4) for k, (nx, ny, *_) in enumerate(CASES)]
+    other = torch.cuda.Stream()
+    mine = torch.cuda.Stream()
+    with lbm.Lattice(4096, 4096, 0.6, 0.2, "f32") as big, lbm.Pool(1 << 30, "f32") as P:
+        big.set_stream(other)
+        big.init()
+        P.set_stream(mine)
+        P.set_mode(lbm.PERSISTENT)
+        slots = [P.add(nx, ny, tau, c2) for (nx, ny, tau, c2, _) in CASES]
+        for s, f in zip(slots, fields):
+            P.init(s, *f)
+        torch.cuda.synchronize()
+        big.step(200)  # about 40 ms of work queued on the other stream
+        P.step(slots, [c[4] for c in CASES])
+        P.sync()
+        members = P.persistent_members()
+        got = [P.get_f(s) for s in slots]
+        torch.cuda.synchronize()
+    assert members >= 1
+    for (nx, ny, tau, c2, n), f, g in zip(CASES, fields, got):
+        assert np.array_equal(g, run_alone(nx, ny, tau, c2, n, "f32", f)), (nx, ny)
+
+
 @pytest.mark.parametrize("tile,per_item", [((1, 4, 0), 1), ((2, 16, 2), 3), ((4, 8, 0), 8), ((2, 8, 2), 64)])
 def test_pool_tile_does_not_change_results(tile, per_item):
     fields = [smooth_random_state(nx, ny, seed=k) for k, (nx, ny, *_) in enumerate(CASES)]
