@@ -177,18 +177,22 @@ def cpu_baseline(workloads, n, steps, steps_one_core):
 
     rho, ux, uy = workloads.plane_wave_fields(n, n, 0.2, seed=1)
 
-    def leg(threads, k):
+    def leg(threads, k, keep=False):
         oracle.set_threads(threads)
         o = oracle.Oracle(n, n, 0.6, 0.2).init(rho, ux, uy)
         o.step(1)  # page in
         t0 = time.perf_counter()
         o.step(k)
         sec = time.perf_counter() - t0
+        if keep:
+            return n * n * k / sec / 1e6, sec, oracle.get_threads(), o
         o.close()
-        return n * n * k / sec / 1e6, sec, oracle.get_threads()
+        return n * n * k / sec / 1e6, sec, oracle.get_threads(), None
 
-    all_mlups, all_sec, cores = leg(0, steps)
-    one_mlups, one_sec, _ = leg(1, steps_one_core)
+    all_mlups, all_sec, cores, ref = leg(0, steps, keep=True)
+    parity = parity_against(ref, rho, ux, uy, n, steps + 1)
+    ref.close()
+    one_mlups, one_sec, _, _ = leg(1, steps_one_core)
     oracle.set_threads(0)
     try:
         usable = len(os.sched_getaffinity(0))
@@ -202,7 +206,29 @@ def cpu_baseline(workloads, n, steps, steps_one_core):
                          "seconds": round(one_sec, 2)},
             "all_cores": {"value": round(all_mlups, 2), "unit": "MLUPS", "threads": cores, "steps": steps,
                           "seconds": round(all_sec, 2)},
-            "cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": usable}
+            "cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": usable, "parity": parity}
+
+
+def parity_against(ref, rho, ux, uy, n, steps, amp=1e-3):
+    """The GPU's FP32 and FP64 forms against the oracle state `ref` (the same
+    lattice, fields and step count): max relative error in f, and the errors
+    of delta rho and u normalised by the wave's amplitude."""
+    import numpy as np
+    import paper_0707_2437_amd as lbm
+
+    f_ref = ref.get_f()
+    r_ref, ux_ref, uy_ref, _ = ref.moments()
+    out = {"steps": steps, "lattice": [n, n], "c2": 0.2, "tau": 0.6}
+    for dtype in ("f32", "f64"):
+        with lbm.Lattice(n, n, 0.6, 0.2, dtype) as L:
+            L.init(rho, ux, uy).step(steps)
+            f = L.get_f()
+            r, u, v, _ = L.moments()
+        out[dtype] = {"max_rel_err_f": float(np.max(np.abs(f - f_ref) / np.abs(f_ref))),
+                      "drho_err_over_amp": float(np.max(np.abs(r - r_ref)) / amp),
+                      "u_err_over_amp": float(max(np.max(np.abs(u - ux_ref)), np.max(np.abs(v - uy_ref))) / amp)}
+        del f
+    return out
 
 
 def measure_batched(lbm, workloads, torch, nlat, steps, mode, warmup=5, persistent_steps=0):
