@@ -52,6 +52,8 @@ def parse():
     p.add_argument("--batch-mode", default="graph", choices=["grouped", "graph", "persistent"])
     p.add_argument("--batch-persistent-steps", type=int, default=200,
                    help="also time the persistent form for this many steps (0: skip)")
+    p.add_argument("--pcie-steps", type=int, default=1000,
+                   help="steps of the host-array run (fields in, populations out; 0: skip)")
     p.add_argument("--precision-steps", type=int, default=300,
                    help="steps of the precision workload (8192^2 shear wave, shifted FP32 / FP16; 0: skip)")
     p.add_argument("--serve-seconds", type=float, default=30.0,
@@ -314,6 +316,30 @@ def measure_batched(lbm, workloads, torch, nlat, steps, mode, warmup=5, persiste
             "graph_capture_s": None if capture is None else max(0.0, capture - sec)}
 
 
+def measure_host_transfers(lbm, workloads, torch, n, steps):
+    """One lattice of the sweep as a caller with host arrays runs it: FP64
+    fields in through lbm_init (host to device, then the equilibrium set-up
+    kernel), `steps` steps, the populations back through lbm_get_f (device to
+    host, FP64). Not the headline (which starts with the state resident in
+    HBM); the rate that includes PCIe."""
+    rho, ux, uy = workloads.plane_wave_fields(n, n, 0.2, seed=1)
+    with lbm.Lattice(n, n, 0.6, 0.2, "f32") as L:
+        L.init(rho, ux, uy).step(2)
+        L.get_f()  # warm: buffers, staging memory, code
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L.init(rho, ux, uy)  # synchronous
+        t1 = time.perf_counter()
+        L.step(steps)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        L.get_f()  # synchronous
+        t3 = time.perf_counter()
+    return {"mlups": n * n * steps / (t3 - t0) / 1e6, "steps": steps, "lattice": [n, n],
+            "init_s": t1 - t0, "steps_s": t2 - t1, "get_f_s": t3 - t2,
+            "bytes_in": 3 * n * n * 8, "bytes_out": 9 * n * n * 8}
+
+
 def measure_precision(lbm, workloads, torch, steps, warmup=5, n=8192):
     """The precision workload: a periodic 8192^2 shear wave (tau = 0.7,
     c^2 = 0.25) in the shifted FP32 and FP16 storage forms."""
@@ -414,6 +440,9 @@ def main():
         sv = forms["served_f32"]
         print(f"# served: {sv['mlups']:.0f} MLUPS, {sv['jobs_completed']} jobs done, latency p50 "
               f"{sv['latency_p50_s']} s p99 {sv['latency_p99_s']} s", file=sys.stderr, flush=True)
+
+    if a.pcie_steps > 0:
+        forms["f32_with_host_transfers"] = measure_host_transfers(lbm, workloads, torch, n, a.pcie_steps)
 
     cpu = None if a.no_cpu else cpu_baseline(workloads, n, a.cpu_steps, a.cpu_steps_one_core)
     if cpu is not None:
