@@ -95,3 +95,31 @@ def test_batched_full_size_against_plain_kernel_and_oracle():
               f"max rel err {err:.2e}", flush=True)
         assert err <= TOL_F32, (k, sp, err)
     print(f"worst over {len(subset)} lattices: {worst:.2e}")
+
+
+def test_batched_full_size_one_persistent_launch():
+    """The same workload as one persistent launch of 2000 steps (its own
+    autotuned shape): every lattice's populations bitwise equal to the graph
+    mode's, which the test above ties to the plain kernel and the oracle."""
+    specs = workloads.batch_specs(256, seed=0)
+    stream = torch.cuda.Stream()
+    budget = sum(lbm.Pool.slot_bytes(s["nx"], s["ny"], "f32") for s in specs)
+    states = {}
+    for mode in (lbm.GRAPH, lbm.PERSISTENT):
+        with lbm.Pool(budget, "f32") as P:
+            P.set_stream(stream)
+            P.set_mode(mode)
+            slots = []
+            for sp in specs:
+                s = P.add(sp["nx"], sp["ny"], sp["tau"], sp["c2"])
+                P.init(s, *workloads.batch_fields(sp))
+                slots.append(s)
+            tile = P.autotune(slots, reps=3)
+            P.step(slots, STEPS)
+            P.sync()
+            if mode == lbm.PERSISTENT:
+                print(f"persistent tile {tile}, {P.persistent_members()} workgroups", flush=True)
+            states[mode] = [P.get_f(s) for s in slots]
+    for k, (a, b) in enumerate(zip(states[lbm.GRAPH], states[lbm.PERSISTENT])):
+        assert np.array_equal(a, b), (k, specs[k])
+    print("all 256 lattices bitwise equal in graph and persistent modes", flush=True)
