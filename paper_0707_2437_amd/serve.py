@@ -46,7 +46,7 @@ class Job:
     remaining: int = 0
     t_admit: float = math.nan
     t_done: float = math.nan
-    status: str = "queued"  # queued | running | done | failed
+    status: str = "queued"  # queued | running | retiring (totals in flight) | done | failed
     totals: list = field(default_factory=list)
 
     @property
@@ -83,7 +83,8 @@ def pulse_field_device(torch, nx, ny, amp, device="cuda"):
 
 
 class Server:
-    def __init__(self, budget_bytes, dtype="f32", tick_steps=100, stream=None, keep_f=False, progress_every=0.0):
+    def __init__(self, budget_bytes, dtype="f32", tick_steps=100, stream=None, keep_f=False, progress_every=0.0,
+                 ring_rows=1024):
         import torch
 
         self.torch = torch
@@ -107,7 +108,7 @@ class Server:
         self._ring = 0
         self._ring_dev = None
         self._ring_host = None
-        self._ensure_ring(1024)
+        self._ensure_ring(int(ring_rows))
 
     def _ensure_ring(self, rows):
         if self._ring_dev is not None and self._ring_dev.shape[0] >= rows:
@@ -175,8 +176,11 @@ class Server:
         entry = {"ev0": ev0, "ev1": ev1, "jobs": done}
         if done:
             if self._ring + len(done) > self._ring_dev.shape[0]:
-                self._ensure_ring(max(2 * self._ring_dev.shape[0], len(done)))
-                if self._ring + len(done) > self._ring_dev.shape[0]:
+                # wrap: read back every queued tick first (their rows are
+                # reused); grow when one tick's jobs fill half the ring
+                if 2 * len(done) > self._ring_dev.shape[0]:
+                    self._ensure_ring(2 * len(done))
+                else:
                     self.drain(keep=0)
                     self._ring = 0
             r0 = self._ring
@@ -193,7 +197,7 @@ class Server:
             evd = torch.cuda.Event()
             evd.record(self.stream)
             entry.update({"rows": rows, "done_ev": evd})
-            self._ring = (r0 + len(done)) % self._ring_dev.shape[0]
+            self._ring = r0 + len(done)
         self.pending.append(entry)
 
     def drain(self, keep=1):

@@ -43,6 +43,27 @@ def test_each_job_same_alone_and_in_the_mix():
         assert j.t_done >= j.t_admit >= j.arrival
 
 
+def test_totals_ring_wraps_and_grows():
+    """The totals of finishing jobs go through a ring of device rows copied to
+    pinned host rows and read one tick later. With a ring of 4 rows and many
+    short jobs, the ring wraps (after reading back the queued ticks) and
+    grows (when one tick finishes more jobs than half of it); every job's
+    FP64 totals are still bitwise those of the job stepped alone."""
+    jobs = serve.job_stream(rate=3000.0, duration=0.025, seed=11, side_log2=(5, 6), steps=(10, 80))
+    assert len(jobs) >= 40
+    srv = serve.Server(1 << 28, "f32", tick_steps=7, ring_rows=4)
+    st = srv.run(jobs, duration=0.0, drain=True)
+    srv.close()
+    assert st["jobs_completed"] == len(jobs)
+    assert srv._ring_dev.shape[0] > 4  # it grew at least once
+    for j in srv.finished:
+        rho = serve.pulse_field_device(torch, j.nx, j.ny, j.amp)
+        with lbm.Lattice(j.nx, j.ny, j.tau, j.c2, "f32") as L:
+            L.init_device(rho, None, None)
+            tot = L.step(j.steps).totals()
+        assert np.array_equal(np.asarray(tot), np.asarray(j.totals)), j.id
+
+
 def test_unstable_job_fails_alone():
     jobs = [serve.Job(id=0, nx=64, ny=64, tau=0.6, c2=0.3, amp=0.05, steps=200, arrival=0.0),
             serve.Job(id=1, nx=48, ny=48, tau=0.505, c2=3.0, amp=0.3, steps=2000, arrival=0.0),
