@@ -208,6 +208,18 @@ def test_pool_errors():
         with pytest.raises(lbm.LBMError) as ei:
             P.add(2, 32, 0.8, 0.3)
         assert ei.value.status == lbm.EINVAL
+        out = torch.zeros(3, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()  # the fill (torch's stream) before the pool's stream writes
+        with pytest.raises(lbm.LBMError) as ei:
+            P.totals_device(s + 7, out)  # no such slot
+        assert ei.value.status == lbm.EINVAL
+        with pytest.raises(lbm.LBMError) as ei:
+            P.step_noalloc([s, s], [1, 1])  # a slot listed twice
+        assert ei.value.status == lbm.EINVAL
+        assert P.persistent_members() == 0  # no persistent launch yet
+        P.totals_device(s, out)
+        P.sync()
+        assert np.array_equal(out.cpu().numpy(), P.totals(s)[0])
 
 
 def test_nonfinite_job_detected_and_isolated():
