@@ -205,13 +205,23 @@ size_t lbm_footprint_bytes(int nx, int ny, int dtype);
  * a march-form shape (no LBM_TILE_VSTACK) while the lattice has a c2 field,
  * or for a shape whose grid would exceed one dispatch (2^32 work items) on
  * this lattice (only small shapes on the largest lattices).
+ * Two-step form (LBM_TILE_VSTACK | LBM_TILE_TWO_STEP, optionally
+ * LBM_TILE_NT_STORE; LBM_F64, LBM_F32 and LBM_F32S): one launch takes two
+ * steps of Eq. 5, keeping the first step's results in on-chip memory, so
+ * each site is loaded and stored once per two steps. vx = 1 or 2, nw = 12
+ * or 16 waves; a workgroup writes nw - 6 rows and (64 - 2 ceil(2 / vx)) vx
+ * columns. lbm_step takes the steps in pairs; a lone last step, and every
+ * step while inlet/outlet boundaries are set, use the default shape. The
+ * results are those of single steps, bit for bit. LBM_EINVAL while the
+ * lattice has a c2 field; setting a c2 field replaces it by the default.
  * lbm_get_tile: any pointer may be NULL. */
 enum lbm_tile_flags {
     LBM_TILE_PREFETCH = 1, /* issue the next row's loads before relaxing the current row */
     LBM_TILE_NT_STORE = 2, /* non-temporal (streaming) stores                              */
     LBM_TILE_ROWBAND = 4,  /* tile order: all strips of a row chunk before the next chunk  */
     LBM_TILE_PREFETCH2 = 8, /* issue loads two rows ahead (overrides LBM_TILE_PREFETCH)     */
-    LBM_TILE_VSTACK = 16    /* vertical-stack form (no march; uses only LBM_TILE_NT_STORE)  */
+    LBM_TILE_VSTACK = 16,   /* vertical-stack form (no march; uses only LBM_TILE_NT_STORE)  */
+    LBM_TILE_TWO_STEP = 32  /* with LBM_TILE_VSTACK: two steps per launch (see lbm_set_tile) */
 };
 int lbm_set_tile(lbm_lattice* L, int vx, int nw, int h, int flags);
 int lbm_get_tile(const lbm_lattice* L, int* vx, int* nw, int* h, int* flags);

@@ -15,7 +15,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblbm.so")
-SOURCES = ["kernels.hip", "batch.hip", "runtime.hip", "pool.hip", "tune.hip"]
+SOURCES = ["kernels.hip", "step2.hip", "batch.hip", "runtime.hip", "pool.hip", "tune.hip"]
 ARCH = os.environ.get("LBM_OFFLOAD_ARCH", "gfx950")
 
 

@@ -10,10 +10,15 @@
 
 #include "internal.h"
 #include "liblbm.h"
+#include "step2.h"
 
 namespace lbm {
 hipError_t launch_step(int dtype, int vx, int nw, int flags, const StepTile& t, hipStream_t st);
 bool step_shape_supported(int dtype, int vx, int nw, int flags);
+// Two steps per launch (step2.hip); t's strips and row groups are those of
+// step2_cols / step2_rows.
+hipError_t launch_step2(int dtype, int vx, int nw, int flags, const StepTile& t, hipStream_t st);
+bool step2_shape_supported(int dtype, int vx, int nw);
 hipError_t launch_init(int dtype, void* s, const Geom& g, const double* rho, const double* ux, const double* uy,
                        double eqs, hipStream_t st);
 hipError_t launch_xbc(int dtype, void* s, const Geom& g, double rho_in, double eqs, hipStream_t st);

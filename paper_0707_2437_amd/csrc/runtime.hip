@@ -55,13 +55,24 @@ TileDefault default_tile(int dtype)
     }
 }
 
+// A step shape of lbm_set_tile: the two-step form (LBM_TILE_TWO_STEP, with
+// LBM_TILE_VSTACK and at most LBM_TILE_NT_STORE besides) or a single-step one.
+bool tile_supported(int dtype, int vx, int nw, int flags)
+{
+    if (flags & ~63) return false;
+    if (flags & LBM_TILE_TWO_STEP)
+        return (flags & LBM_TILE_VSTACK) && !(flags & ~(LBM_TILE_TWO_STEP | LBM_TILE_VSTACK | LBM_TILE_NT_STORE)) &&
+               step2_shape_supported(dtype, vx, nw);
+    return step_shape_supported(dtype, vx, nw, flags);
+}
+
 // Optional override for experiments: LBM_TILE="vx,nw,h,flags".
 void apply_tile_env(int dtype, int* vx, int* nw, int* h, int* flags)
 {
     const char* e = std::getenv("LBM_TILE");
     int a = 0, b = 0, c = 0, f = 0;
-    if (e && std::sscanf(e, "%d,%d,%d,%d", &a, &b, &c, &f) == 4 && step_shape_supported(dtype, a, b, f) &&
-        !(f & ~31) && (c > 0 || (f & LBM_TILE_VSTACK))) {
+    if (e && std::sscanf(e, "%d,%d,%d,%d", &a, &b, &c, &f) == 4 && tile_supported(dtype, a, b, f) &&
+        (c > 0 || (f & LBM_TILE_VSTACK))) {
         *vx = a;
         *nw = b;
         *h = c;
@@ -78,7 +89,13 @@ StepTile make_tile(const lbm_lattice* L)
     t.c = L->coef;
     t.h = L->h;
     t.xcd_chunk = 0;
-    if (L->kflags & LBM_TILE_VSTACK) {
+    if (L->kflags & LBM_TILE_TWO_STEP) {
+        // step2_cols(vx) columns and step2_rows(nw) rows per workgroup
+        const int W = step2_cols(L->vx), R = step2_rows(L->nw);
+        t.nstrips = (L->nx + W - 1) / W;
+        t.nchunks = (L->ny + R - 1) / R;
+        t.xcd_chunk = xcd_chunk_tiles(t.nstrips);
+    } else if (L->kflags & LBM_TILE_VSTACK) {
         // one strip of 64 * vx columns and nw - 2 rows per workgroup
         const int W = 64 * L->vx, R = L->nw - 2;
         t.nstrips = (L->nx + W - 1) / W;
@@ -95,11 +112,11 @@ StepTile make_tile(const lbm_lattice* L)
     return t;
 }
 
-// A lattice with a c2 field steps with the vertical-stack kernels only: a
-// march-form tile is replaced by the dtype's default.
+// A lattice with a c2 field steps with the single-step vertical-stack
+// kernels only: another tile is replaced by the dtype's default.
 void field_tile(lbm_lattice* L)
 {
-    if (L->kflags & LBM_TILE_VSTACK) return;
+    if ((L->kflags & LBM_TILE_VSTACK) && !(L->kflags & LBM_TILE_TWO_STEP)) return;
     const TileDefault td = default_tile(L->dtype);
     L->vx = td.vx;
     L->nw = td.nw;
@@ -239,8 +256,9 @@ long long lbm_time(const lbm_lattice* L) { return L ? L->t : -1; }
 
 int lbm_set_tile(lbm_lattice* L, int vx, int nw, int h, int flags)
 {
-    if (!L || (flags & ~31) || !step_shape_supported(L->dtype, vx, nw, flags)) return LBM_EINVAL;
+    if (!L || !tile_supported(L->dtype, vx, nw, flags)) return LBM_EINVAL;
     if (!(flags & LBM_TILE_VSTACK) && (h < 1 || L->field)) return LBM_EINVAL;
+    if ((flags & LBM_TILE_TWO_STEP) && L->field) return LBM_EINVAL;
     {
         // the shape's grid must fit one dispatch for this lattice
         lbm_lattice tmp = *L;
@@ -269,18 +287,26 @@ int lbm_autotune(lbm_lattice* L, int reps, int use_cache)
     TileCand c{};
     if (use_cache && tune_cache_get(key, &c)) return lbm_set_tile(L, c.vx, c.nw, c.h, c.flags);
     std::vector<TileCand> cands = lattice_candidates(L->dtype);
-    if (L->field)  // the vertical-stack kernels only
+    if (L->field)  // the single-step vertical-stack kernels only
         cands.erase(std::remove_if(cands.begin(), cands.end(),
-                                   [](const TileCand& k) { return !(k.flags & LBM_TILE_VSTACK); }),
+                                   [](const TileCand& k) {
+                                       return !(k.flags & LBM_TILE_VSTACK) || (k.flags & LBM_TILE_TWO_STEP);
+                                   }),
                     cands.end());
-    // read cur, write nxt, no swap: the state does not change
+    // Each candidate is timed over two steps (two single-step launches or
+    // one two-step launch), reading cur and writing nxt with no swap: the
+    // state does not change.
     auto launch = [&](const TileCand& k) -> hipError_t {
         lbm_lattice tmp = *L;
         tmp.vx = k.vx;
         tmp.nw = k.nw;
         tmp.h = k.h;
         tmp.kflags = k.flags;
-        return launch_step(L->dtype, k.vx, k.nw, k.flags, make_tile(&tmp), L->stream);
+        const StepTile t = make_tile(&tmp);
+        if (k.flags & LBM_TILE_TWO_STEP) return launch_step2(L->dtype, k.vx, k.nw, k.flags, t, L->stream);
+        hipError_t e = launch_step(L->dtype, k.vx, k.nw, k.flags, t, L->stream);
+        if (e == hipSuccess) e = launch_step(L->dtype, k.vx, k.nw, k.flags, t, L->stream);
+        return e;
     };
     float us = 0;
     const int best = time_candidates(cands, reps, L->stream, launch, &us);
@@ -398,17 +424,38 @@ int lbm_step(lbm_lattice* L, int n)
 {
     if (!L || n < 0) return LBM_EINVAL;
     if (!L->ready) return LBM_ESTATE;
-    for (int k = 0; k < n; ++k) {
-        StepTile t = make_tile(L);
-        hipError_t e = launch_step(L->dtype, L->vx, L->nw, L->kflags, t, L->stream);
-        if (e == hipSuccess && L->xbc == LBM_XBC_INLET_OUTLET)
-            e = launch_xbc(L->dtype, L->nxt, L->g, inlet_density(L->amp, L->period, L->t), eq_shift(L->c2, L->model),
-                           L->stream);
+    // A two-step shape advances two steps per launch; a lone last step, and
+    // every step of a lattice with inlet/outlet boundaries (applied after
+    // each step), take the dtype's default single-step shape.
+    const bool two = (L->kflags & LBM_TILE_TWO_STEP) != 0;
+    lbm_lattice one = *L;
+    if (two) {
+        const TileDefault td = default_tile(L->dtype);
+        one.vx = td.vx;
+        one.nw = td.nw;
+        one.h = td.h;
+        one.kflags = td.flags;
+    }
+    for (int k = 0; k < n;) {
+        hipError_t e;
+        int done = 1;
+        if (two && L->xbc != LBM_XBC_INLET_OUTLET && n - k >= 2) {
+            e = launch_step2(L->dtype, L->vx, L->nw, L->kflags, make_tile(L), L->stream);
+            done = 2;
+        } else {
+            one.cur = L->cur;
+            one.nxt = L->nxt;
+            e = launch_step(L->dtype, one.vx, one.nw, one.kflags, make_tile(&one), L->stream);
+            if (e == hipSuccess && L->xbc == LBM_XBC_INLET_OUTLET)
+                e = launch_xbc(L->dtype, L->nxt, L->g, inlet_density(L->amp, L->period, L->t),
+                               eq_shift(L->c2, L->model), L->stream);
+        }
         if (e != hipSuccess) return status_of(e);
         void* tmp = L->cur;
         L->cur = L->nxt;
         L->nxt = tmp;
-        L->t += 1;
+        L->t += done;
+        k += done;
     }
     return LBM_OK;
 }

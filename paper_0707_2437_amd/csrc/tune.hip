@@ -98,13 +98,18 @@ std::vector<TileCand> lattice_candidates(int dtype)
         for (int nw : nws)
             for (int nts = 0; nts < 2; ++nts)
                 v.push_back({vx, nw, 8, LBM_TILE_VSTACK | (nts ? LBM_TILE_NT_STORE : 0), 0});
+    // two steps per launch (FP16 storage has no two-step form)
+    if (dtype != LBM_F16S)
+        for (int vx : {1, 2})
+            for (int nw : {12, 16})
+                for (int nts = 0; nts < 2; ++nts)
+                    v.push_back({vx, nw, 8, LBM_TILE_VSTACK | LBM_TILE_TWO_STEP | (nts ? LBM_TILE_NT_STORE : 0), 0});
     // march form: prefetched, row-band order
     for (int vx : {1, 2})
         for (int h : {4, 8})
             for (int f : {LBM_TILE_PREFETCH2 | LBM_TILE_NT_STORE | LBM_TILE_ROWBAND,
                           LBM_TILE_PREFETCH | LBM_TILE_NT_STORE | LBM_TILE_ROWBAND})
                 v.push_back({vx, 4, h, f, 0});
-    (void)dtype;
     return v;
 }
 

@@ -1,0 +1,111 @@
+"""The two-step form (LBM_TILE_VSTACK | LBM_TILE_TWO_STEP: two steps of Eq. 5
+per launch, the first step's results held in LDS) gives the bits of single
+steps: every shape, stored type and store flavour, on lattices that span
+several tiles with ragged edges and on lattices smaller than one tile (whose
+halo rows and columns are periodic images of the lattice itself), for odd
+and even step counts (a lone last step takes the single-step kernel). The
+oracle check of the single-step path therefore carries over; one case is
+also checked against the oracle directly."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import max_rel_err, smooth_random_state
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_0707_2437_amd as lbm  # noqa: E402
+
+VSTACK, TWO_STEP, NT = 16, 32, 2
+SHAPES = [(vx, nw, f) for vx in (1, 2) for nw in (12, 16) for f in (VSTACK | TWO_STEP, VSTACK | TWO_STEP | NT)]
+
+
+def run(nx, ny, tau, c2, dtype, steps, fields, tile=None, model=None):
+    with lbm.Lattice(nx, ny, tau, c2, dtype) as L:
+        if model is not None:
+            L.set_model(model)
+        if tile:
+            L.set_tile(*tile)
+        L.init(*fields)
+        L.step(steps)
+        return L.get_f()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "f32s"])
+@pytest.mark.parametrize("nx,ny", [(3, 3), (5, 4), (7, 3), (65, 3), (130, 77), (300, 41), (257, 129)])
+def test_two_step_bitwise_equals_single_steps(dtype, nx, ny):
+    fields = smooth_random_state(nx, ny, seed=nx * 31 + ny)
+    for steps in (6, 7):
+        ref = run(nx, ny, 0.7, 0.45, dtype, steps, fields)
+        for vx, nw, f in SHAPES:
+            got = run(nx, ny, 0.7, 0.45, dtype, steps, fields, (vx, nw, 0, f))
+            assert np.array_equal(got, ref), (dtype, nx, ny, steps, vx, nw, f)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_two_step_altered_equilibrium_model_bitwise(dtype):
+    nx, ny = 200, 90
+    fields = smooth_random_state(nx, ny, seed=5)
+    ref = run(nx, ny, 0.75, 0.2, dtype, 8, fields, model=lbm.MODEL_EQUILIBRIUM)
+    for vx, nw in ((1, 16), (2, 12)):
+        got = run(nx, ny, 0.75, 0.2, dtype, 8, fields, (vx, nw, 0, VSTACK | TWO_STEP | NT), model=lbm.MODEL_EQUILIBRIUM)
+        assert np.array_equal(got, ref), (dtype, vx, nw)
+
+
+def test_two_step_parity_with_oracle():
+    nx, ny, tau, c2 = 130, 77, 0.8, 0.2
+    fields = smooth_random_state(nx, ny, seed=77)
+    ref = oracle.Oracle(nx, ny, tau, c2).init(*fields).step(40).get_f()
+    for dtype, tol in (("f64", 1e-12), ("f32", 1e-5)):
+        got = run(nx, ny, tau, c2, dtype, 40, fields, (2, 16, 0, VSTACK | TWO_STEP | NT))
+        assert max_rel_err(got, ref) <= tol, dtype
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_two_step_full_size_bitwise(dtype):
+    """4096 x 4096, the benchmark's lattice: 10 steps (5 two-step launches)
+    in the default two-step shapes against 10 single steps."""
+    n = 4096
+    rng = np.random.default_rng(3)
+    rho = 1.0 + 1e-3 * rng.standard_normal((n, n))
+    ux = 1e-3 * rng.standard_normal((n, n))
+    uy = 1e-3 * rng.standard_normal((n, n))
+    ref = run(n, n, 0.6, 0.25, dtype, 10, (rho, ux, uy), (2, 8, 0, VSTACK | NT))
+    for vx, nw in ((1, 16), (2, 16)):
+        got = run(n, n, 0.6, 0.25, dtype, 10, (rho, ux, uy), (vx, nw, 0, VSTACK | TWO_STEP | NT))
+        assert np.array_equal(got, ref), (dtype, vx, nw)
+        del got
+
+
+def test_two_step_with_inlet_outlet_and_field():
+    nx, ny = 160, 40
+    fields = smooth_random_state(nx, ny, seed=9)
+    with lbm.Lattice(nx, ny, 0.7, 0.3, "f32") as L:
+        L.set_tile(2, 16, 0, VSTACK | TWO_STEP)
+        L.set_x_boundaries(lbm.XBC_INLET_OUTLET, 0.01, 50.0)
+        got = L.init(*fields).step(9).get_f()
+    with lbm.Lattice(nx, ny, 0.7, 0.3, "f32") as L:
+        L.set_x_boundaries(lbm.XBC_INLET_OUTLET, 0.01, 50.0)
+        ref = L.init(*fields).step(9).get_f()
+    assert np.array_equal(got, ref)
+    with lbm.Lattice(nx, ny, 0.7, 0.3, "f32") as L:
+        L.set_tile(2, 16, 0, VSTACK | TWO_STEP)
+        L.set_c2_field(np.full((ny, nx), 0.3))
+        assert L.get_tile()[3] & TWO_STEP == 0  # a c2 field takes the single-step default
+        with pytest.raises(lbm.LBMError):
+            L.set_tile(2, 16, 0, VSTACK | TWO_STEP)
+
+
+def test_two_step_shape_errors():
+    with lbm.Lattice(64, 64, 0.7, 0.3, "f32") as L:
+        for bad in ((4, 16, 0, VSTACK | TWO_STEP), (2, 8, 0, VSTACK | TWO_STEP), (2, 16, 0, TWO_STEP),
+                    (2, 16, 0, VSTACK | TWO_STEP | 1), (2, 16, 0, 64 | VSTACK)):
+            with pytest.raises(lbm.LBMError):
+                L.set_tile(*bad)
+    with lbm.Lattice(64, 64, 0.7, 0.3, "f16s") as L:
+        with pytest.raises(lbm.LBMError):
+            L.set_tile(2, 16, 0, VSTACK | TWO_STEP)
