@@ -29,7 +29,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
-TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "step_f32_4096_traffic.json")
+# rocprofv3 counter records of the FP32 4096^2 launches: the two-step and single-step kernels
+TRAFFIC_RECORDS = {"step2": os.path.join(ROOT, "profiles", "step2_f32_4096_traffic.json"),
+                   "step": os.path.join(ROOT, "profiles", "step_f32_4096_traffic.json")}
+TWO_STEP = 32  # LBM_TILE_TWO_STEP
 BYTES_PER_SITE = {"f64": 144, "f32": 72, "f32s": 72, "f16s": 36}  # 9 reads + 9 writes
 FIELD_BYTES = {"f64": 8, "f32": 4, "f32s": 4, "f16s": 4}  # one read of a c^2 field's coefficient
 
@@ -40,9 +43,10 @@ def parse():
     p.add_argument("--steps", type=int, default=1000)
     p.add_argument("--warmup", type=int, default=20)
     p.add_argument("--n", type=int, default=4096, help="lattice side")
-    p.add_argument("--forms", default="f64,f32_eq,f32_field",
+    p.add_argument("--forms", default="f32_1step,f64,f32_eq,f32_field",
                    help="extra forms to time, comma separated ('' for none); a '_eq' suffix selects the "
-                        "altered-equilibrium model over its own c^2 sweep, '_field' a c^2 field per lattice")
+                        "altered-equilibrium model over its own c^2 sweep, '_field' a c^2 field per lattice, "
+                        "'_1step' the single-step kernel")
     p.add_argument("--form-steps", type=int, default=300)
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     p.add_argument("--cpu-steps", type=int, default=100, help="oracle steps on all host cores")
@@ -97,18 +101,26 @@ def make_sweep(lbm, workloads, torch, n, form, stream):
     return lattices
 
 
+def launches_of(tile, steps):
+    """Kernel launches lbm_step makes for `steps` steps in this shape: two
+    steps per launch for a two-step shape (a lone last step takes one more)."""
+    return (steps + 1) // 2 if tile[3] & TWO_STEP else steps
+
+
 def time_sweep(torch, lattices, steps, warmup, stream):
-    for _ in range(warmup):
-        for L in lattices:
-            L.step(1)
+    # Steps are taken two at a time per lattice (one two-step launch, or two
+    # single-step launches), lattice after lattice.
+    def run(k):
+        for s in range(0, k, 2):
+            for L in lattices:
+                L.step(min(2, k - s))
+    run(warmup)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     e0.record(stream)
-    for _ in range(steps):
-        for L in lattices:
-            L.step(1)
+    run(steps)
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -119,6 +131,8 @@ def kernel_name(tile, form):
     vx, nw, h, flags = tile
     dtype, variant = form_parts(form)
     t = {"f64": "double,false", "f32": "float,false", "f32s": "float,true", "f16s": "_Float16,true"}[dtype]
+    if flags & TWO_STEP:
+        return f"lbm::step2_vstack_kernel<{t},{vx},{nw},{'true' if flags & 2 else 'false'}>"
     if flags & 16:
         return (f"lbm::step_vstack_kernel<{t},{vx},{nw},{'true' if flags & 2 else 'false'},"
                 f"{'true' if variant == 'field' else 'false'}>")
@@ -127,30 +141,36 @@ def kernel_name(tile, form):
 
 
 def measured_traffic(kernel, n):
-    """HBM bytes per launch from the committed rocprofv3 counter record, if it
-    was taken on the current kernel source and kernel; else None."""
+    """HBM bytes per launch from the committed rocprofv3 counter record of
+    this kernel (two-step or single-step), if it was taken on the current
+    kernel source and kernel; else None."""
+    which = "step2" if kernel.startswith("lbm::step2_") else "step"
     try:
         from paper_0707_2437_amd import profiling
-        rec = json.load(open(TRAFFIC_RECORD))
+        rec = json.load(open(TRAFFIC_RECORDS[which]))
     except (OSError, ValueError, ImportError):
         return None
-    if rec.get("kernel_source_sha256") != profiling.kernel_source_sha() or rec.get("kernel") != kernel \
+    if rec.get("kernel_source_sha256") != profiling.kernel_source_sha(which) or rec.get("kernel") != kernel \
             or rec.get("algorithmic_bytes_per_launch") != BYTES_PER_SITE["f32"] * n * n:
         return None
     return rec["traffic_bytes_per_launch"]
 
 
-def measure_form(lbm, workloads, torch, n, dtype, steps, warmup):
+def measure_form(lbm, workloads, torch, n, dtype, steps, warmup, tile=None):
     # all launches go to one dedicated stream; the HIP events are recorded on it
     stream = torch.cuda.Stream()
     lats = make_sweep(lbm, workloads, torch, n, dtype, stream)
+    if tile is not None:
+        for L in lats:
+            L.set_tile(*tile)
     tile = lats[0].get_tile()
     sec, wall = time_sweep(torch, lats, steps, warmup, stream)
     tot = [L.totals() for L in lats]
     for L in lats:
         L.close()
     sites = n * n * len(lats)
-    launches = steps * len(lats)
+    # every launch reads and writes each site's nine populations once
+    launches = launches_of(tile, steps) * len(lats)
     mlups = sites * steps / sec / 1e6
     gbs = form_bytes_per_site(dtype) * n * n / (sec / launches) / 1e9
     return {"mlups": mlups, "ms_per_step": 1e3 * sec / steps, "kernel_us": 1e6 * sec / launches,
@@ -355,7 +375,7 @@ def measure_precision(lbm, workloads, torch, steps, warmup=5, n=8192):
         tile = L.get_tile()
         L.close()
         mlups = n * n * steps / sec / 1e6
-        gbs = form_bytes_per_site(dtype) * n * n * steps / sec / 1e9
+        gbs = form_bytes_per_site(dtype) * n * n * launches_of(tile, steps) / sec / 1e9
         out[dtype] = {"mlups": mlups, "achieved_GBs": gbs, "frac": gbs / PEAK_HBM_GBS, "steps": steps,
                       "kernel": kernel_name(tile, dtype), "lattice": [n, n]}
     return out
@@ -417,7 +437,11 @@ def main():
     head = measure_form(lbm, workloads, torch, n, "f32", a.steps, a.warmup)
     forms = {"f32": head}
     for f in [s for s in a.forms.split(",") if s]:
-        forms[f] = measure_form(lbm, workloads, torch, n, f, a.form_steps, a.warmup)
+        if f.endswith("_1step"):  # the single-step vertical-stack kernel (the default shape before two-step)
+            forms[f] = measure_form(lbm, workloads, torch, n, f[:-len("_1step")], a.form_steps, a.warmup,
+                                    tile=(2, 8, 8, 18))
+        else:
+            forms[f] = measure_form(lbm, workloads, torch, n, f, a.form_steps, a.warmup)
         print(f"# form {f}: {forms[f]['mlups']:.0f} MLUPS, {100 * forms[f]['frac']:.1f}% of HBM peak",
               file=sys.stderr, flush=True)
 

@@ -199,9 +199,10 @@ size_t lbm_footprint_bytes(int nx, int ny, int dtype);
  * each owning its own column strip of 64 * vx sites and marching h >= 1
  * rows. Vertical-stack form (LBM_TILE_VSTACK): nw = 4, 8 or 16 waves per
  * workgroup covering one strip and nw - 2 rows (h is ignored). Default:
- * vertical stack with non-temporal stores; vx = 2 and nw = 8 for LBM_F64,
- * LBM_F32 and LBM_F32S, vx = 4 and nw = 8 for LBM_F16S. Results do not
- * depend on the shape (bitwise). LBM_EINVAL for an unsupported shape, for
+ * the two-step form below with vx = 2 and nw = 16 for LBM_F64 (plain
+ * stores), LBM_F32 and LBM_F32S (non-temporal stores); for LBM_F16S the
+ * vertical stack with vx = 4, nw = 8 and non-temporal stores. Results do
+ * not depend on the shape (bitwise). LBM_EINVAL for an unsupported shape, for
  * a march-form shape (no LBM_TILE_VSTACK) while the lattice has a c2 field,
  * or for a shape whose grid would exceed one dispatch (2^32 work items) on
  * this lattice (only small shapes on the largest lattices).
@@ -211,9 +212,11 @@ size_t lbm_footprint_bytes(int nx, int ny, int dtype);
  * each site is loaded and stored once per two steps. vx = 1 or 2, nw = 12
  * or 16 waves; a workgroup writes nw - 6 rows and (64 - 2 ceil(2 / vx)) vx
  * columns. lbm_step takes the steps in pairs; a lone last step, and every
- * step while inlet/outlet boundaries are set, use the default shape. The
+ * step while inlet/outlet boundaries are set, use the single-step vertical
+ * stack (vx = 2, nw = 8, non-temporal stores). The
  * results are those of single steps, bit for bit. LBM_EINVAL while the
- * lattice has a c2 field; setting a c2 field replaces it by the default.
+ * lattice has a c2 field; setting a c2 field replaces it by that
+ * single-step shape.
  * lbm_get_tile: any pointer may be NULL. */
 enum lbm_tile_flags {
     LBM_TILE_PREFETCH = 1, /* issue the next row's loads before relaxing the current row */

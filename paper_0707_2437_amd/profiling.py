@@ -33,12 +33,13 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = {
     "step": [os.path.join(PKG, "csrc", n) for n in ("kernels.hip", "step.h", "internal.h")],
     "batch": [os.path.join(PKG, "csrc", n) for n in ("batch.hip", "step.h", "internal.h")],
+    "step2": [os.path.join(PKG, "csrc", n) for n in ("step2.hip", "step2.h", "step.h", "internal.h")],
 }
 
 
 def kernel_source_sha(which="step"):
-    """SHA-256 over the device sources of the step ("step") or batched
-    ("batch") kernels."""
+    """SHA-256 over the device sources of the single-step ("step"), two-step
+    ("step2") or batched ("batch") kernels."""
     h = hashlib.sha256()
     for path in KERNEL_SOURCES[which]:
         with open(path, "rb") as f:
