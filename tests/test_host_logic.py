@@ -140,6 +140,12 @@ def test_committed_traffic_record_matches_the_kernel_sources():
     rec = json.load(open(os.path.join(ROOT, "profiles", "step_f32_4096_traffic.json")))
     assert rec["kernel_source_sha256"] == profiling.kernel_source_sha()
     assert bench.measured_traffic(rec["kernel"], 4096) == rec["traffic_bytes_per_launch"]
+    # the two-step kernel (the benchmark's headline shape) has its own record
+    rec2 = json.load(open(os.path.join(ROOT, "profiles", "step2_f32_4096_traffic.json")))
+    assert rec2["kernel_sources"] == "step2" and rec2["kernel_source_sha256"] == profiling.kernel_source_sha("step2")
+    assert rec2["kernel"] == "lbm::step2_vstack_kernel<float,false,2,16,true>"
+    assert bench.measured_traffic(rec2["kernel"], 4096) == rec2["traffic_bytes_per_launch"]
+    assert 1.0 < rec2["traffic_over_algorithmic"] < 1.5
 
 
 def test_slot_arena_ranges(tmp_path):
