@@ -199,10 +199,10 @@ size_t lbm_footprint_bytes(int nx, int ny, int dtype);
  * each owning its own column strip of 64 * vx sites and marching h >= 1
  * rows. Vertical-stack form (LBM_TILE_VSTACK): nw = 4, 8 or 16 waves per
  * workgroup covering one strip and nw - 2 rows (h is ignored). Default:
- * the two-step form below with vx = 2 and nw = 16 for LBM_F64 (plain
- * stores), LBM_F32 and LBM_F32S (non-temporal stores); for LBM_F16S the
- * vertical stack with vx = 4, nw = 8 and non-temporal stores. Results do
- * not depend on the shape (bitwise). LBM_EINVAL for an unsupported shape, for
+ * the two-step form below with nw = 16 and non-temporal stores, vx = 1 for
+ * LBM_F64 and vx = 2 for LBM_F32 and LBM_F32S; for LBM_F16S the vertical
+ * stack with vx = 4, nw = 8 and non-temporal stores. Results do not depend
+ * on the shape (bitwise). LBM_EINVAL for an unsupported shape, for
  * a march-form shape (no LBM_TILE_VSTACK) while the lattice has a c2 field,
  * or for a shape whose grid would exceed one dispatch (2^32 work items) on
  * this lattice (only small shapes on the largest lattices).
@@ -210,7 +210,7 @@ size_t lbm_footprint_bytes(int nx, int ny, int dtype);
  * LBM_TILE_NT_STORE; LBM_F64, LBM_F32 and LBM_F32S): one launch takes two
  * steps of Eq. 5, keeping the first step's results in on-chip memory, so
  * each site is loaded and stored once per two steps. vx = 1 or 2, nw = 12
- * or 16 waves; a workgroup writes nw - 6 rows and (64 - 2 ceil(2 / vx)) vx
+ * or 16 waves; a workgroup writes nw - 6 rows and (64 - 2 ceil(3 / vx)) vx
  * columns. lbm_step takes the steps in pairs; a lone last step, and every
  * step while inlet/outlet boundaries are set, use the single-step vertical
  * stack (vx = 2, nw = 8, non-temporal stores). The

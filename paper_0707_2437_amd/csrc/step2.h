@@ -5,13 +5,15 @@
 namespace lbm {
 
 // A two-step tile advances a block of sites by two steps of Eq. 5 in one
-// pass over memory. The second step at a site needs the first step's
-// results at the sites up to two columns away (its gather and the densities
-// of its x-neighbours), and those need the stored values up to one more
-// column away, which each lane's window already loads. So a strip of 64
-// lanes writes the columns of its inner lanes and leaves ceil(2 / vx) lanes
-// at each side to supply only the first step.
-constexpr int step2_halo_lanes(int vx) { return (2 + vx - 1) / vx; }
+// pass over memory. Each lane gathers its own vx columns and takes its
+// x-neighbours' densities from its neighbour lanes, so the first step has
+// no result at the outermost column on either side of a 64-lane strip. The
+// second step at a column needs first-step results up to two columns away
+// (its gather and its neighbours' densities), so a strip writes the columns
+// from the fourth to the fourth last: ceil(3 / vx) lanes at each side only
+// supply the first step. (For vx = 2, a strip writes 120 columns, which
+// also keeps the strips' boundaries on 32-byte sectors of FP32 rows.)
+constexpr int step2_halo_lanes(int vx) { return (3 + vx - 1) / vx; }
 constexpr int step2_cols(int vx) { return (64 - 2 * step2_halo_lanes(vx)) * vx; }
 // Vertically the second step's density gradient needs its gathers one row
 // above and below, those need first-step results one more row out, and

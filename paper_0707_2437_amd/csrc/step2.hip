@@ -13,14 +13,18 @@
 // step2_halo_lanes(VX) (step2.h). Rows and columns outside the lattice are
 // periodic images (Sec. 4), gathered from the wrapped positions. Phases,
 // separated by workgroup barriers:
-//   1. the waves gather their rows from memory (Eq. 5, left-hand side) and
-//      publish the densities of their columns in LDS;
+//   1. the waves gather their rows' own columns from memory (Eq. 5,
+//      left-hand side: plane i from column x - e_ix of row y - e_iy) and
+//      publish the densities in LDS, one row per wave;
 //   2. waves 1 .. NW-2 relax (first step) into LDS, rounded to the storage
-//      type: the values a single step would store;
+//      type: the values a single step would store; the density gradient
+//      takes the x-neighbours from the wave's own LDS row and the
+//      y-neighbours from the rows above and below;
 //   3. waves 2 .. NW-3 gather from those and publish the new densities;
 //   4. waves 3 .. NW-4, inner lanes only, relax (second step) and write.
-// Every site's arithmetic is the single-step code of step.h (VTileF) on the
-// same inputs, so a two-step pass gives the bits of two single steps.
+// Every site's arithmetic is the single-step code of step.h (the same drho
+// and collide functions, on the same inputs), so a two-step pass gives the
+// bits of two single steps.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -35,23 +39,27 @@ __device__ __forceinline__ int wrap_mod(int v, int n)
     return r < 0 ? r + n : r;
 }
 
-// Window gather (the columns of window_loads in step.h) for a lane whose
-// window may reach past a lattice edge: every element loaded on its own
-// from its source column taken mod nx. r is a row in [0, ny).
-template <class T, int NV>
-__device__ __forceinline__ void gather_wrapped(const char* const (&pb)[9], const Geom& g, int r, int x,
-                                               Pack<T, NV> (&v)[9])
+// Own-column gather of a lane whose sources may wrap: f_i at column x + j
+// is S_i at column x + j - e_ix, taken mod nx; rb are the source rows of
+// the nine planes (row_bases in step.h). The columns are x - 1 + k with
+// k = j + 1 - e_ix in [0, VX + 1]: one remainder per lane, x0 = (x - 1) mod
+// nx, then x0 + k <= nx + VX < 3 nx, so at most two subtractions of nx.
+template <class T, int VX>
+__device__ __forceinline__ void gather_own_wrapped(const char* const (&rb)[9], const Geom& g, int x,
+                                                   T (&v)[9][VX])
 {
     constexpr int ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    static_assert(VX <= 5, "two subtractions of nx suffice for nx >= 3");
     constexpr unsigned es = sizeof(T);
-    const char* rb[9];
-    row_bases<T>(pb, g, r, rb);
+    const int x0 = wrap_mod(x - 1, g.nx);
 #pragma unroll
     for (int i = 0; i < 9; ++i)
 #pragma unroll
-        for (int j = 0; j < NV; ++j) {
-            const int s = wrap_mod(x + j - 1 - ex[i], g.nx);
-            v[i].v[j] = ld_g<T>(rb[i] + (size_t)((unsigned)(s + 2) * es));
+        for (int j = 0; j < VX; ++j) {
+            int s = x0 + (j + 1 - ex[i]);
+            s = s >= g.nx ? s - g.nx : s;
+            s = s >= g.nx ? s - g.nx : s;
+            v[i][j] = ld_g<T>(rb[i] + (size_t)((unsigned)(s + 2) * es));
         }
 }
 
@@ -59,16 +67,17 @@ template <class T, bool SHIFT, int VX, int NW, bool NTS>
 __global__ __launch_bounds__(64 * NW) void step2_vstack_kernel(StepTile a, int ntiles)
 {
     using C = typename CompT<T>::type;
+    using K = KeepT<T, C>;
     constexpr bool RC = ModelCentred<C>::value;
-    using V = VTileF<T, SHIFT, VX, NW, NTS, false, RC>;
     constexpr int HL = step2_halo_lanes(VX);
     constexpr int W2 = step2_cols(VX);
     constexpr int R2 = step2_rows(NW);
     static_assert(R2 >= 1, "a two-step tile needs at least 7 waves");
-    constexpr int LW = 64 * VX + 4;  // an LDS plane row: the lanes' columns and two more on each side
+    constexpr int LW = 64 * VX + 2;  // an LDS row: the lanes' columns and one more on each side
     constexpr int ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
     constexpr int ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
-    __shared__ C rho[NW][64 * VX];   // densities of the lanes' columns, one row per wave
+    constexpr unsigned es = sizeof(T);
+    __shared__ C rho[NW][LW];        // densities, one row per wave
     __shared__ T fs[NW - 2][9][LW];  // first-step results of waves 1 .. NW - 2
 
     const int t = xcd_tile(blockIdx.x, gridDim.x, a.xcd_chunk);
@@ -82,65 +91,95 @@ __global__ __launch_bounds__(64 * NW) void step2_vstack_kernel(StepTile a, int n
     const int y = y0 - 3 + wave;
     const int xs = strip * W2;
     const int x = xs + (lane - HL) * VX;
-    // The windows of the whole strip (columns x - 2 .. x + VX + 1 of every
-    // lane) lie inside the lattice, or some elements wrap.
-    const bool edge = xs - HL * VX - 2 < 0 || xs + (64 - HL) * VX + 2 > g.nx;
+    // sources of the strip: columns x - 1 .. x + VX of every lane
+    const bool edge = xs - HL * VX - 1 < 0 || xs + (64 - HL) * VX + 1 > g.nx;
     const CoefC<C> k = coef_c<C>(a.c);
     const Centre<C> cn = centre_c<C, RC>(a.c);
-    const int col = lane * VX + 2;  // LDS column of the lane's first column
+    const int col = lane * VX + 1;  // LDS column of the lane's first column
 
-    V v;
-    v.af = {};
-    // 1. Gather from memory; waves past the last row the group needs idle.
+    K d[9][VX];
+    C w[VX];
+    // densities and x differences of the lane's columns from a row of LDS
+    auto relax = [&](const C* rrow, const C* rup, const C* rdn, C (&o)[VX][9]) {
+#pragma unroll
+        for (int j = 0; j < VX; ++j) {
+            const C left = j == 0 ? rrow[col - 1] : w[j - 1];
+            const C right = j == VX - 1 ? rrow[col + VX] : w[j + 1];
+            // undivided central differences at time t (Sec. 4)
+            const C gx = right - left;
+            const C gy = rup[col + j] - rdn[col + j];
+            collide<T, SHIFT, C, VX, RC>(d, j, w[j], gx, gy, k, cn, o[j]);
+        }
+    };
+    // 1. Gather the own columns from memory; waves past the last row the group needs idle.
     if (wave <= nrows + 5) {
         const char* sb[9];
         src_bases<T>(a.src, g, sb);
-        const int yw = wrap_mod(y, g.ny);
-        if (edge) gather_wrapped<T, VX + 2>(sb, g, yw, x, v.raw);
-        else gather_raw<T, VX + 2, T, VX + 2, false>(sb, g, yw, x, v.raw);
-        v.land_regs(a);
+        const char* rb[9];
+        row_bases<T>(sb, g, wrap_mod(y, g.ny), rb);
+        T raw[9][VX];
+        if (edge) {
+            gather_own_wrapped<T, VX>(rb, g, x, raw);
+        } else {
+            constexpr int A = es < 4 ? (int)es : 4;
 #pragma unroll
-        for (int j = 0; j < VX; ++j) rho[wave][lane * VX + j] = v.w[j + 1];
+            for (int i = 0; i < 9; ++i) {
+                const Pack<T, VX> p = ld_vec<T, VX, A>(rb[i], (unsigned)(x - ex[i] + 2) * es);
+#pragma unroll
+                for (int j = 0; j < VX; ++j) raw[i][j] = p.v[j];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+#pragma unroll
+            for (int j = 0; j < VX; ++j) d[i][j] = keep_of<T, SHIFT, C>(raw[i][j], i, cn);
+#pragma unroll
+        for (int j = 0; j < VX; ++j) {
+            w[j] = drho_of<T, SHIFT, C, VX>(d, j, cn);
+            rho[wave][col + j] = w[j];
+        }
     }
     __syncthreads();
     // 2. First step, every lane, into LDS.
     if (wave >= 1 && wave <= min(nrows + 4, NW - 2)) {
+        C o[VX][9];
+        relax(rho[wave], rho[wave + 1], rho[wave - 1], o);
 #pragma unroll
-        for (int j = 0; j < VX; ++j) {
-            // undivided central differences at time t (Sec. 4)
-            const C gx = v.w[j + 2] - v.w[j];
-            const C gy = rho[wave + 1][lane * VX + j] - rho[wave - 1][lane * VX + j];
-            C o[9];
-            collide<T, SHIFT, C, VX, RC>(v.d, j, v.w[j + 1], gx, gy, k, cn, o);
+        for (int j = 0; j < VX; ++j)
 #pragma unroll
-            for (int i = 0; i < 9; ++i) fs[wave - 1][i][col + j] = from_d<T, SHIFT, C>(o[i], i, cn);
-        }
+            for (int i = 0; i < 9; ++i) fs[wave - 1][i][col + j] = from_d<T, SHIFT, C>(o[j][i], i, cn);
     }
     __syncthreads();
     // 3. Second gather, from LDS: f_i at column c of row y is the first
-    // step's S_i at column c - e_ix of row y - e_iy. The halo lanes read two
-    // LDS columns that nothing wrote; their results are never written.
+    // step's S_i at column c - e_ix of row y - e_iy. Lanes next to the strip
+    // edge read LDS columns that nothing wrote; their results are never written.
     const bool act3 = wave >= 2 && wave <= min(nrows + 3, NW - 3);
     if (act3) {
 #pragma unroll
         for (int i = 0; i < 9; ++i)
 #pragma unroll
-            for (int j = 0; j < VX + 2; ++j) v.raw[i].v[j] = fs[wave - ey[i] - 1][i][col - 1 + j - ex[i]];
-        v.land_regs(a);
+            for (int j = 0; j < VX; ++j) d[i][j] = keep_of<T, SHIFT, C>(fs[wave - ey[i] - 1][i][col + j - ex[i]], i, cn);
 #pragma unroll
-        for (int j = 0; j < VX; ++j) rho[wave][lane * VX + j] = v.w[j + 1];
+        for (int j = 0; j < VX; ++j) {
+            w[j] = drho_of<T, SHIFT, C, VX>(d, j, cn);
+            rho[wave][col + j] = w[j];
+        }
     }
     __syncthreads();
     // 4. Second step: the group's rows, inner lanes, columns inside the lattice.
-    VRow r;
-    r.wave = wave;
-    r.lane = lane;
-    r.y = y;
-    r.x = x;
-    r.nv = min(VX, g.nx - x);
-    r.load = act3;
-    r.relax = wave >= 3 && wave <= nrows + 2 && lane >= HL && lane < 64 - HL && r.nv > 0;
-    v.relax_g(a, a.dst, r, [&](int j) { return rho[wave + 1][lane * VX + j] - rho[wave - 1][lane * VX + j]; });
+    const int nv = min(VX, g.nx - x);
+    if (wave >= 3 && wave <= nrows + 2 && lane >= HL && lane < 64 - HL && nv > 0) {
+        C o[VX][9];
+        relax(rho[wave], rho[wave + 1], rho[wave - 1], o);
+        Pack<T, VX> out[9];
+#pragma unroll
+        for (int j = 0; j < VX; ++j)
+#pragma unroll
+            for (int i = 0; i < 9; ++i) out[i].v[j] = from_d<T, SHIFT, C>(o[j][i], i, cn);
+        char* dbase[9];
+        dst_bases<T>(a.dst, g, dbase);
+        write_row<T, VX, NTS>(dbase, g, y, x, nv, out);
+    }
 }
 
 template <class T, bool SHIFT, int VX, int NW>

@@ -33,7 +33,7 @@ def test_bench_form_names_and_bytes():
     assert bench.form_bytes_per_site("f16s") == 36 and bench.form_bytes_per_site("f32_eq") == 72
     assert bench.form_bytes_per_site("f32_field") == 76 and bench.form_bytes_per_site("f64_field") == 152
     assert bench.kernel_name((2, 16, 8, 50), "f32") == "lbm::step2_vstack_kernel<float,false,2,16,true>"
-    assert bench.kernel_name((2, 16, 8, 48), "f64") == "lbm::step2_vstack_kernel<double,false,2,16,false>"
+    assert bench.kernel_name((1, 16, 8, 50), "f64") == "lbm::step2_vstack_kernel<double,false,1,16,true>"
     assert bench.launches_of((2, 16, 8, 50), 1000) == 500 and bench.launches_of((2, 16, 8, 50), 7) == 4
     assert bench.launches_of((2, 8, 8, 18), 1000) == 1000
     assert bench.kernel_name((2, 8, 8, 18), "f32_field") == "lbm::step_vstack_kernel<float,false,2,8,true,true>"
