@@ -132,7 +132,8 @@ def kernel_name(tile, form):
     dtype, variant = form_parts(form)
     t = {"f64": "double,false", "f32": "float,false", "f32s": "float,true", "f16s": "_Float16,true"}[dtype]
     if flags & TWO_STEP:
-        return f"lbm::step2_vstack_kernel<{t},{vx},{nw},{'true' if flags & 2 else 'false'}>"
+        return (f"lbm::step2_vstack_kernel<{t},{vx},{nw},{'true' if flags & 2 else 'false'},"
+                f"{'true' if variant == 'field' else 'false'}>")
     if flags & 16:
         return (f"lbm::step_vstack_kernel<{t},{vx},{nw},{'true' if flags & 2 else 'false'},"
                 f"{'true' if variant == 'field' else 'false'}>")

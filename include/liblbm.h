@@ -214,9 +214,7 @@ size_t lbm_footprint_bytes(int nx, int ny, int dtype);
  * columns. lbm_step takes the steps in pairs; a lone last step, and every
  * step while inlet/outlet boundaries are set, use the single-step vertical
  * stack (vx = 2, nw = 8, non-temporal stores). The
- * results are those of single steps, bit for bit. LBM_EINVAL while the
- * lattice has a c2 field; setting a c2 field replaces it by that
- * single-step shape.
+ * results are those of single steps, bit for bit (c2 fields included).
  * lbm_get_tile: any pointer may be NULL. */
 enum lbm_tile_flags {
     LBM_TILE_PREFETCH = 1, /* issue the next row's loads before relaxing the current row */

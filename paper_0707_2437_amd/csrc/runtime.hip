@@ -43,7 +43,7 @@ thread_local int g_last_error = LBM_OK;
 // Defaults from repeated tile sweeps on MI355X at 4096^2 and 8192^2
 // (row-interleaved layout). Single-step shapes: the vertical-stack form for
 // every dtype; they also take the steps a two-step shape cannot (a lone last
-// step, inlet/outlet boundaries, c2 fields).
+// step, inlet/outlet boundaries).
 struct TileDefault {
     int vx, nw, h, flags;
 };
@@ -126,12 +126,12 @@ StepTile make_tile(const lbm_lattice* L)
     return t;
 }
 
-// A lattice with a c2 field steps with the single-step vertical-stack
-// kernels only: another tile is replaced by the dtype's default.
+// A lattice with a c2 field steps with the vertical-stack kernels (single-
+// or two-step) only: a march-form tile is replaced by the dtype's default.
 void field_tile(lbm_lattice* L)
 {
-    if ((L->kflags & LBM_TILE_VSTACK) && !(L->kflags & LBM_TILE_TWO_STEP)) return;
-    const TileDefault td = default_single_tile(L->dtype);
+    if (L->kflags & LBM_TILE_VSTACK) return;
+    const TileDefault td = default_tile(L->dtype);
     L->vx = td.vx;
     L->nw = td.nw;
     L->h = td.h;
@@ -272,7 +272,6 @@ int lbm_set_tile(lbm_lattice* L, int vx, int nw, int h, int flags)
 {
     if (!L || !tile_supported(L->dtype, vx, nw, flags)) return LBM_EINVAL;
     if (!(flags & LBM_TILE_VSTACK) && (h < 1 || L->field)) return LBM_EINVAL;
-    if ((flags & LBM_TILE_TWO_STEP) && L->field) return LBM_EINVAL;
     {
         // the shape's grid must fit one dispatch for this lattice
         lbm_lattice tmp = *L;
@@ -301,11 +300,9 @@ int lbm_autotune(lbm_lattice* L, int reps, int use_cache)
     TileCand c{};
     if (use_cache && tune_cache_get(key, &c)) return lbm_set_tile(L, c.vx, c.nw, c.h, c.flags);
     std::vector<TileCand> cands = lattice_candidates(L->dtype);
-    if (L->field)  // the single-step vertical-stack kernels only
+    if (L->field)  // the vertical-stack kernels only
         cands.erase(std::remove_if(cands.begin(), cands.end(),
-                                   [](const TileCand& k) {
-                                       return !(k.flags & LBM_TILE_VSTACK) || (k.flags & LBM_TILE_TWO_STEP);
-                                   }),
+                                   [](const TileCand& k) { return !(k.flags & LBM_TILE_VSTACK); }),
                     cands.end());
     // Each candidate is timed over two steps (two single-step launches or
     // one two-step launch), reading cur and writing nxt with no swap: the

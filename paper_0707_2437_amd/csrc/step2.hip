@@ -63,7 +63,31 @@ __device__ __forceinline__ void gather_own_wrapped(const char* const (&rb)[9], c
         }
 }
 
-template <class T, bool SHIFT, int VX, int NW, bool NTS>
+// The per-site source coefficients (a c2 field, array of row pitch
+// a.fpitch in compute precision) of the lane's columns of row r in
+// [0, ny); columns outside the lattice are taken mod nx as in
+// gather_own_wrapped. The field does not change with time, so one load
+// serves both steps.
+template <class C, int VX>
+__device__ __forceinline__ void field_own(const StepTile& a, int r, int x, bool edge, C (&af)[VX])
+{
+    const char* row = (const char*)a.field + (size_t)r * a.fpitch * sizeof(C);
+    if (edge) {
+        const int x0 = wrap_mod(x, a.g.nx);
+#pragma unroll
+        for (int j = 0; j < VX; ++j) {
+            const int s = x0 + j >= a.g.nx ? x0 + j - a.g.nx : x0 + j;
+            af[j] = ld_g<C>(row + (size_t)((unsigned)s * sizeof(C)));
+        }
+    } else {
+        const Pack<C, VX> p = ld_vec<C, VX, 4>(row, (unsigned)x * (unsigned)sizeof(C));
+#pragma unroll
+        for (int j = 0; j < VX; ++j) af[j] = p.v[j];
+    }
+}
+
+// FIELD: a lattice with a c2 field (per-site source coefficients).
+template <class T, bool SHIFT, int VX, int NW, bool NTS, bool FIELD>
 __global__ __launch_bounds__(64 * NW) void step2_vstack_kernel(StepTile a, int ntiles)
 {
     using C = typename CompT<T>::type;
@@ -99,6 +123,7 @@ __global__ __launch_bounds__(64 * NW) void step2_vstack_kernel(StepTile a, int n
 
     K d[9][VX];
     C w[VX];
+    C af[VX] = {};  // per-site source coefficients (FIELD)
     // densities and x differences of the lane's columns from a row of LDS
     auto relax = [&](const C* rrow, const C* rup, const C* rdn, C (&o)[VX][9]) {
 #pragma unroll
@@ -108,7 +133,7 @@ __global__ __launch_bounds__(64 * NW) void step2_vstack_kernel(StepTile a, int n
             // undivided central differences at time t (Sec. 4)
             const C gx = right - left;
             const C gy = rup[col + j] - rdn[col + j];
-            collide<T, SHIFT, C, VX, RC>(d, j, w[j], gx, gy, k, cn, o[j]);
+            collide<T, SHIFT, C, VX, RC>(d, j, w[j], gx, gy, site_coef<FIELD>(k, af[j]), cn, o[j]);
         }
     };
     // 1. Gather the own columns from memory; waves past the last row the group needs idle.
@@ -116,7 +141,10 @@ __global__ __launch_bounds__(64 * NW) void step2_vstack_kernel(StepTile a, int n
         const char* sb[9];
         src_bases<T>(a.src, g, sb);
         const char* rb[9];
-        row_bases<T>(sb, g, wrap_mod(y, g.ny), rb);
+        const int yw = wrap_mod(y, g.ny);
+        row_bases<T>(sb, g, yw, rb);
+        if constexpr (FIELD)
+            if (wave >= 1 && wave <= nrows + 4) field_own<C, VX>(a, yw, x, edge, af);
         T raw[9][VX];
         if (edge) {
             gather_own_wrapped<T, VX>(rb, g, x, raw);
@@ -190,8 +218,13 @@ static hipError_t launch2_t(bool nts, const StepTile& t, hipStream_t st)
     const int grid = (ntiles + q - 1) / q * q;
     if (!grid_fits(grid, 64 * NW)) return hipErrorInvalidConfiguration;
     const dim3 gd(grid), bd(64 * NW);
-    if (nts) hipLaunchKernelGGL((step2_vstack_kernel<T, SHIFT, VX, NW, true>), gd, bd, 0, st, t, ntiles);
-    else hipLaunchKernelGGL((step2_vstack_kernel<T, SHIFT, VX, NW, false>), gd, bd, 0, st, t, ntiles);
+    if (t.field) {
+        if (nts) hipLaunchKernelGGL((step2_vstack_kernel<T, SHIFT, VX, NW, true, true>), gd, bd, 0, st, t, ntiles);
+        else hipLaunchKernelGGL((step2_vstack_kernel<T, SHIFT, VX, NW, false, true>), gd, bd, 0, st, t, ntiles);
+    } else {
+        if (nts) hipLaunchKernelGGL((step2_vstack_kernel<T, SHIFT, VX, NW, true, false>), gd, bd, 0, st, t, ntiles);
+        else hipLaunchKernelGGL((step2_vstack_kernel<T, SHIFT, VX, NW, false, false>), gd, bd, 0, st, t, ntiles);
+    }
     return hipGetLastError();
 }
 
@@ -224,7 +257,7 @@ bool step2_shape_supported(int dtype, int vx, int nw)
 // flags: LBM_TILE_NT_STORE (2) selects non-temporal stores.
 hipError_t launch_step2(int dtype, int vx, int nw, int flags, const StepTile& t, hipStream_t st)
 {
-    if (!step2_shape_supported(dtype, vx, nw) || t.field) return hipErrorInvalidValue;
+    if (!step2_shape_supported(dtype, vx, nw)) return hipErrorInvalidValue;
     const bool nts = (flags & 2) != 0;
     switch (dtype) {
     case 0: return launch2_vx<double, false>(vx, nw, nts, t, st);

@@ -81,7 +81,7 @@ def test_two_step_full_size_bitwise(dtype):
         del got
 
 
-def test_two_step_with_inlet_outlet_and_field():
+def test_two_step_with_inlet_outlet():
     nx, ny = 160, 40
     fields = smooth_random_state(nx, ny, seed=9)
     with lbm.Lattice(nx, ny, 0.7, 0.3, "f32") as L:
@@ -92,12 +92,7 @@ def test_two_step_with_inlet_outlet_and_field():
         L.set_x_boundaries(lbm.XBC_INLET_OUTLET, 0.01, 50.0)
         ref = L.init(*fields).step(9).get_f()
     assert np.array_equal(got, ref)
-    with lbm.Lattice(nx, ny, 0.7, 0.3, "f32") as L:
-        L.set_tile(2, 16, 0, VSTACK | TWO_STEP)
-        L.set_c2_field(np.full((ny, nx), 0.3))
-        assert L.get_tile()[3] & TWO_STEP == 0  # a c2 field takes the single-step default
-        with pytest.raises(lbm.LBMError):
-            L.set_tile(2, 16, 0, VSTACK | TWO_STEP)
+
 
 
 def test_two_step_shape_errors():
@@ -109,3 +104,32 @@ def test_two_step_shape_errors():
     with lbm.Lattice(64, 64, 0.7, 0.3, "f16s") as L:
         with pytest.raises(lbm.LBMError):
             L.set_tile(2, 16, 0, VSTACK | TWO_STEP)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "f32s"])
+@pytest.mark.parametrize("nx,ny", [(3, 3), (7, 5), (130, 77), (300, 41)])
+def test_two_step_c2_field_bitwise(dtype, nx, ny):
+    """A c2 field varying in x and y (per-site source coefficients, read once
+    per two-step launch for both steps) gives the bits of single steps."""
+    fields = smooth_random_state(nx, ny, seed=nx + 7 * ny)
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    c2 = 0.2 + 0.15 * np.sin(2 * np.pi * xx / nx) * np.cos(2 * np.pi * yy / ny) + 0.001 * xx / nx
+
+    def go(tile):
+        with lbm.Lattice(nx, ny, 0.7, 0.3, dtype) as L:
+            L.set_c2_field(c2)
+            if tile:
+                L.set_tile(*tile)
+            return L.init(*fields).step(7).get_f()
+
+    ref = go((2, 8, 0, VSTACK | NT))
+    for vx, nw, f in SHAPES:
+        assert np.array_equal(go((vx, nw, 0, f)), ref), (dtype, nx, ny, vx, nw, f)
+    assert np.array_equal(go(None), ref)  # the default shape (two-step)
+
+
+def test_march_shape_with_field_takes_the_default():
+    with lbm.Lattice(64, 64, 0.7, 0.3, "f32") as L:
+        L.set_tile(1, 1, 4, 0)
+        L.set_c2_field(np.full((64, 64), 0.3))
+        assert L.get_tile()[3] & (VSTACK | TWO_STEP) == VSTACK | TWO_STEP

@@ -32,8 +32,9 @@ def test_bench_form_names_and_bytes():
     assert bench.form_bytes_per_site("f32") == 72 and bench.form_bytes_per_site("f64") == 144
     assert bench.form_bytes_per_site("f16s") == 36 and bench.form_bytes_per_site("f32_eq") == 72
     assert bench.form_bytes_per_site("f32_field") == 76 and bench.form_bytes_per_site("f64_field") == 152
-    assert bench.kernel_name((2, 16, 8, 50), "f32") == "lbm::step2_vstack_kernel<float,false,2,16,true>"
-    assert bench.kernel_name((1, 16, 8, 50), "f64") == "lbm::step2_vstack_kernel<double,false,1,16,true>"
+    assert bench.kernel_name((2, 16, 8, 50), "f32") == "lbm::step2_vstack_kernel<float,false,2,16,true,false>"
+    assert bench.kernel_name((1, 16, 8, 50), "f64") == "lbm::step2_vstack_kernel<double,false,1,16,true,false>"
+    assert bench.kernel_name((2, 16, 8, 50), "f32_field") == "lbm::step2_vstack_kernel<float,false,2,16,true,true>"
     assert bench.launches_of((2, 16, 8, 50), 1000) == 500 and bench.launches_of((2, 16, 8, 50), 7) == 4
     assert bench.launches_of((2, 8, 8, 18), 1000) == 1000
     assert bench.kernel_name((2, 8, 8, 18), "f32_field") == "lbm::step_vstack_kernel<float,false,2,8,true,true>"
@@ -143,7 +144,7 @@ def test_committed_traffic_record_matches_the_kernel_sources():
     # the two-step kernel (the benchmark's headline shape) has its own record
     rec2 = json.load(open(os.path.join(ROOT, "profiles", "step2_f32_4096_traffic.json")))
     assert rec2["kernel_sources"] == "step2" and rec2["kernel_source_sha256"] == profiling.kernel_source_sha("step2")
-    assert rec2["kernel"] == "lbm::step2_vstack_kernel<float,false,2,16,true>"
+    assert rec2["kernel"] == "lbm::step2_vstack_kernel<float,false,2,16,true,false>"
     assert bench.measured_traffic(rec2["kernel"], 4096) == rec2["traffic_bytes_per_launch"]
     assert 1.0 < rec2["traffic_over_algorithmic"] < 1.5
 
