@@ -304,11 +304,13 @@ def measure_batched(lbm, workloads, torch, nlat, steps, mode, warmup=5, persiste
         e1.record(stream)
         torch.cuda.synchronize()
         P.sync()
-        pers = sites * persistent_steps / (e0.elapsed_time(e1) / 1e3) / 1e6
+        pers = sites * persistent_steps / (e0.elapsed_time(e1) / 1e3) / 1e6  # single steps (72 B per update)
         pers_members = P.persistent_members()
     P.close()
-    # plain kernel, one launch per lattice per step (same lattices, fewer steps)
-    psteps = max(1, steps // 10)
+    # plain kernel, the lattices one at a time, two steps per call (the
+    # single-lattice default shape: one two-step launch per lattice per two
+    # steps; same lattices, fewer steps)
+    psteps = max(2, steps // 10) // 2 * 2
     lats = []
     for sp in specs:
         L = lbm.Lattice(sp["nx"], sp["ny"], sp["tau"], sp["c2"], "f32")
@@ -319,9 +321,9 @@ def measure_batched(lbm, workloads, torch, nlat, steps, mode, warmup=5, persiste
         L.step(warmup)
     torch.cuda.synchronize()
     e0.record(stream)
-    for _ in range(psteps):
+    for _ in range(psteps // 2):
         for L in lats:
-            L.step(1)
+            L.step(2)
     e1.record(stream)
     torch.cuda.synchronize()
     psec = e0.elapsed_time(e1) / 1e3
@@ -329,7 +331,10 @@ def measure_batched(lbm, workloads, torch, nlat, steps, mode, warmup=5, persiste
         L.close()
     mlups = sites * steps / sec / 1e6
     plain = sites * psteps / psec / 1e6
-    return {"mlups": mlups, "frac": mlups * 1e6 * BYTES_PER_SITE["f32"] / 1e9 / PEAK_HBM_GBS,
+    # algorithmic bytes per site update: one load and one store per launch,
+    # a two-step launch covering two updates
+    per_update = BYTES_PER_SITE["f32"] / (2 if tile[2] & TWO_STEP else 1)
+    return {"mlups": mlups, "frac": mlups * 1e6 * per_update / 1e9 / PEAK_HBM_GBS,
             "lattices": nlat, "sites": sites, "steps": steps, "mode": mode, "tile": list(tile),
             "seconds": sec, "plain_mlups": plain, "vs_plain": mlups / plain, "nonfinite_lattices": nonfinite,
             "persistent_mlups": pers, "persistent_tile": None if pers_tile is None else list(pers_tile),

@@ -19,6 +19,12 @@ bool step_shape_supported(int dtype, int vx, int nw, int flags);
 // step2_cols / step2_rows.
 hipError_t launch_step2(int dtype, int vx, int nw, int flags, const StepTile& t, hipStream_t st);
 bool step2_shape_supported(int dtype, int vx, int nw);
+// Pass p (steps 2p, 2p + 1) of a batch in two-step tiles (step2.hip): the
+// descriptors' t0 is each lattice's buffer time (its state is in buffer
+// (t0 + p) & 1 at the start of pass p); a lattice with nsteps = 2p + 1
+// takes one step, one with nsteps <= 2p none.
+hipError_t launch_batch2(int dtype, int vx, int nw, bool nts, const BatchLat* lats, const int* item_lat, int nitems,
+                         int p, int ch, hipStream_t st);
 hipError_t launch_init(int dtype, void* s, const Geom& g, const double* rho, const double* ux, const double* uy,
                        double eqs, hipStream_t st);
 hipError_t launch_xbc(int dtype, void* s, const Geom& g, double rho_in, double eqs, hipStream_t st);

@@ -27,10 +27,14 @@ struct Slot {
     size_t bytes = 0;  // buffers + moments scratch
     size_t span = 0;   // arena bytes held (bytes rounded up)
     void* buf = nullptr;
-    void* b0 = nullptr;  // state at even times
-    void* b1 = nullptr;  // state at odd times
+    void* b0 = nullptr;  // state at even buffer times
+    void* b1 = nullptr;  // state at odd buffer times
     double* red = nullptr;
     long long t = 0;
+    // Buffer phase: the state at time t is in buffer (t + ph) & 1. Single
+    // steps keep it; a two-step pass (one read and one write for two steps)
+    // flips it.
+    int ph = 0;
 };
 
 // Chunks of slot memory come from hipMalloc (see arena.h).
@@ -44,7 +48,7 @@ struct DeviceAlloc {
 using SlotArena = lbm::Arena<DeviceAlloc>;
 
 struct GraphEntry {
-    int nsteps_max = 0, nitems = 0, vx = 0, nw = 0, nts = 0, ch = 0;
+    int nsteps_max = 0, nitems = 0, vx = 0, nw = 0, nts = 0, ch = 0, two = 0;
     const BatchLat* lats = nullptr;
     const int* items = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -98,6 +102,7 @@ struct lbm_pool {
     SlotArena arena;              // device memory of the slots
     hipStream_t own = nullptr, stream = nullptr;
     int vx = 2, nw = 16, nts = 1; // vertical-stack tile of the batched kernels
+    int two = 0;                  // two steps per launch (two-step tiles; grouped and graph modes)
     int mode = LBM_POOL_GROUPED;
     int max_grid = 0;             // persistent mode: workgroup cap (0 = all co-resident)
     BatchLat* d_lats = nullptr;   // device descriptor array
@@ -121,7 +126,38 @@ Slot* slot_of(lbm_pool* P, int s)
     return &P->slots[s];
 }
 
-void* cur_buf(const Slot& S) { return (S.t & 1) ? S.b1 : S.b0; }
+void* cur_buf(const Slot& S) { return ((S.t + S.ph) & 1) ? S.b1 : S.b0; }
+
+// The buffer time a batch descriptor carries for slot S (see BatchLat and
+// Slot::ph).
+long long buffer_time(const Slot& S) { return S.t + S.ph; }
+
+// Advance slot S by n steps taken in two-step passes (two != 0: ceil(n / 2)
+// launches, each moving the state to the other buffer) or in single steps.
+void advance(Slot& S, int n, int two)
+{
+    if (two) S.ph = (int)((S.ph + (n + 1) / 2 + n) & 1);
+    S.t += n;
+}
+
+// The dtype's default tile of the batched kernels (from the batched
+// sweeps): with two_ok, the two-step tile where the dtype has one (16
+// waves, vx = 1 for FP64 and 2 otherwise, as for single lattices), else the
+// single-step vertical stack of 8 waves (vx = 4 for FP16, 2 otherwise);
+// non-temporal stores.
+void set_default_tile(lbm_pool* P, bool two_ok)
+{
+    P->nts = 1;
+    if (two_ok && P->dtype != LBM_F16S) {
+        P->two = 1;
+        P->nw = 16;
+        P->vx = P->dtype == LBM_F64 ? 1 : 2;
+    } else {
+        P->two = 0;
+        P->nw = 8;
+        P->vx = P->dtype == LBM_F16S ? 4 : 2;
+    }
+}
 
 void drop_graphs(lbm_pool* P)
 {
@@ -143,8 +179,9 @@ size_t slot_bytes(int nx, int ny, int dtype, Geom* g_out, size_t* red_at = nullp
 }
 
 // The descriptor of a slot for vertical-stack tiles of vx columns per lane
-// and nw waves (the shape of the launch that reads it).
-StepTile slot_tile(const Slot& S, int vx, int nw)
+// and nw waves (the shape of the launch that reads it); two: the two-step
+// tiles of step2_cols / step2_rows.
+StepTile slot_tile(const Slot& S, int vx, int nw, int two)
 {
     StepTile t{};
     t.src = S.b0;
@@ -152,7 +189,7 @@ StepTile slot_tile(const Slot& S, int vx, int nw)
     t.g = S.g;
     t.c = S.coef;
     t.h = nw - 2;
-    const int W = 64 * vx, R = nw - 2;
+    const int W = two ? step2_cols(vx) : 64 * vx, R = two ? step2_rows(nw) : nw - 2;
     t.nstrips = (S.nx + W - 1) / W;
     t.nchunks = (S.ny + R - 1) / R;
     t.rowband = 1;
@@ -218,22 +255,28 @@ hipError_t run_batch(lbm_pool* P, int nmax)
     if (P->mode == LBM_POOL_PERSISTENT)
         return launch_batch(P->dtype, P->vx, P->nw, nts, true, P->d_lats, P->d_items, nitems, nmax,
                             P->max_grid, P->xcd_chunk, P->d_bar, P->stream);
+    // launch k of the call: step k, or two-step pass k
+    const int nlaunch = P->two ? (nmax + 1) / 2 : nmax;
+    auto launch_k = [&](int k) {
+        return P->two ? launch_batch2(P->dtype, P->vx, P->nw, nts, P->d_lats, P->d_items, nitems, k, P->xcd_chunk,
+                                      P->stream)
+                      : launch_batch(P->dtype, P->vx, P->nw, nts, false, P->d_lats, P->d_items, nitems, k, 0,
+                                     P->xcd_chunk, nullptr, P->stream);
+    };
     if (P->mode == LBM_POOL_GRAPH) {
         GraphEntry* ge = nullptr;
         for (auto& g : P->graphs)
             if (g.nsteps_max == nmax && g.nitems == nitems && g.vx == P->vx && g.nw == P->nw && g.nts == P->nts &&
-                g.ch == P->xcd_chunk && g.lats == P->d_lats && g.items == P->d_items)
+                g.ch == P->xcd_chunk && g.two == P->two && g.lats == P->d_lats && g.items == P->d_items)
                 ge = &g;
         if (!ge) {
-            // Capture nmax grouped launches once; replays re-read the
+            // Capture the call's grouped launches once; replays re-read the
             // descriptors, which are refreshed above before every replay.
             hipGraph_t graph = nullptr;
             e = hipStreamBeginCapture(P->stream, hipStreamCaptureModeThreadLocal);
             if (e != hipSuccess) return e;
             hipError_t le = hipSuccess;
-            for (int s = 0; s < nmax && le == hipSuccess; ++s)
-                le = launch_batch(P->dtype, P->vx, P->nw, nts, false, P->d_lats, P->d_items, nitems, s, 0,
-                                  P->xcd_chunk, nullptr, P->stream);
+            for (int k = 0; k < nlaunch && le == hipSuccess; ++k) le = launch_k(k);
             e = hipStreamEndCapture(P->stream, &graph);
             if (le != hipSuccess) e = le;
             hipGraphExec_t exec = nullptr;
@@ -245,14 +288,12 @@ hipError_t run_batch(lbm_pool* P, int nmax)
                 P->graphs.erase(P->graphs.begin());
             }
             P->graphs.push_back(
-                GraphEntry{nmax, nitems, P->vx, P->nw, P->nts, P->xcd_chunk, P->d_lats, P->d_items, exec});
+                GraphEntry{nmax, nitems, P->vx, P->nw, P->nts, P->xcd_chunk, P->two, P->d_lats, P->d_items, exec});
             ge = &P->graphs.back();
         }
         return hipGraphLaunch(ge->exec, P->stream);
     }
-    for (int s = 0; s < nmax && e == hipSuccess; ++s)
-        e = launch_batch(P->dtype, P->vx, P->nw, nts, false, P->d_lats, P->d_items, nitems, s, 0, P->xcd_chunk,
-                         nullptr, P->stream);
+    for (int k = 0; k < nlaunch && e == hipSuccess; ++k) e = launch_k(k);
     return e;
 }
 
@@ -276,12 +317,7 @@ lbm_pool* lbm_pool_create(size_t budget_bytes, int dtype)
     P->dtype = dtype;
     P->esize = esize_of(dtype);
     P->budget = budget_bytes;
-    switch (dtype) {  // vertical-stack tiles from the batched sweeps
-    case LBM_F64: P->vx = 2; P->nw = 8; P->nts = 1; break;
-    case LBM_F32: P->vx = 2; P->nw = 8; P->nts = 1; break;
-    case LBM_F32S: P->vx = 2; P->nw = 8; P->nts = 1; break;
-    default: P->vx = 4; P->nw = 8; P->nts = 1; break;
-    }
+    set_default_tile(P, true);
     if (const char* ev = std::getenv("LBM_XCD_CHUNK")) {  // experiments: items per XCD chunk
         const int v = std::atoi(ev);
         if (v >= 0 && v <= 4096) P->xcd_chunk = v;
@@ -397,6 +433,7 @@ int lbm_pool_init(lbm_pool* P, int slot, const double* rho, const double* ux, co
     if (e == hipSuccess) e = hipStreamSynchronize(P->stream);
     if (e != hipSuccess) return status_of(e);
     S->t = 0;
+    S->ph = 0;
     S->ready = true;
     return LBM_OK;
 }
@@ -408,6 +445,7 @@ int lbm_pool_init_device(lbm_pool* P, int slot, const double* rho, const double*
     hipError_t e = launch_init(P->dtype, S->b0, S->g, rho, ux, uy, 0.0, P->stream);
     if (e != hipSuccess) return status_of(e);
     S->t = 0;
+    S->ph = 0;
     S->ready = true;
     return LBM_OK;
 }
@@ -429,8 +467,8 @@ static int build_batch(lbm_pool* P, const int* slots, const int* nsteps, int cou
             if (slots[j] == slots[k]) return LBM_EINVAL;  // a slot listed twice
         if (nsteps[k] == 0) continue;
         BatchLat b{};
-        b.tile = slot_tile(*S, P->vx, P->nw);
-        b.t0 = S->t;
+        b.tile = slot_tile(*S, P->vx, P->nw, P->two);
+        b.t0 = buffer_time(*S);
         b.nsteps = nsteps[k];
         add_lattice(P, b);
         *nmax = std::max(*nmax, nsteps[k]);
@@ -445,7 +483,7 @@ int lbm_pool_step(lbm_pool* P, const int* slots, const int* nsteps, int count)
     if (st != LBM_OK || P->h_lats.empty()) return st;
     hipError_t e = run_batch(P, nmax);
     if (e != hipSuccess) return status_of(e);
-    for (int k = 0; k < count; ++k) P->slots[slots[k]].t += nsteps[k];
+    for (int k = 0; k < count; ++k) advance(P->slots[slots[k]], nsteps[k], P->two);
     return LBM_OK;
 }
 
@@ -474,6 +512,9 @@ int lbm_pool_step_noalloc(lbm_pool* P, const int* slots, const int* nsteps, int 
         if (P->mode == LBM_POOL_PERSISTENT) {
             e = launch_batch(P->dtype, P->vx, P->nw, nts, true, d_lats, d_items, nitems, nmax, P->max_grid,
                              P->xcd_chunk, P->d_bar, P->stream);
+        } else if (P->two) {
+            for (int k = 0; k < (nmax + 1) / 2 && e == hipSuccess; ++k)
+                e = launch_batch2(P->dtype, P->vx, P->nw, nts, d_lats, d_items, nitems, k, P->xcd_chunk, P->stream);
         } else {
             for (int s = 0; s < nmax && e == hipSuccess; ++s)
                 e = launch_batch(P->dtype, P->vx, P->nw, nts, false, d_lats, d_items, nitems, s, 0, P->xcd_chunk,
@@ -481,7 +522,7 @@ int lbm_pool_step_noalloc(lbm_pool* P, const int* slots, const int* nsteps, int 
         }
     }
     if (e != hipSuccess) return status_of(e);
-    for (int k = 0; k < count; ++k) P->slots[slots[k]].t += nsteps[k];
+    for (int k = 0; k < count; ++k) advance(P->slots[slots[k]], nsteps[k], P->two);
     return LBM_OK;
 }
 
@@ -575,6 +616,12 @@ long long lbm_pool_time(const lbm_pool* P, int slot)
 int lbm_pool_set_mode(lbm_pool* P, int mode, int max_grid)
 {
     if (!P || mode < LBM_POOL_GROUPED || mode > LBM_POOL_PERSISTENT || max_grid < 0) return LBM_EINVAL;
+    if (mode == LBM_POOL_PERSISTENT && P->two) {
+        // the persistent kernel takes single steps: the dtype's single-step tile
+        hipError_t e = hipStreamSynchronize(P->stream);
+        if (e != hipSuccess) return status_of(e);
+        set_default_tile(P, false);
+    }
     P->mode = mode;
     P->max_grid = max_grid;
     return LBM_OK;
@@ -582,11 +629,20 @@ int lbm_pool_set_mode(lbm_pool* P, int mode, int max_grid)
 
 int lbm_pool_set_tile(lbm_pool* P, int vx, int nw, int flags)
 {
-    if (!P || (flags & ~LBM_TILE_NT_STORE) || !step_shape_supported(P->dtype, vx, nw, LBM_TILE_VSTACK)) return LBM_EINVAL;
+    if (!P) return LBM_EINVAL;
+    const bool two = (flags & LBM_TILE_TWO_STEP) != 0;
+    if (two) {
+        if ((flags & ~(LBM_TILE_TWO_STEP | LBM_TILE_VSTACK | LBM_TILE_NT_STORE)) ||
+            !step2_shape_supported(P->dtype, vx, nw) || P->mode == LBM_POOL_PERSISTENT)
+            return LBM_EINVAL;
+    } else if ((flags & ~LBM_TILE_NT_STORE) || !step_shape_supported(P->dtype, vx, nw, LBM_TILE_VSTACK)) {
+        return LBM_EINVAL;
+    }
     hipError_t e = hipStreamSynchronize(P->stream);
     P->vx = vx;
     P->nw = nw;
     P->nts = (flags & LBM_TILE_NT_STORE) ? 1 : 0;
+    P->two = two ? 1 : 0;
     return status_of(e);
 }
 
@@ -616,12 +672,16 @@ int lbm_pool_autotune(lbm_pool* P, const int* slots, int count, int reps, int us
         return lbm_pool_set_tile(P, c.vx, c.nw, c.flags);
     }
     std::vector<TileCand> cands = pool_candidates(P->dtype);
-    if (pers)  // 4-wave tiles (2 rows each) take one atomic per 2 rows: far slower persistent, and slow to time
-        cands.erase(std::remove_if(cands.begin(), cands.end(), [](const TileCand& k) { return k.nw < 8; }),
+    if (pers)  // 4-wave tiles (2 rows each) take one atomic per 2 rows: far slower persistent, and slow to time;
+               // the persistent kernel takes single steps
+        cands.erase(std::remove_if(cands.begin(), cands.end(),
+                                   [](const TileCand& k) { return k.nw < 8 || (k.flags & LBM_TILE_TWO_STEP); }),
                     cands.end());
-    // one batched launch at step 0 of a 1-step call (a persistent launch of
-    // one step in persistent mode): reads each slot's current buffer and
-    // writes the other, without advancing any slot. The
+    // Every candidate is timed over two steps without advancing any slot:
+    // two batched launches at step 0 of a 1-step call (each reads each
+    // slot's current buffer and writes the other; a persistent launch of
+    // one step in persistent mode), or one two-step pass of a 2-step call
+    // (reads the current buffer, writes the other). The
     // descriptors and the item map of a shape are built and uploaded by its
     // first (untimed) launch only, so that the timed launches measure the
     // kernel and not the host work, which grows with the number of items.
@@ -629,12 +689,19 @@ int lbm_pool_autotune(lbm_pool* P, const int* slots, int count, int reps, int us
     bool have_built = false;
     int nitems = 0;
     auto launch = [&](const TileCand& k) -> hipError_t {
+        const int two = (k.flags & LBM_TILE_TWO_STEP) ? 1 : 0;
+        const bool nts = (k.flags & LBM_TILE_NT_STORE) != 0;
         auto go = [&]() {
-            return launch_batch(P->dtype, k.vx, k.nw, (k.flags & LBM_TILE_NT_STORE) != 0, pers, P->d_lats,
-                                P->d_items, nitems, pers ? 1 : 0, pers ? P->max_grid : 0, k.ch,
-                                pers ? P->d_bar : nullptr, P->stream);
+            if (two) return launch_batch2(P->dtype, k.vx, k.nw, nts, P->d_lats, P->d_items, nitems, 0, k.ch, P->stream);
+            hipError_t ge = hipSuccess;
+            for (int r = 0; r < 2 && ge == hipSuccess; ++r)
+                ge = launch_batch(P->dtype, k.vx, k.nw, nts, pers, P->d_lats, P->d_items, nitems, pers ? 1 : 0,
+                                  pers ? P->max_grid : 0, k.ch, pers ? P->d_bar : nullptr, P->stream);
+            return ge;
         };
-        if (have_built && built.vx == k.vx && built.nw == k.nw && built.h == k.h) return go();
+        if (have_built && built.vx == k.vx && built.nw == k.nw && built.h == k.h &&
+            (built.flags & LBM_TILE_TWO_STEP) == (k.flags & LBM_TILE_TWO_STEP))
+            return go();
         have_built = false;
         const int ovx = P->vx, onw = P->nw, opi = P->per_item;
         P->vx = k.vx;
@@ -644,9 +711,9 @@ int lbm_pool_autotune(lbm_pool* P, const int* slots, int count, int reps, int us
         P->h_items.clear();
         for (int j = 0; j < count; ++j) {
             BatchLat b{};
-            b.tile = slot_tile(P->slots[slots[j]], k.vx, k.nw);
-            b.t0 = P->slots[slots[j]].t;
-            b.nsteps = 1;
+            b.tile = slot_tile(P->slots[slots[j]], k.vx, k.nw, two);
+            b.t0 = buffer_time(P->slots[slots[j]]);
+            b.nsteps = two ? 2 : 1;
             add_lattice(P, b);
         }
         P->vx = ovx;
@@ -688,7 +755,7 @@ int lbm_pool_get_tile(const lbm_pool* P, int* vx, int* nw, int* flags)
     if (!P) return LBM_EINVAL;
     if (vx) *vx = P->vx;
     if (nw) *nw = P->nw;
-    if (flags) *flags = P->nts ? LBM_TILE_NT_STORE : 0;
+    if (flags) *flags = (P->nts ? LBM_TILE_NT_STORE : 0) | (P->two ? LBM_TILE_TWO_STEP : 0);
     return LBM_OK;
 }
 

@@ -86,28 +86,40 @@ __device__ __forceinline__ void field_own(const StepTile& a, int r, int x, bool 
     }
 }
 
-// FIELD: a lattice with a c2 field (per-site source coefficients).
-template <class T, bool SHIFT, int VX, int NW, bool NTS, bool FIELD>
-__global__ __launch_bounds__(64 * NW) void step2_vstack_kernel(StepTile a, int ntiles)
+// LDS of a two-step tile: the densities (one row per wave) and the first
+// step's results of waves 1 .. NW - 2, in rows of the lanes' columns plus
+// one column on each side.
+template <class T, int VX, int NW> struct Step2Lds {
+    static constexpr int LW = 64 * VX + 2;
+    typename CompT<T>::type rho[NW][LW];
+    T fs[NW - 2][9][LW];
+};
+
+// One two-step tile: strip `strip`, row group `grp` of lattice a, reading
+// src and writing dst. single: take one step only (the group's rows and
+// the strip's columns as for two steps, phases 1 and 4 of the header with
+// the relaxed rows written; the lone last step of an odd step count in the
+// batched form). FIELD: the lattice has a c2 field. RC: centre the
+// arithmetic on the lattice model's state at rest (see Centre in step.h).
+// Every wave of the workgroup must call it (it holds workgroup barriers);
+// the caller places a barrier between two calls that reuse lds.
+template <class T, bool SHIFT, int VX, int NW, bool NTS, bool FIELD, bool RC>
+__device__ __forceinline__ void step2_tile(const StepTile& a, const void* src, void* dst, int strip, int grp,
+                                           bool single, Step2Lds<T, VX, NW>& lds)
 {
     using C = typename CompT<T>::type;
     using K = KeepT<T, C>;
-    constexpr bool RC = ModelCentred<C>::value;
     constexpr int HL = step2_halo_lanes(VX);
     constexpr int W2 = step2_cols(VX);
     constexpr int R2 = step2_rows(NW);
     static_assert(R2 >= 1, "a two-step tile needs at least 7 waves");
-    constexpr int LW = 64 * VX + 2;  // an LDS row: the lanes' columns and one more on each side
     constexpr int ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
     constexpr int ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
     constexpr unsigned es = sizeof(T);
-    __shared__ C rho[NW][LW];        // densities, one row per wave
-    __shared__ T fs[NW - 2][9][LW];  // first-step results of waves 1 .. NW - 2
+    auto& rho = lds.rho;
+    auto& fs = lds.fs;
 
-    const int t = xcd_tile(blockIdx.x, gridDim.x, a.xcd_chunk);
-    if (t >= ntiles) return;
     const Geom g = a.g;
-    const int strip = t % a.nstrips, grp = t / a.nstrips;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     const int y0 = grp * R2;
@@ -120,6 +132,9 @@ __global__ __launch_bounds__(64 * NW) void step2_vstack_kernel(StepTile a, int n
     const CoefC<C> k = coef_c<C>(a.c);
     const Centre<C> cn = centre_c<C, RC>(a.c);
     const int col = lane * VX + 1;  // LDS column of the lane's first column
+    const int nv = min(VX, g.nx - x);
+    // the rows and lanes the tile writes
+    const bool out = wave >= 3 && wave <= nrows + 2 && lane >= HL && lane < 64 - HL && nv > 0;
 
     K d[9][VX];
     C w[VX];
@@ -136,15 +151,28 @@ __global__ __launch_bounds__(64 * NW) void step2_vstack_kernel(StepTile a, int n
             collide<T, SHIFT, C, VX, RC>(d, j, w[j], gx, gy, site_coef<FIELD>(k, af[j]), cn, o[j]);
         }
     };
-    // 1. Gather the own columns from memory; waves past the last row the group needs idle.
-    if (wave <= nrows + 5) {
+    auto write = [&](const C (&o)[VX][9]) {
+        Pack<T, VX> pk[9];
+#pragma unroll
+        for (int j = 0; j < VX; ++j)
+#pragma unroll
+            for (int i = 0; i < 9; ++i) pk[i].v[j] = from_d<T, SHIFT, C>(o[j][i], i, cn);
+        char* dbase[9];
+        dst_bases<T>(dst, g, dbase);
+        write_row<T, VX, NTS>(dbase, g, y, x, nv, pk);
+    };
+    // 1. Gather the own columns from memory: rows 0 .. nrows + 5 for two
+    // steps, 2 .. nrows + 3 for one; the other waves idle.
+    const bool load = single ? (wave >= 2 && wave <= nrows + 3) : (wave <= nrows + 5);
+    if (load) {
         const char* sb[9];
-        src_bases<T>(a.src, g, sb);
+        src_bases<T>(src, g, sb);
         const char* rb[9];
         const int yw = wrap_mod(y, g.ny);
         row_bases<T>(sb, g, yw, rb);
         if constexpr (FIELD)
-            if (wave >= 1 && wave <= nrows + 4) field_own<C, VX>(a, yw, x, edge, af);
+            if (single ? (wave >= 3 && wave <= nrows + 2) : (wave >= 1 && wave <= nrows + 4))
+                field_own<C, VX>(a, yw, x, edge, af);
         T raw[9][VX];
         if (edge) {
             gather_own_wrapped<T, VX>(rb, g, x, raw);
@@ -168,6 +196,14 @@ __global__ __launch_bounds__(64 * NW) void step2_vstack_kernel(StepTile a, int n
         }
     }
     __syncthreads();
+    if (single) {  // one step: relax and write the group's rows
+        if (out) {
+            C o[VX][9];
+            relax(rho[wave], rho[wave + 1], rho[wave - 1], o);
+            write(o);
+        }
+        return;
+    }
     // 2. First step, every lane, into LDS.
     if (wave >= 1 && wave <= min(nrows + 4, NW - 2)) {
         C o[VX][9];
@@ -181,8 +217,7 @@ __global__ __launch_bounds__(64 * NW) void step2_vstack_kernel(StepTile a, int n
     // 3. Second gather, from LDS: f_i at column c of row y is the first
     // step's S_i at column c - e_ix of row y - e_iy. Lanes next to the strip
     // edge read LDS columns that nothing wrote; their results are never written.
-    const bool act3 = wave >= 2 && wave <= min(nrows + 3, NW - 3);
-    if (act3) {
+    if (wave >= 2 && wave <= min(nrows + 3, NW - 3)) {
 #pragma unroll
         for (int i = 0; i < 9; ++i)
 #pragma unroll
@@ -195,18 +230,54 @@ __global__ __launch_bounds__(64 * NW) void step2_vstack_kernel(StepTile a, int n
     }
     __syncthreads();
     // 4. Second step: the group's rows, inner lanes, columns inside the lattice.
-    const int nv = min(VX, g.nx - x);
-    if (wave >= 3 && wave <= nrows + 2 && lane >= HL && lane < 64 - HL && nv > 0) {
+    if (out) {
         C o[VX][9];
         relax(rho[wave], rho[wave + 1], rho[wave - 1], o);
-        Pack<T, VX> out[9];
-#pragma unroll
-        for (int j = 0; j < VX; ++j)
-#pragma unroll
-            for (int i = 0; i < 9; ++i) out[i].v[j] = from_d<T, SHIFT, C>(o[j][i], i, cn);
-        char* dbase[9];
-        dst_bases<T>(a.dst, g, dbase);
-        write_row<T, VX, NTS>(dbase, g, y, x, nv, out);
+        write(o);
+    }
+}
+
+// FIELD: a lattice with a c2 field (per-site source coefficients).
+template <class T, bool SHIFT, int VX, int NW, bool NTS, bool FIELD>
+__global__ __launch_bounds__(64 * NW) void step2_vstack_kernel(StepTile a, int ntiles)
+{
+    __shared__ Step2Lds<T, VX, NW> lds;
+    const int t = xcd_tile(blockIdx.x, gridDim.x, a.xcd_chunk);
+    if (t >= ntiles) return;
+    step2_tile<T, SHIFT, VX, NW, NTS, FIELD, ModelCentred<typename CompT<T>::type>::value>(
+        a, a.src, a.dst, t % a.nstrips, t / a.nstrips, false, lds);
+}
+
+// Batched form: pass p (steps 2p and 2p + 1) of every lattice of a batch
+// (BatchLat in internal.h; one workgroup per item, items dealt to the XCDs
+// in chunks of ch, see xcd_tile). A lattice's descriptor carries as t0 its
+// buffer time: the state at the start of the call is in buffer t0 & 1
+// (tile.src for even, tile.dst for odd), and every pass moves it to the
+// other buffer. A lattice with nsteps <= 2p sits out; one with nsteps =
+// 2p + 1 takes its last step alone. Pools step the paper's model, centred
+// on the weights (as the single-step batched kernels).
+// Compiled for 8 waves per SIMD (two 16-wave workgroups per CU): left to
+// itself the compiler spends more scalar registers than that allows.
+template <class T, bool SHIFT, int VX, int NW, bool NTS>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(8, 8))) void batch_step2_kernel(const BatchLat* __restrict__ lats,
+                                                              const int* __restrict__ item_lat, int nitems, int p,
+                                                              int ch)
+{
+    __shared__ Step2Lds<T, VX, NW> lds;
+    const int i = xcd_tile(blockIdx.x, gridDim.x, ch);
+    if (i >= nitems) return;
+    const BatchLat& L = lats[item_lat[i]];
+    if (2 * p >= L.nsteps) return;
+    const bool single = 2 * p + 1 == L.nsteps;
+    const bool odd = ((L.t0 + p) & 1) != 0;
+    const void* src = odd ? L.tile.dst : L.tile.src;
+    void* dst = odd ? const_cast<void*>(L.tile.src) : L.tile.dst;
+    const int t0 = (i - L.item_begin) * L.per_item;
+    const int t1 = min(t0 + L.per_item, L.ntiles);
+    for (int t = t0; t < t1; ++t) {
+        if (t > t0) __syncthreads();  // lds of the previous tile is still being read
+        step2_tile<T, SHIFT, VX, NW, NTS, false, false>(L.tile, src, dst, t % L.tile.nstrips, t / L.tile.nstrips,
+                                                        single, lds);
     }
 }
 
@@ -248,6 +319,34 @@ static hipError_t launch2_vx(int vx, int nw, bool nts, const StepTile& t, hipStr
     }
 }
 
+template <class T, bool SHIFT, int VX, int NW>
+static hipError_t launch_batch2_t(bool nts, const BatchLat* lats, const int* item_lat, int nitems, int p, int ch,
+                                  hipStream_t st)
+{
+    const int q = ch > 0 ? 8 * ch : 8;
+    const int grid = (nitems + q - 1) / q * q;
+    if (nitems <= 0) return hipSuccess;
+    if (!grid_fits(grid, 64 * NW)) return hipErrorInvalidConfiguration;
+    if (nts)
+        hipLaunchKernelGGL((batch_step2_kernel<T, SHIFT, VX, NW, true>), dim3(grid), dim3(64 * NW), 0, st, lats,
+                           item_lat, nitems, p, ch);
+    else
+        hipLaunchKernelGGL((batch_step2_kernel<T, SHIFT, VX, NW, false>), dim3(grid), dim3(64 * NW), 0, st, lats,
+                           item_lat, nitems, p, ch);
+    return hipGetLastError();
+}
+
+template <class T, bool SHIFT>
+static hipError_t launch_batch2_vx(int vx, int nw, bool nts, const BatchLat* lats, const int* item_lat, int nitems,
+                                   int p, int ch, hipStream_t st)
+{
+    if (vx == 1 && nw == 12) return launch_batch2_t<T, SHIFT, 1, 12>(nts, lats, item_lat, nitems, p, ch, st);
+    if (vx == 1 && nw == 16) return launch_batch2_t<T, SHIFT, 1, 16>(nts, lats, item_lat, nitems, p, ch, st);
+    if (vx == 2 && nw == 12) return launch_batch2_t<T, SHIFT, 2, 12>(nts, lats, item_lat, nitems, p, ch, st);
+    if (vx == 2 && nw == 16) return launch_batch2_t<T, SHIFT, 2, 16>(nts, lats, item_lat, nitems, p, ch, st);
+    return hipErrorInvalidValue;
+}
+
 // dtype: 0 FP64, 1 FP32, 2 FP32-shifted (FP16 storage has no two-step form).
 bool step2_shape_supported(int dtype, int vx, int nw)
 {
@@ -263,6 +362,20 @@ hipError_t launch_step2(int dtype, int vx, int nw, int flags, const StepTile& t,
     case 0: return launch2_vx<double, false>(vx, nw, nts, t, st);
     case 1: return launch2_vx<float, false>(vx, nw, nts, t, st);
     case 2: return launch2_vx<float, true>(vx, nw, nts, t, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+// Batched form, pass p (see batch_step2_kernel); the lattices' tiles are
+// those of step2_cols / step2_rows.
+hipError_t launch_batch2(int dtype, int vx, int nw, bool nts, const BatchLat* lats, const int* item_lat, int nitems,
+                         int p, int ch, hipStream_t st)
+{
+    if (!step2_shape_supported(dtype, vx, nw)) return hipErrorInvalidValue;
+    switch (dtype) {
+    case 0: return launch_batch2_vx<double, false>(vx, nw, nts, lats, item_lat, nitems, p, ch, st);
+    case 1: return launch_batch2_vx<float, false>(vx, nw, nts, lats, item_lat, nitems, p, ch, st);
+    case 2: return launch_batch2_vx<float, true>(vx, nw, nts, lats, item_lat, nitems, p, ch, st);
     }
     return hipErrorInvalidValue;
 }

@@ -123,7 +123,12 @@ std::vector<TileCand> pool_candidates(int dtype)
             for (int nts = 0; nts < 2; ++nts)
                 for (int per : {1, 2})
                     for (int ch : {8, 32}) v.push_back({vx, nw, per, nts ? LBM_TILE_NT_STORE : 0, ch});
-    (void)dtype;
+    // two steps per launch (grouped and graph modes; no FP16 form)
+    if (dtype != LBM_F16S)
+        for (int vx : {1, 2})
+            for (int nw : {12, 16})
+                for (int per : {1, 2})
+                    for (int ch : {8, 32}) v.push_back({vx, nw, per, LBM_TILE_TWO_STEP | LBM_TILE_NT_STORE, ch});
     return v;
 }
 

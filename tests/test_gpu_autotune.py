@@ -44,7 +44,7 @@ def test_pool_autotune_keeps_state(tmp_path, monkeypatch):
         after = [P.get_f(s) for s in slots]
         assert all(np.array_equal(a, b) for a, b in zip(before, after))
         assert [P.time(s) for s in slots] == [3, 3, 3]
-        assert tile[1] in (4, 8, 16)
+        assert tile[1] in (4, 8, 12, 16)
 
 
 _TUNE_CHILD = """
