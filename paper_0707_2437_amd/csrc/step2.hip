@@ -24,7 +24,11 @@
 //   4. waves 3 .. NW-4, inner lanes only, relax (second step) and write.
 // Every site's arithmetic is the single-step code of step.h (the same drho
 // and collide functions, on the same inputs), so a two-step pass gives the
-// bits of two single steps.
+// bits of two single steps. FP16 storage takes the same code with each
+// value converted to FP32 where it is used: the single-step FP16 kernel
+// reads its halves as operands of mixed-precision FMAs, which convert them
+// exactly and round once, the same bits. Its rows' ghost columns (see
+// GhostCols in step.h) are written with the second step's results.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -83,6 +87,30 @@ __device__ __forceinline__ void field_own(const StepTile& a, int r, int x, bool 
         const Pack<C, VX> p = ld_vec<C, VX, 4>(row, (unsigned)x * (unsigned)sizeof(C));
 #pragma unroll
         for (int j = 0; j < VX; ++j) af[j] = p.v[j];
+    }
+}
+
+// Base pointers of the nine planes at column c0 of row r (in [0, ny)) of
+// buffer buf; with SHIFT_ROWS plane i is taken at row r - e_iy (wrapped).
+// The planes are stepped through with 64-bit additions (the planes of the
+// plane-major layout may span more than 4 GB together); row offsets are
+// 32-bit products (a plane, and a row-interleaved buffer, spans less than
+// 4 GB: offsets_fit on the host).
+template <class T, bool SHIFT_ROWS>
+__device__ __forceinline__ void plane_rows(const void* buf, const Geom& g, int c0, int r, const char* (&p)[9])
+{
+    constexpr unsigned es = sizeof(T);
+    constexpr int ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    const unsigned rsb = (unsigned)g.rs * es;
+    const unsigned long long psb = (unsigned long long)g.ps * es;
+    const unsigned o0 = (unsigned)r * rsb;
+    const unsigned om = SHIFT_ROWS ? (unsigned)(r == 0 ? g.ny - 1 : r - 1) * rsb : o0;
+    const unsigned op = SHIFT_ROWS ? (unsigned)(r == g.ny - 1 ? 0 : r + 1) * rsb : o0;
+    const char* q = (const char*)buf + (long long)(g.off + c0) * (long long)es;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        p[i] = q + (ey[i] > 0 ? om : (ey[i] < 0 ? op : o0));
+        q += psb;
     }
 }
 
@@ -158,18 +186,27 @@ __device__ __forceinline__ void step2_tile(const StepTile& a, const void* src, v
 #pragma unroll
             for (int i = 0; i < 9; ++i) pk[i].v[j] = from_d<T, SHIFT, C>(o[j][i], i, cn);
         char* dbase[9];
-        dst_bases<T>(dst, g, dbase);
-        write_row<T, VX, NTS>(dbase, g, y, x, nv, pk);
+        if constexpr (VX == 1) {
+            // the row's plane bases as for the loads (measured faster with one
+            // column per lane, slower with two)
+            const char* rows[9];
+            plane_rows<T, false>(dst, g, 0, y, rows);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) dbase[i] = const_cast<char*>(rows[i]);
+            write_row<T, VX, NTS>(dbase, g, 0, x, nv, pk);  // the row is in dbase
+        } else {
+            dst_bases<T>(dst, g, dbase);
+            write_row<T, VX, NTS>(dbase, g, y, x, nv, pk);
+        }
     };
     // 1. Gather the own columns from memory: rows 0 .. nrows + 5 for two
     // steps, 2 .. nrows + 3 for one; the other waves idle.
     const bool load = single ? (wave >= 2 && wave <= nrows + 3) : (wave <= nrows + 5);
     if (load) {
-        const char* sb[9];
-        src_bases<T>(src, g, sb);
+        // y in [-3, ny + 2] and ny >= 3: one wrap
+        const int yw = y < 0 ? y + g.ny : (y >= g.ny ? y - g.ny : y);
         const char* rb[9];
-        const int yw = wrap_mod(y, g.ny);
-        row_bases<T>(sb, g, yw, rb);
+        plane_rows<T, true>(src, g, -2, yw, rb);
         if constexpr (FIELD)
             if (single ? (wave >= 3 && wave <= nrows + 2) : (wave >= 1 && wave <= nrows + 4))
                 field_own<C, VX>(a, yw, x, edge, af);
@@ -347,10 +384,10 @@ static hipError_t launch_batch2_vx(int vx, int nw, bool nts, const BatchLat* lat
     return hipErrorInvalidValue;
 }
 
-// dtype: 0 FP64, 1 FP32, 2 FP32-shifted (FP16 storage has no two-step form).
+// dtype: 0 FP64, 1 FP32, 2 FP32-shifted, 3 FP16-shifted.
 bool step2_shape_supported(int dtype, int vx, int nw)
 {
-    return dtype >= 0 && dtype <= 2 && (vx == 1 || vx == 2) && (nw == 12 || nw == 16);
+    return dtype >= 0 && dtype <= 3 && (vx == 1 || vx == 2) && (nw == 12 || nw == 16);
 }
 
 // flags: LBM_TILE_NT_STORE (2) selects non-temporal stores.
@@ -362,6 +399,7 @@ hipError_t launch_step2(int dtype, int vx, int nw, int flags, const StepTile& t,
     case 0: return launch2_vx<double, false>(vx, nw, nts, t, st);
     case 1: return launch2_vx<float, false>(vx, nw, nts, t, st);
     case 2: return launch2_vx<float, true>(vx, nw, nts, t, st);
+    case 3: return launch2_vx<_Float16, true>(vx, nw, nts, t, st);
     }
     return hipErrorInvalidValue;
 }
@@ -376,6 +414,7 @@ hipError_t launch_batch2(int dtype, int vx, int nw, bool nts, const BatchLat* la
     case 0: return launch_batch2_vx<double, false>(vx, nw, nts, lats, item_lat, nitems, p, ch, st);
     case 1: return launch_batch2_vx<float, false>(vx, nw, nts, lats, item_lat, nitems, p, ch, st);
     case 2: return launch_batch2_vx<float, true>(vx, nw, nts, lats, item_lat, nitems, p, ch, st);
+    case 3: return launch_batch2_vx<_Float16, true>(vx, nw, nts, lats, item_lat, nitems, p, ch, st);
     }
     return hipErrorInvalidValue;
 }

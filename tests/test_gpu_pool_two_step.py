@@ -46,9 +46,9 @@ def run(dtype, tile, mode=lbm.GROUPED, calls=CALLS, noalloc=False):
                 P.get_tile())
 
 
-@pytest.mark.parametrize("dtype", ["f64", "f32", "f32s"])
+@pytest.mark.parametrize("dtype", ["f64", "f32", "f32s", "f16s"])
 def test_pool_two_step_bitwise(dtype):
-    ref_f, ref_tot, ref_t, _ = run(dtype, SINGLE)
+    ref_f, ref_tot, ref_t, _ = run(dtype, (4, 8, NT) if dtype == "f16s" else SINGLE)
     assert ref_t == [sum(c[k] for c in CALLS) for k in range(len(SPECS))]
     for vx, nw in ((1, 12), (1, 16), (2, 12), (2, 16)):
         for mode in (lbm.GROUPED, lbm.GRAPH):
@@ -118,6 +118,7 @@ def test_pool_two_step_shape_errors():
                 P.set_tile(*bad)
         P.set_tile(2, 16, TWO | 16 | NT)  # the vertical-stack bit is accepted
         assert P.get_tile() == (2, 16, TWO | NT)
-    with lbm.Pool(1 << 26, "f16s") as P:
-        with pytest.raises(lbm.LBMError):
-            P.set_tile(2, 16, TWO)
+    with lbm.Pool(1 << 26, "f16s") as P:  # FP16 storage has the two-step form too
+        P.set_tile(2, 16, TWO)
+        P.set_mode(lbm.PERSISTENT)
+        assert P.get_tile() == (4, 8, NT)  # the single-step default of FP16 pools

@@ -1,6 +1,6 @@
 """The two-step form (LBM_TILE_VSTACK | LBM_TILE_TWO_STEP: two steps of Eq. 5
 per launch, the first step's results held in LDS) gives the bits of single
-steps: every shape, stored type and store flavour, on lattices that span
+steps: every shape, stored type (FP16 storage included) and store flavour, on lattices that span
 several tiles with ragged edges and on lattices smaller than one tile (whose
 halo rows and columns are periodic images of the lattice itself), for odd
 and even step counts (a lone last step takes the single-step kernel). The
@@ -35,7 +35,7 @@ def run(nx, ny, tau, c2, dtype, steps, fields, tile=None, model=None):
         return L.get_f()
 
 
-@pytest.mark.parametrize("dtype", ["f64", "f32", "f32s"])
+@pytest.mark.parametrize("dtype", ["f64", "f32", "f32s", "f16s"])
 @pytest.mark.parametrize("nx,ny", [(3, 3), (5, 4), (7, 3), (65, 3), (130, 77), (300, 41), (257, 129)])
 def test_two_step_bitwise_equals_single_steps(dtype, nx, ny):
     fields = smooth_random_state(nx, ny, seed=nx * 31 + ny)
@@ -101,12 +101,11 @@ def test_two_step_shape_errors():
                     (2, 16, 0, VSTACK | TWO_STEP | 1), (2, 16, 0, 64 | VSTACK)):
             with pytest.raises(lbm.LBMError):
                 L.set_tile(*bad)
-    with lbm.Lattice(64, 64, 0.7, 0.3, "f16s") as L:
-        with pytest.raises(lbm.LBMError):
-            L.set_tile(2, 16, 0, VSTACK | TWO_STEP)
+    with lbm.Lattice(64, 64, 0.7, 0.3, "f16s") as L:  # FP16 storage has the two-step form too
+        L.set_tile(2, 16, 0, VSTACK | TWO_STEP)
 
 
-@pytest.mark.parametrize("dtype", ["f64", "f32", "f32s"])
+@pytest.mark.parametrize("dtype", ["f64", "f32", "f32s", "f16s"])
 @pytest.mark.parametrize("nx,ny", [(3, 3), (7, 5), (130, 77), (300, 41)])
 def test_two_step_c2_field_bitwise(dtype, nx, ny):
     """A c2 field varying in x and y (per-site source coefficients, read once
@@ -122,10 +121,10 @@ def test_two_step_c2_field_bitwise(dtype, nx, ny):
                 L.set_tile(*tile)
             return L.init(*fields).step(7).get_f()
 
-    ref = go((2, 8, 0, VSTACK | NT))
+    ref = go((4, 8, 0, VSTACK | NT) if dtype == "f16s" else (2, 8, 0, VSTACK | NT))
     for vx, nw, f in SHAPES:
         assert np.array_equal(go((vx, nw, 0, f)), ref), (dtype, nx, ny, vx, nw, f)
-    assert np.array_equal(go(None), ref)  # the default shape (two-step)
+    assert np.array_equal(go(None), ref)  # the default shape
 
 
 def test_march_shape_with_field_takes_the_default():
