@@ -146,6 +146,10 @@ __device__ __forceinline__ void step2_tile(const StepTile& a, const void* src, v
     constexpr unsigned es = sizeof(T);
     auto& rho = lds.rho;
     auto& fs = lds.fs;
+    // LDS column c -> slot: with two columns per lane, even and odd columns
+    // in the two halves of a row, so that lanes touch consecutive slots
+    constexpr int HW = Step2Lds<T, VX, NW>::LW / 2;
+    auto li = [](int c) { return VX == 2 ? (c & 1) * HW + (c >> 1) : c; };
 
     const Geom g = a.g;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -171,11 +175,11 @@ __device__ __forceinline__ void step2_tile(const StepTile& a, const void* src, v
     auto relax = [&](const C* rrow, const C* rup, const C* rdn, C (&o)[VX][9]) {
 #pragma unroll
         for (int j = 0; j < VX; ++j) {
-            const C left = j == 0 ? rrow[col - 1] : w[j - 1];
-            const C right = j == VX - 1 ? rrow[col + VX] : w[j + 1];
+            const C left = j == 0 ? rrow[li(col - 1)] : w[j - 1];
+            const C right = j == VX - 1 ? rrow[li(col + VX)] : w[j + 1];
             // undivided central differences at time t (Sec. 4)
             const C gx = right - left;
-            const C gy = rup[col + j] - rdn[col + j];
+            const C gy = rup[li(col + j)] - rdn[li(col + j)];
             collide<T, SHIFT, C, VX, RC>(d, j, w[j], gx, gy, site_coef<FIELD>(k, af[j]), cn, o[j]);
         }
     };
@@ -229,7 +233,7 @@ __device__ __forceinline__ void step2_tile(const StepTile& a, const void* src, v
 #pragma unroll
         for (int j = 0; j < VX; ++j) {
             w[j] = drho_of<T, SHIFT, C, VX>(d, j, cn);
-            rho[wave][col + j] = w[j];
+            rho[wave][li(col + j)] = w[j];
         }
     }
     __syncthreads();
@@ -248,7 +252,7 @@ __device__ __forceinline__ void step2_tile(const StepTile& a, const void* src, v
 #pragma unroll
         for (int j = 0; j < VX; ++j)
 #pragma unroll
-            for (int i = 0; i < 9; ++i) fs[wave - 1][i][col + j] = from_d<T, SHIFT, C>(o[j][i], i, cn);
+            for (int i = 0; i < 9; ++i) fs[wave - 1][i][li(col + j)] = from_d<T, SHIFT, C>(o[j][i], i, cn);
     }
     __syncthreads();
     // 3. Second gather, from LDS: f_i at column c of row y is the first
@@ -258,11 +262,12 @@ __device__ __forceinline__ void step2_tile(const StepTile& a, const void* src, v
 #pragma unroll
         for (int i = 0; i < 9; ++i)
 #pragma unroll
-            for (int j = 0; j < VX; ++j) d[i][j] = keep_of<T, SHIFT, C>(fs[wave - ey[i] - 1][i][col + j - ex[i]], i, cn);
+            for (int j = 0; j < VX; ++j)
+                d[i][j] = keep_of<T, SHIFT, C>(fs[wave - ey[i] - 1][i][li(col + j - ex[i])], i, cn);
 #pragma unroll
         for (int j = 0; j < VX; ++j) {
             w[j] = drho_of<T, SHIFT, C, VX>(d, j, cn);
-            rho[wave][col + j] = w[j];
+            rho[wave][li(col + j)] = w[j];
         }
     }
     __syncthreads();
