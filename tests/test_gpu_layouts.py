@@ -2,7 +2,9 @@
 ABI. A lattice is stored row-interleaved when its whole buffer fits the
 kernels' 32-bit byte offsets (about 119 M sites in FP32, 60 M in FP64), and
 plane-major beyond that (each plane must fit). LBM_LAYOUT=soa forces the
-plane-major layout at lbm_create, so that small lattices can test it."""
+plane-major layout at lbm_create, so that small lattices can test it. The
+largest lattices take the default shape: two steps per launch (and a lone
+last step) for FP32 and FP64."""
 import numpy as np
 import pytest
 
@@ -18,7 +20,8 @@ if not torch.cuda.is_available():
 import paper_0707_2437_amd as lbm  # noqa: E402
 
 TOL = {"f64": 1e-12, "f32": 1e-5, "f32s": 1e-5, "f16s": 2e-3}
-TILES = [(2, 8, 0, 18), (1, 8, 0, 18), (4, 8, 0, 16), (2, 16, 0, 18), (1, 1, 1, 0), (2, 4, 8, 15)]
+TILES = [(2, 8, 0, 18), (1, 8, 0, 18), (4, 8, 0, 16), (2, 16, 0, 18), (1, 1, 1, 0), (2, 4, 8, 15),
+         (2, 16, 0, 50), (1, 12, 0, 48)]  # the last two: two steps per launch
 
 
 def run(nx, ny, dtype, fields, tile, steps=30):
