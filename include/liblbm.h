@@ -338,24 +338,20 @@ long long lbm_pool_time(const lbm_pool* P, int slot);
 
 /* Launch mode (lbm_pool_mode) and, for LBM_POOL_PERSISTENT, a cap on the
  * workgroups of the persistent launch (0: as many as the runtime reports a
- * CU can hold at once; those not resident when it starts take no part).
- * The persistent kernel takes single steps: selecting LBM_POOL_PERSISTENT
- * while a two-step tile is set replaces it by the dtype's default tile
- * (waiting for the pool's stream first). */
+ * CU can hold at once; those not resident when it starts take no part). */
 int lbm_pool_set_mode(lbm_pool* P, int mode, int max_grid);
 /* Vertical-stack tile of the batched kernels: vx in {1, 2, 4}, nw in
  * {4, 8, 16}, flags 0 or LBM_TILE_NT_STORE. Default: the two-step tile
  * below with nw 16, vx 1 for LBM_F64 and 2 for LBM_F32 and LBM_F32S, and
- * non-temporal stores; for LBM_F16S (and in LBM_POOL_PERSISTENT mode) vx 4
- * (2) and nw 8 with non-temporal stores. Two-step tiles (flags
- * LBM_TILE_TWO_STEP, optionally with LBM_TILE_VSTACK and LBM_TILE_NT_STORE;
- * vx 1 or 2, nw 12 or 16; LBM_F64, LBM_F32, LBM_F32S; grouped and graph
- * modes): each launch takes two steps of every listed lattice (the shapes
- * of lbm_set_tile's two-step form), a lattice with an odd step count takes
- * its last step alone in the last launch. LBM_EINVAL for other shapes and
- * for a two-step tile in LBM_POOL_PERSISTENT mode. Does not change results
- * (bitwise). lbm_pool_get_tile reports LBM_TILE_TWO_STEP and
- * LBM_TILE_NT_STORE. */
+ * non-temporal stores; for LBM_F16S vx 4 and nw 8 with non-temporal
+ * stores. Two-step tiles (flags LBM_TILE_TWO_STEP, optionally with
+ * LBM_TILE_VSTACK and LBM_TILE_NT_STORE; vx 1 or 2, nw 12 or 16; every
+ * dtype and mode): each launch (in LBM_POOL_PERSISTENT mode, each pass
+ * between grid barriers) takes two steps of every listed lattice (the
+ * shapes of lbm_set_tile's two-step form); a lattice with an odd step count
+ * takes its last step alone in the last one. LBM_EINVAL for other shapes.
+ * Does not change results (bitwise). lbm_pool_get_tile reports
+ * LBM_TILE_TWO_STEP and LBM_TILE_NT_STORE. */
 int lbm_pool_set_tile(lbm_pool* P, int vx, int nw, int flags);
 int lbm_pool_get_tile(const lbm_pool* P, int* vx, int* nw, int* flags);
 /* Tiles per work item of the batched kernels (1..64, default 1): a
@@ -366,8 +362,8 @@ int lbm_pool_set_items(lbm_pool* P, int tiles_per_item);
  * tiles per item and the order in which items are dealt to the GPU's
  * chiplets, single- and two-step tiles, each timed over two steps of the
  * listed slots without advancing them (in LBM_POOL_PERSISTENT mode, on
- * one-step persistent launches of single-step tiles, whose best shape
- * differs); cached per architecture, mode, dtype, and the batch's
+ * persistent launches, whose best shape differs); cached per
+ * architecture, mode, dtype, and the batch's
  * lattice count and total sites rounded up to powers of two. Call it after
  * lbm_pool_set_mode. */
 int lbm_pool_autotune(lbm_pool* P, const int* slots, int count, int reps, int use_cache);

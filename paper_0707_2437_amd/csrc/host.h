@@ -19,6 +19,19 @@ bool step_shape_supported(int dtype, int vx, int nw, int flags);
 // step2_cols / step2_rows.
 hipError_t launch_step2(int dtype, int vx, int nw, int flags, const StepTile& t, hipStream_t st);
 bool step2_shape_supported(int dtype, int vx, int nw);
+// Set-up of a persistent batched launch of kernel kern (threads per
+// workgroup): the grid (what the runtime reports as resident at once,
+// capped by max_grid, a multiple of 8 ch, or of 8 with *ch = 0, or *ch =
+// -1 below 8), the bounded barrier wait and the membership grace in device
+// clock ticks; and the reset of the barrier words bar on stream st.
+hipError_t persistent_setup(const void* kern, int threads, int max_grid, int* ch, int* grid,
+                            unsigned long long* wait_ticks, unsigned long long* grace_ticks, unsigned* bar,
+                            hipStream_t st);
+// All passes (npasses of two steps) of a batch in one persistent launch of
+// two-step tiles (step2.hip), with a grid barrier between passes (as the
+// single-step persistent kernel, batch.hip).
+hipError_t launch_batch2_persistent(int dtype, int vx, int nw, bool nts, const BatchLat* lats, const int* item_lat,
+                                    int nitems, int npasses, int max_grid, int ch, unsigned* bar, hipStream_t st);
 // Pass p (steps 2p, 2p + 1) of a batch in two-step tiles (step2.hip): the
 // descriptors' t0 is each lattice's buffer time (its state is in buffer
 // (t0 + p) & 1 at the start of pass p); a lattice with nsteps = 2p + 1

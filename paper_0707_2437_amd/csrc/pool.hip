@@ -141,14 +141,13 @@ void advance(Slot& S, int n, int two)
 }
 
 // The dtype's default tile of the batched kernels (from the batched
-// sweeps): with two_ok, the two-step tile where the dtype has one (16
-// waves, vx = 1 for FP64 and 2 otherwise, as for single lattices), else the
-// single-step vertical stack of 8 waves (vx = 4 for FP16, 2 otherwise);
-// non-temporal stores.
-void set_default_tile(lbm_pool* P, bool two_ok)
+// sweeps): the two-step tile where it is faster (16 waves, vx = 1 for FP64
+// and 2 for FP32 and FP32-shifted, as for single lattices), else (FP16) the
+// single-step vertical stack of 8 waves with vx = 4; non-temporal stores.
+void set_default_tile(lbm_pool* P)
 {
     P->nts = 1;
-    if (two_ok && P->dtype != LBM_F16S) {
+    if (P->dtype != LBM_F16S) {
         P->two = 1;
         P->nw = 16;
         P->vx = P->dtype == LBM_F64 ? 1 : 2;
@@ -253,8 +252,10 @@ hipError_t run_batch(lbm_pool* P, int nmax)
     if (e != hipSuccess) return e;
     const bool nts = P->nts != 0;
     if (P->mode == LBM_POOL_PERSISTENT)
-        return launch_batch(P->dtype, P->vx, P->nw, nts, true, P->d_lats, P->d_items, nitems, nmax,
-                            P->max_grid, P->xcd_chunk, P->d_bar, P->stream);
+        return P->two ? launch_batch2_persistent(P->dtype, P->vx, P->nw, nts, P->d_lats, P->d_items, nitems,
+                                                 (nmax + 1) / 2, P->max_grid, P->xcd_chunk, P->d_bar, P->stream)
+                      : launch_batch(P->dtype, P->vx, P->nw, nts, true, P->d_lats, P->d_items, nitems, nmax,
+                                     P->max_grid, P->xcd_chunk, P->d_bar, P->stream);
     // launch k of the call: step k, or two-step pass k
     const int nlaunch = P->two ? (nmax + 1) / 2 : nmax;
     auto launch_k = [&](int k) {
@@ -317,7 +318,7 @@ lbm_pool* lbm_pool_create(size_t budget_bytes, int dtype)
     P->dtype = dtype;
     P->esize = esize_of(dtype);
     P->budget = budget_bytes;
-    set_default_tile(P, true);
+    set_default_tile(P);
     if (const char* ev = std::getenv("LBM_XCD_CHUNK")) {  // experiments: items per XCD chunk
         const int v = std::atoi(ev);
         if (v >= 0 && v <= 4096) P->xcd_chunk = v;
@@ -509,7 +510,10 @@ int lbm_pool_step_noalloc(lbm_pool* P, const int* slots, const int* nsteps, int 
                            P->stream);
     const bool nts = P->nts != 0;
     if (e == hipSuccess) {
-        if (P->mode == LBM_POOL_PERSISTENT) {
+        if (P->mode == LBM_POOL_PERSISTENT && P->two) {
+            e = launch_batch2_persistent(P->dtype, P->vx, P->nw, nts, d_lats, d_items, nitems, (nmax + 1) / 2,
+                                         P->max_grid, P->xcd_chunk, P->d_bar, P->stream);
+        } else if (P->mode == LBM_POOL_PERSISTENT) {
             e = launch_batch(P->dtype, P->vx, P->nw, nts, true, d_lats, d_items, nitems, nmax, P->max_grid,
                              P->xcd_chunk, P->d_bar, P->stream);
         } else if (P->two) {
@@ -616,12 +620,6 @@ long long lbm_pool_time(const lbm_pool* P, int slot)
 int lbm_pool_set_mode(lbm_pool* P, int mode, int max_grid)
 {
     if (!P || mode < LBM_POOL_GROUPED || mode > LBM_POOL_PERSISTENT || max_grid < 0) return LBM_EINVAL;
-    if (mode == LBM_POOL_PERSISTENT && P->two) {
-        // the persistent kernel takes single steps: the dtype's single-step tile
-        hipError_t e = hipStreamSynchronize(P->stream);
-        if (e != hipSuccess) return status_of(e);
-        set_default_tile(P, false);
-    }
     P->mode = mode;
     P->max_grid = max_grid;
     return LBM_OK;
@@ -633,7 +631,7 @@ int lbm_pool_set_tile(lbm_pool* P, int vx, int nw, int flags)
     const bool two = (flags & LBM_TILE_TWO_STEP) != 0;
     if (two) {
         if ((flags & ~(LBM_TILE_TWO_STEP | LBM_TILE_VSTACK | LBM_TILE_NT_STORE)) ||
-            !step2_shape_supported(P->dtype, vx, nw) || P->mode == LBM_POOL_PERSISTENT)
+            !step2_shape_supported(P->dtype, vx, nw))
             return LBM_EINVAL;
     } else if ((flags & ~LBM_TILE_NT_STORE) || !step_shape_supported(P->dtype, vx, nw, LBM_TILE_VSTACK)) {
         return LBM_EINVAL;
@@ -672,10 +670,8 @@ int lbm_pool_autotune(lbm_pool* P, const int* slots, int count, int reps, int us
         return lbm_pool_set_tile(P, c.vx, c.nw, c.flags);
     }
     std::vector<TileCand> cands = pool_candidates(P->dtype);
-    if (pers)  // 4-wave tiles (2 rows each) take one atomic per 2 rows: far slower persistent, and slow to time;
-               // the persistent kernel takes single steps
-        cands.erase(std::remove_if(cands.begin(), cands.end(),
-                                   [](const TileCand& k) { return k.nw < 8 || (k.flags & LBM_TILE_TWO_STEP); }),
+    if (pers)  // 4-wave tiles (2 rows each) take one atomic per 2 rows: far slower persistent, and slow to time
+        cands.erase(std::remove_if(cands.begin(), cands.end(), [](const TileCand& k) { return k.nw < 8; }),
                     cands.end());
     // Every candidate is timed over two steps without advancing any slot:
     // two batched launches at step 0 of a 1-step call (each reads each
@@ -692,6 +688,9 @@ int lbm_pool_autotune(lbm_pool* P, const int* slots, int count, int reps, int us
         const int two = (k.flags & LBM_TILE_TWO_STEP) ? 1 : 0;
         const bool nts = (k.flags & LBM_TILE_NT_STORE) != 0;
         auto go = [&]() {
+            if (two && pers)
+                return launch_batch2_persistent(P->dtype, k.vx, k.nw, nts, P->d_lats, P->d_items, nitems, 1,
+                                                P->max_grid, k.ch, P->d_bar, P->stream);
             if (two) return launch_batch2(P->dtype, k.vx, k.nw, nts, P->d_lats, P->d_items, nitems, 0, k.ch, P->stream);
             hipError_t ge = hipSuccess;
             for (int r = 0; r < 2 && ge == hipSuccess; ++r)

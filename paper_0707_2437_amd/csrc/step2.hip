@@ -31,6 +31,7 @@
 // GhostCols in step.h) are written with the second step's results.
 #include <hip/hip_runtime.h>
 
+#include "grid_sync.h"
 #include "internal.h"
 #include "step.h"
 #include "step2.h"
@@ -131,7 +132,10 @@ template <class T, int VX, int NW> struct Step2Lds {
 // arithmetic on the lattice model's state at rest (see Centre in step.h).
 // Every wave of the workgroup must call it (it holds workgroup barriers);
 // the caller places a barrier between two calls that reuse lds.
-template <class T, bool SHIFT, int VX, int NW, bool NTS, bool FIELD, bool RC>
+// KIND: a distinct instantiation per kernel that uses the tile (measured:
+// sharing one instantiation between the grouped and persistent batched
+// kernels made the compiler spill registers in the grouped one).
+template <class T, bool SHIFT, int VX, int NW, bool NTS, bool FIELD, bool RC, int KIND = 0>
 __device__ __forceinline__ void step2_tile(const StepTile& a, const void* src, void* dst, int strip, int grp,
                                            bool single, Step2Lds<T, VX, NW>& lds)
 {
@@ -298,10 +302,11 @@ __global__ __launch_bounds__(64 * NW) void step2_vstack_kernel(StepTile a, int n
 // other buffer. A lattice with nsteps <= 2p sits out; one with nsteps =
 // 2p + 1 takes its last step alone. Pools step the paper's model, centred
 // on the weights (as the single-step batched kernels).
-// Compiled for 8 waves per SIMD (two 16-wave workgroups per CU): left to
-// itself the compiler spends more scalar registers than that allows.
+// The 16-wave shapes whose LDS lets two workgroups share a CU are compiled
+// for 8 waves per SIMD: left to itself the compiler spends more scalar
+// registers than that allows.
 template <class T, bool SHIFT, int VX, int NW, bool NTS>
-__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(8, 8))) void batch_step2_kernel(const BatchLat* __restrict__ lats,
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW == 16 && sizeof(T) * VX <= 8 ? 8 : 1, 8))) void batch_step2_kernel(const BatchLat* __restrict__ lats,
                                                               const int* __restrict__ item_lat, int nitems, int p,
                                                               int ch)
 {
@@ -320,6 +325,58 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(8, 8)))
         if (t > t0) __syncthreads();  // lds of the previous tile is still being read
         step2_tile<T, SHIFT, VX, NW, NTS, false, false>(L.tile, src, dst, t % L.tile.nstrips, t / L.tile.nstrips,
                                                         single, lds);
+    }
+}
+
+// Persistent form: all npasses passes of a batch in one launch whose G
+// member workgroups (join_members in grid_sync.h) meet at a grid barrier
+// between passes, since pass p + 1 reads what pass p wrote. Work is taken
+// dynamically as in the single-step persistent kernel (batch.hip): one
+// counter per part and pass (two passes' sets alternate; the barrier's last
+// arriver zeroes the next pass's set), a member takes its part's next item
+// with one atomic add, so a pass ends when its work does. Each item is run
+// as in batch_step2_kernel.
+template <class T, bool SHIFT, int VX, int NW, bool NTS>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW == 16 && sizeof(T) * VX <= 8 ? 8 : 1, 8))) void batch_persistent2_kernel(
+    const BatchLat* __restrict__ lats, const int* __restrict__ item_lat, int nitems, int npasses, int ch,
+    unsigned* bar, unsigned long long wait_ticks, unsigned long long grace_ticks)
+{
+    __shared__ Step2Lds<T, VX, NW> lds;
+    __shared__ int next_item;
+    if (stale_barrier_error(bar)) return;
+    int rank = 0;
+    const int G = join_members(bar, wait_ticks, grace_ticks, &rank);
+    if (G == 0) return;
+    const bool by_xcd = G == (int)gridDim.x && G % 8 == 0;
+    const int nparts = by_xcd ? 8 : 1;
+    const int part = by_xcd ? (int)(blockIdx.x & 7u) : 0;
+    const int chunk = ch > 0 ? ch : 1;
+    for (int p = 0; p < npasses; ++p) {
+        unsigned* ctr = bar + kBarCtr + (p & 1) * 8 + part;
+        for (;;) {
+            if (threadIdx.x == 0) next_item = min(part_item((int)atomicAdd(ctr, 1u), part, nparts, chunk), nitems);
+            __syncthreads();
+            const int i = next_item;
+            __syncthreads();  // read by every wave before the next item is written; lds free again
+            if (i >= nitems) break;
+            const BatchLat* L = &lats[ldc(&item_lat[i])];
+            const int n = ldc(&L->nsteps);
+            if (2 * p >= n) continue;  // this lattice takes fewer steps
+            const bool single = 2 * p + 1 == n;
+            const StepTile a = ldc(&L->tile);
+            const bool odd = ((ldc(&L->t0) + p) & 1) != 0;
+            const void* src = odd ? a.dst : a.src;
+            void* dst = odd ? const_cast<void*>(a.src) : a.dst;
+            const int per = ldc(&L->per_item);
+            const int t0 = (i - ldc(&L->item_begin)) * per;
+            const int t1 = min(t0 + per, ldc(&L->ntiles));
+            for (int t = t0; t < t1; ++t) {
+                if (t > t0) __syncthreads();  // lds of the previous tile is still being read
+                step2_tile<T, SHIFT, VX, NW, NTS, false, false, 1>(a, src, dst, t % a.nstrips, t / a.nstrips,
+                                                                   single, lds);
+            }
+        }
+        if (!grid_barrier(bar, G, wait_ticks, bar + kBarCtr + ((p + 1) & 1) * 8, p + 1 < npasses ? 8 : 0)) return;
     }
 }
 
@@ -378,6 +435,43 @@ static hipError_t launch_batch2_t(bool nts, const BatchLat* lats, const int* ite
     return hipGetLastError();
 }
 
+template <class T, bool SHIFT, int VX, int NW>
+static hipError_t launch_batch2_persistent_t(bool nts, const BatchLat* lats, const int* item_lat, int nitems,
+                                             int npasses, int max_grid, int ch, unsigned* bar, hipStream_t st)
+{
+    const void* kern = nts ? (const void*)batch_persistent2_kernel<T, SHIFT, VX, NW, true>
+                           : (const void*)batch_persistent2_kernel<T, SHIFT, VX, NW, false>;
+    int grid = 0;
+    unsigned long long wait_ticks = 0, grace_ticks = 0;
+    hipError_t e = persistent_setup(kern, 64 * NW, max_grid, &ch, &grid, &wait_ticks, &grace_ticks, bar, st);
+    if (e != hipSuccess) return e;
+    // an ordinary launch: the membership makes it correct whether or not
+    // every workgroup is resident at once
+    if (nts)
+        hipLaunchKernelGGL((batch_persistent2_kernel<T, SHIFT, VX, NW, true>), dim3(grid), dim3(64 * NW), 0, st,
+                           lats, item_lat, nitems, npasses, ch, bar, wait_ticks, grace_ticks);
+    else
+        hipLaunchKernelGGL((batch_persistent2_kernel<T, SHIFT, VX, NW, false>), dim3(grid), dim3(64 * NW), 0, st,
+                           lats, item_lat, nitems, npasses, ch, bar, wait_ticks, grace_ticks);
+    return hipGetLastError();
+}
+
+template <class T, bool SHIFT>
+static hipError_t launch_batch2_pers_vx(int vx, int nw, bool nts, const BatchLat* lats, const int* item_lat,
+                                        int nitems, int npasses, int max_grid, int ch, unsigned* bar, hipStream_t st)
+{
+#define LBM_P2(VXV, NWV)                                                                                          \
+    if (vx == VXV && nw == NWV)                                                                                   \
+        return launch_batch2_persistent_t<T, SHIFT, VXV, NWV>(nts, lats, item_lat, nitems, npasses, max_grid, ch, \
+                                                              bar, st);
+    LBM_P2(1, 12)
+    LBM_P2(1, 16)
+    LBM_P2(2, 12)
+    LBM_P2(2, 16)
+#undef LBM_P2
+    return hipErrorInvalidValue;
+}
+
 template <class T, bool SHIFT>
 static hipError_t launch_batch2_vx(int vx, int nw, bool nts, const BatchLat* lats, const int* item_lat, int nitems,
                                    int p, int ch, hipStream_t st)
@@ -420,6 +514,19 @@ hipError_t launch_batch2(int dtype, int vx, int nw, bool nts, const BatchLat* la
     case 1: return launch_batch2_vx<float, false>(vx, nw, nts, lats, item_lat, nitems, p, ch, st);
     case 2: return launch_batch2_vx<float, true>(vx, nw, nts, lats, item_lat, nitems, p, ch, st);
     case 3: return launch_batch2_vx<_Float16, true>(vx, nw, nts, lats, item_lat, nitems, p, ch, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_batch2_persistent(int dtype, int vx, int nw, bool nts, const BatchLat* lats, const int* item_lat,
+                                    int nitems, int npasses, int max_grid, int ch, unsigned* bar, hipStream_t st)
+{
+    if (!step2_shape_supported(dtype, vx, nw) || npasses < 1) return hipErrorInvalidValue;
+    switch (dtype) {
+    case 0: return launch_batch2_pers_vx<double, false>(vx, nw, nts, lats, item_lat, nitems, npasses, max_grid, ch, bar, st);
+    case 1: return launch_batch2_pers_vx<float, false>(vx, nw, nts, lats, item_lat, nitems, npasses, max_grid, ch, bar, st);
+    case 2: return launch_batch2_pers_vx<float, true>(vx, nw, nts, lats, item_lat, nitems, npasses, max_grid, ch, bar, st);
+    case 3: return launch_batch2_pers_vx<_Float16, true>(vx, nw, nts, lats, item_lat, nitems, npasses, max_grid, ch, bar, st);
     }
     return hipErrorInvalidValue;
 }

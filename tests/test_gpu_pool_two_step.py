@@ -2,7 +2,8 @@
 steps of every listed lattice, the first held in LDS). Their results are
 bitwise those of the single-step batched kernels: uneven lattices (sub-tile
 and ragged), per-slot step counts (an odd count takes its last step alone),
-several calls in a row (each slot's buffer phase), grouped and graph modes,
+several calls in a row (each slot's buffer phase), grouped, graph and
+persistent modes,
 the no-allocation entry point, reads after two-step calls, switching tiles
 and modes between calls, and the shape errors."""
 import numpy as np
@@ -77,12 +78,30 @@ def test_pool_switching_tiles_and_modes_between_calls():
         P.set_tile(*SINGLE)
         P.step(slots, np.array(CALLS[1], dtype=np.int32))
         P.set_tile(1, 16, TWO)
-        P.set_mode(lbm.PERSISTENT)  # replaces the two-step tile
-        assert not P.get_tile()[2] & TWO
-        with pytest.raises(lbm.LBMError):
-            P.set_tile(2, 16, TWO | NT)
+        P.set_mode(lbm.PERSISTENT)  # two-step passes between grid barriers
+        assert P.get_tile() == (1, 16, TWO)
         P.step(slots, np.array(CALLS[2], dtype=np.int32))
         got = [P.get_f(s) for s in slots]
+    assert all(np.array_equal(a, b) for a, b in zip(got, ref_f))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("max_grid", [0, 3])
+def test_pool_two_step_persistent_bitwise(dtype, max_grid):
+    """One persistent launch per call in two-step tiles (all members, or 3
+    workgroups taking every item), across consecutive calls with per-slot
+    odd and even counts, equals the single-step grouped pool."""
+    ref_f, ref_tot, ref_t, _ = run(dtype, SINGLE)
+    P, slots = make_pool(dtype, (2, 16, TWO | NT), lbm.PERSISTENT)
+    with P:
+        P.set_mode(lbm.PERSISTENT, max_grid)
+        for n in CALLS:
+            P.step(slots, np.array(n, dtype=np.int32))
+        P.sync()
+        got = [P.get_f(s) for s in slots]
+        members = P.persistent_members()
+        assert [P.time(s) for s in slots] == ref_t
+    assert (members == 3) if max_grid == 3 else (members >= 8)
     assert all(np.array_equal(a, b) for a, b in zip(got, ref_f))
 
 
@@ -119,6 +138,7 @@ def test_pool_two_step_shape_errors():
         P.set_tile(2, 16, TWO | 16 | NT)  # the vertical-stack bit is accepted
         assert P.get_tile() == (2, 16, TWO | NT)
     with lbm.Pool(1 << 26, "f16s") as P:  # FP16 storage has the two-step form too
+        assert P.get_tile() == (4, 8, NT)  # its default stays single-step
         P.set_tile(2, 16, TWO)
         P.set_mode(lbm.PERSISTENT)
-        assert P.get_tile() == (4, 8, NT)  # the single-step default of FP16 pools
+        assert P.get_tile() == (2, 16, TWO)
