@@ -249,12 +249,13 @@ int lbm_autotune(lbm_lattice* L, int reps, int use_cache);
 typedef struct lbm_pool lbm_pool;
 
 enum lbm_pool_mode {
-    LBM_POOL_GROUPED = 0,   /* one launch per step                                     */
+    LBM_POOL_GROUPED = 0,   /* one launch per step (per two steps in two-step tiles)   */
     LBM_POOL_GRAPH = 1,     /* the launches of a call captured once in a hipGraph and
                                replayed by later calls with the same shape             */
     LBM_POOL_PERSISTENT = 2 /* one launch for all steps of a call: the workgroups
                                resident when it starts take items dynamically, with a
-                               grid barrier between steps                              */
+                               grid barrier between steps (between two-step passes in
+                               two-step tiles)                                         */
 };
 
 /* Create an empty pool for lattices of `dtype` whose device memory
