@@ -199,10 +199,9 @@ size_t lbm_footprint_bytes(int nx, int ny, int dtype);
  * each owning its own column strip of 64 * vx sites and marching h >= 1
  * rows. Vertical-stack form (LBM_TILE_VSTACK): nw = 4, 8 or 16 waves per
  * workgroup covering one strip and nw - 2 rows (h is ignored). Default:
- * the two-step form below with nw = 16 and non-temporal stores, vx = 1 for
- * LBM_F64 and vx = 2 for LBM_F32 and LBM_F32S; for LBM_F16S the vertical
- * stack with vx = 4, nw = 8 and non-temporal stores. Results do not depend
- * on the shape (bitwise). LBM_EINVAL for an unsupported shape, for
+ * the two-step form below; nw = 16 and non-temporal stores with vx = 1 for
+ * LBM_F64 and vx = 2 for LBM_F32 and LBM_F32S; vx = 1, nw = 32 and plain
+ * stores for LBM_F16S. Results do not depend on the shape (bitwise). LBM_EINVAL for an unsupported shape, for
  * a march-form shape (no LBM_TILE_VSTACK) while the lattice has a c2 field,
  * or for a shape whose grid would exceed one dispatch (2^32 work items) on
  * this lattice (only small shapes on the largest lattices).
@@ -210,8 +209,9 @@ size_t lbm_footprint_bytes(int nx, int ny, int dtype);
  * LBM_TILE_NT_STORE; LBM_F64, LBM_F32 and LBM_F32S): one launch takes two
  * steps of Eq. 5, keeping the first step's results in on-chip memory, so
  * each site is loaded and stored once per two steps. vx = 1 or 2, nw = 12
- * or 16 waves; a workgroup writes nw - 6 rows and (64 - 2 ceil(3 / vx)) vx
- * columns. lbm_step takes the steps in pairs; a lone last step, and every
+ * or 16 waves, or nw = 32 rows on 16 waves (two rows each; vx = 1 and
+ * LBM_F32, LBM_F32S or LBM_F16S); a workgroup writes nw - 6 rows and
+ * (64 - 2 ceil(3 / vx)) vx columns. lbm_step takes the steps in pairs; a lone last step, and every
  * step while inlet/outlet boundaries are set, use the single-step vertical
  * stack (vx = 2, nw = 8, non-temporal stores). The
  * results are those of single steps, bit for bit (c2 fields included).
@@ -346,8 +346,8 @@ int lbm_pool_set_mode(lbm_pool* P, int mode, int max_grid);
  * below with nw 16, vx 1 for LBM_F64 and 2 for LBM_F32 and LBM_F32S, and
  * non-temporal stores; for LBM_F16S vx 4 and nw 8 with non-temporal
  * stores. Two-step tiles (flags LBM_TILE_TWO_STEP, optionally with
- * LBM_TILE_VSTACK and LBM_TILE_NT_STORE; vx 1 or 2, nw 12 or 16; every
- * dtype and mode): each launch (in LBM_POOL_PERSISTENT mode, each pass
+ * LBM_TILE_VSTACK and LBM_TILE_NT_STORE; vx 1 or 2, nw 12 or 16, one row
+ * per wave; every dtype and mode): each launch (in LBM_POOL_PERSISTENT mode, each pass
  * between grid barriers) takes two steps of every listed lattice (the
  * shapes of lbm_set_tile's two-step form); a lattice with an odd step count
  * takes its last step alone in the last one. LBM_EINVAL for other shapes.

@@ -630,8 +630,9 @@ int lbm_pool_set_tile(lbm_pool* P, int vx, int nw, int flags)
     if (!P) return LBM_EINVAL;
     const bool two = (flags & LBM_TILE_TWO_STEP) != 0;
     if (two) {
+        // the batched two-step kernels take one row per wave (nw 12 or 16)
         if ((flags & ~(LBM_TILE_TWO_STEP | LBM_TILE_VSTACK | LBM_TILE_NT_STORE)) ||
-            !step2_shape_supported(P->dtype, vx, nw))
+            !step2_shape_supported(P->dtype, vx, nw) || nw > 16)
             return LBM_EINVAL;
     } else if ((flags & ~LBM_TILE_NT_STORE) || !step_shape_supported(P->dtype, vx, nw, LBM_TILE_VSTACK)) {
         return LBM_EINVAL;

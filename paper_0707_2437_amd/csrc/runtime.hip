@@ -56,16 +56,17 @@ TileDefault default_single_tile(int dtype)
     default: return {4, 8, 8, LBM_TILE_VSTACK | LBM_TILE_NT_STORE};
     }
 }
-// The default shape of a new lattice: two steps per launch where the dtype
-// has that form (FP64 with one column per lane, which measured faster for
-// it and keeps its LDS at half of the CU's).
+// The default shape of a new lattice: two steps per launch (FP64 with one
+// column per lane, which measured faster for it and keeps its LDS at half
+// of the CU's; FP16 in 32-row tiles with plain stores, the only two-step
+// shape that beat its single-step kernel).
 TileDefault default_tile(int dtype)
 {
     switch (dtype) {
     case LBM_F64: return {1, 16, 8, LBM_TILE_VSTACK | LBM_TILE_TWO_STEP | LBM_TILE_NT_STORE};
     case LBM_F32:
     case LBM_F32S: return {2, 16, 8, LBM_TILE_VSTACK | LBM_TILE_TWO_STEP | LBM_TILE_NT_STORE};
-    default: return default_single_tile(dtype);
+    default: return {1, 32, 8, LBM_TILE_VSTACK | LBM_TILE_TWO_STEP};
     }
 }
 

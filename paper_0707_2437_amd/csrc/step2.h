@@ -17,8 +17,8 @@ constexpr int step2_halo_lanes(int vx) { return (3 + vx - 1) / vx; }
 constexpr int step2_cols(int vx) { return (64 - 2 * step2_halo_lanes(vx)) * vx; }
 // Vertically the second step's density gradient needs its gathers one row
 // above and below, those need first-step results one more row out, and
-// those need first-step densities one more row out: a workgroup of nw waves
-// (one row each) writes nw - 6 rows.
+// those need first-step densities one more row out: a tile of nw rows (one
+// per wave, or two per wave for nw = 32) writes nw - 6 rows.
 constexpr int step2_rows(int nw) { return nw - 6; }
 
 }  // namespace lbm

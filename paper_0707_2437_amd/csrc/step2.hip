@@ -283,14 +283,195 @@ __device__ __forceinline__ void step2_tile(const StepTile& a, const void* src, v
     }
 }
 
+// The single-lattice kernel's tile: as step2_tile below, for tiles of NW
+// rows on step2_waves(NW) waves (two rows per wave for 32-row tiles). The
+// batched kernels keep the one-row form: this one's registers spill there,
+// under their 8-waves-per-SIMD target.
+//
+// One two-step tile (NW rows, step2_waves(NW) waves): strip `strip`, row
+// group `grp` of lattice a, reading
+// src and writing dst. single: take one step only (the group's rows and
+// the strip's columns as for two steps, phases 1 and 4 of the header with
+// the relaxed rows written; the lone last step of an odd step count in the
+// batched form). FIELD: the lattice has a c2 field. RC: centre the
+// arithmetic on the lattice model's state at rest (see Centre in step.h).
+// Every wave of the workgroup must call it (it holds workgroup barriers);
+// the caller places a barrier between two calls that reuse lds.
+// KIND: a distinct instantiation per kernel that uses the tile (measured:
+// sharing one instantiation between the grouped and persistent batched
+// kernels made the compiler spill registers in the grouped one).
+// Waves of a two-step tile of NW rows: one row per wave up to 16 waves (the
+// most a workgroup holds), two rows per wave for 32-row tiles (one column
+// per lane and 4-byte or smaller storage, whose LDS still lets two
+// workgroups share a CU). Wave w then holds tile rows w and w + 16, and
+// every phase runs over both.
+constexpr int step2_waves(int nw) { return nw > 16 ? 16 : nw; }
+
+template <class T, bool SHIFT, int VX, int NW, bool NTS, bool FIELD, bool RC>
+__device__ __forceinline__ void step2_tile_rows(const StepTile& a, const void* src, void* dst, int strip, int grp,
+                                           bool single, Step2Lds<T, VX, NW>& lds)
+{
+    using C = typename CompT<T>::type;
+    using K = KeepT<T, C>;
+    constexpr int NWAVES = step2_waves(NW);
+    constexpr int RPW = NW / NWAVES;  // rows per wave
+    static_assert(RPW * NWAVES == NW, "rows a multiple of the waves");
+    constexpr int HL = step2_halo_lanes(VX);
+    constexpr int W2 = step2_cols(VX);
+    constexpr int R2 = step2_rows(NW);
+    static_assert(R2 >= 1, "a two-step tile needs at least 7 rows");
+    constexpr int ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    constexpr int ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    constexpr unsigned es = sizeof(T);
+    auto& rho = lds.rho;
+    auto& fs = lds.fs;
+    constexpr int HW = Step2Lds<T, VX, NW>::LW / 2;
+    auto li = [](int c) { return VX == 2 ? (c & 1) * HW + (c >> 1) : c; };
+
+    const Geom g = a.g;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const int y0 = grp * R2;
+    const int nrows = min(R2, g.ny - y0);
+    const int xs = strip * W2;
+    const int x = xs + (lane - HL) * VX;
+    const bool edge = xs - HL * VX - 1 < 0 || xs + (64 - HL) * VX + 1 > g.nx;
+    const CoefC<C> k = coef_c<C>(a.c);
+    const Centre<C> cn = centre_c<C, RC>(a.c);
+    const int col = lane * VX + 1;
+    const int nv = min(VX, g.nx - x);
+    const bool lane_out = lane >= HL && lane < 64 - HL && nv > 0;
+
+    K d[RPW][9][VX];
+    C w[RPW][VX];
+    C af[RPW][VX] = {};
+    auto relax = [&](int q, int r, C (&o)[VX][9]) {
+        const C* rrow = rho[r];
+#pragma unroll
+        for (int j = 0; j < VX; ++j) {
+            const C left = j == 0 ? rrow[li(col - 1)] : w[q][j - 1];
+            const C right = j == VX - 1 ? rrow[li(col + VX)] : w[q][j + 1];
+            const C gx = right - left;
+            const C gy = rho[r + 1][li(col + j)] - rho[r - 1][li(col + j)];
+            collide<T, SHIFT, C, VX, RC>(d[q], j, w[q][j], gx, gy, site_coef<FIELD>(k, af[q][j]), cn, o[j]);
+        }
+    };
+    auto write = [&](int r, const C (&o)[VX][9]) {
+        const int y = y0 - 3 + r;
+        Pack<T, VX> pk[9];
+#pragma unroll
+        for (int j = 0; j < VX; ++j)
+#pragma unroll
+            for (int i = 0; i < 9; ++i) pk[i].v[j] = from_d<T, SHIFT, C>(o[j][i], i, cn);
+        char* dbase[9];
+        if constexpr (VX == 1) {
+            const char* rows[9];
+            plane_rows<T, false>(dst, g, 0, y, rows);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) dbase[i] = const_cast<char*>(rows[i]);
+            write_row<T, VX, NTS>(dbase, g, 0, x, nv, pk);
+        } else {
+            dst_bases<T>(dst, g, dbase);
+            write_row<T, VX, NTS>(dbase, g, y, x, nv, pk);
+        }
+    };
+#pragma unroll
+    for (int q = 0; q < RPW; ++q) {
+        const int r = wave + q * NWAVES;  // the tile row, at lattice row y0 - 3 + r
+        const bool load = single ? (r >= 2 && r <= nrows + 3) : (r <= nrows + 5);
+        if (load) {
+            const int y = y0 - 3 + r;
+            const int yw = y < 0 ? y + g.ny : (y >= g.ny ? y - g.ny : y);
+            const char* rb[9];
+            plane_rows<T, true>(src, g, -2, yw, rb);
+            if constexpr (FIELD)
+                if (single ? (r >= 3 && r <= nrows + 2) : (r >= 1 && r <= nrows + 4))
+                    field_own<C, VX>(a, yw, x, edge, af[q]);
+            T raw[9][VX];
+            if (edge) {
+                gather_own_wrapped<T, VX>(rb, g, x, raw);
+            } else {
+                constexpr int A = es < 4 ? (int)es : 4;
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    const Pack<T, VX> p = ld_vec<T, VX, A>(rb[i], (unsigned)(x - ex[i] + 2) * es);
+#pragma unroll
+                    for (int j = 0; j < VX; ++j) raw[i][j] = p.v[j];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+#pragma unroll
+                for (int j = 0; j < VX; ++j) d[q][i][j] = keep_of<T, SHIFT, C>(raw[i][j], i, cn);
+#pragma unroll
+            for (int j = 0; j < VX; ++j) {
+                w[q][j] = drho_of<T, SHIFT, C, VX>(d[q], j, cn);
+                rho[r][li(col + j)] = w[q][j];
+            }
+        }
+    }
+    __syncthreads();
+    if (single) {
+#pragma unroll
+        for (int q = 0; q < RPW; ++q) {
+            const int r = wave + q * NWAVES;
+            if (r >= 3 && r <= nrows + 2 && lane_out) {
+                C o[VX][9];
+                relax(q, r, o);
+                write(r, o);
+            }
+        }
+        return;
+    }
+#pragma unroll
+    for (int q = 0; q < RPW; ++q) {
+        const int r = wave + q * NWAVES;
+        if (r >= 1 && r <= min(nrows + 4, NW - 2)) {
+            C o[VX][9];
+            relax(q, r, o);
+#pragma unroll
+            for (int j = 0; j < VX; ++j)
+#pragma unroll
+                for (int i = 0; i < 9; ++i) fs[r - 1][i][li(col + j)] = from_d<T, SHIFT, C>(o[j][i], i, cn);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < RPW; ++q) {
+        const int r = wave + q * NWAVES;
+        if (r >= 2 && r <= min(nrows + 3, NW - 3)) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+#pragma unroll
+                for (int j = 0; j < VX; ++j)
+                    d[q][i][j] = keep_of<T, SHIFT, C>(fs[r - ey[i] - 1][i][li(col + j - ex[i])], i, cn);
+#pragma unroll
+            for (int j = 0; j < VX; ++j) {
+                w[q][j] = drho_of<T, SHIFT, C, VX>(d[q], j, cn);
+                rho[r][li(col + j)] = w[q][j];
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < RPW; ++q) {
+        const int r = wave + q * NWAVES;
+        if (r >= 3 && r <= nrows + 2 && lane_out) {
+            C o[VX][9];
+            relax(q, r, o);
+            write(r, o);
+        }
+    }
+}
+
 // FIELD: a lattice with a c2 field (per-site source coefficients).
 template <class T, bool SHIFT, int VX, int NW, bool NTS, bool FIELD>
-__global__ __launch_bounds__(64 * NW) void step2_vstack_kernel(StepTile a, int ntiles)
+__global__ __launch_bounds__(64 * step2_waves(NW)) void step2_vstack_kernel(StepTile a, int ntiles)
 {
     __shared__ Step2Lds<T, VX, NW> lds;
     const int t = xcd_tile(blockIdx.x, gridDim.x, a.xcd_chunk);
     if (t >= ntiles) return;
-    step2_tile<T, SHIFT, VX, NW, NTS, FIELD, ModelCentred<typename CompT<T>::type>::value>(
+    step2_tile_rows<T, SHIFT, VX, NW, NTS, FIELD, ModelCentred<typename CompT<T>::type>::value>(
         a, a.src, a.dst, t % a.nstrips, t / a.nstrips, false, lds);
 }
 
@@ -386,8 +567,8 @@ static hipError_t launch2_t(bool nts, const StepTile& t, hipStream_t st)
     const int ntiles = t.nstrips * t.nchunks;  // strips x row groups
     const int q = t.xcd_chunk > 0 ? 8 * t.xcd_chunk : 8;
     const int grid = (ntiles + q - 1) / q * q;
-    if (!grid_fits(grid, 64 * NW)) return hipErrorInvalidConfiguration;
-    const dim3 gd(grid), bd(64 * NW);
+    if (!grid_fits(grid, 64 * step2_waves(NW))) return hipErrorInvalidConfiguration;
+    const dim3 gd(grid), bd(64 * step2_waves(NW));
     if (t.field) {
         if (nts) hipLaunchKernelGGL((step2_vstack_kernel<T, SHIFT, VX, NW, true, true>), gd, bd, 0, st, t, ntiles);
         else hipLaunchKernelGGL((step2_vstack_kernel<T, SHIFT, VX, NW, false, true>), gd, bd, 0, st, t, ntiles);
@@ -404,6 +585,9 @@ static hipError_t launch2_nw(int nw, bool nts, const StepTile& t, hipStream_t st
     switch (nw) {
     case 12: return launch2_t<T, SHIFT, VX, 12>(nts, t, st);
     case 16: return launch2_t<T, SHIFT, VX, 16>(nts, t, st);
+    case 32:
+        if constexpr (VX == 1 && sizeof(T) <= 4) return launch2_t<T, SHIFT, VX, 32>(nts, t, st);
+        return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
     }
 }
@@ -424,13 +608,14 @@ static hipError_t launch_batch2_t(bool nts, const BatchLat* lats, const int* ite
 {
     const int q = ch > 0 ? 8 * ch : 8;
     const int grid = (nitems + q - 1) / q * q;
+    constexpr int threads = 64 * step2_waves(NW);
     if (nitems <= 0) return hipSuccess;
-    if (!grid_fits(grid, 64 * NW)) return hipErrorInvalidConfiguration;
+    if (!grid_fits(grid, threads)) return hipErrorInvalidConfiguration;
     if (nts)
-        hipLaunchKernelGGL((batch_step2_kernel<T, SHIFT, VX, NW, true>), dim3(grid), dim3(64 * NW), 0, st, lats,
+        hipLaunchKernelGGL((batch_step2_kernel<T, SHIFT, VX, NW, true>), dim3(grid), dim3(threads), 0, st, lats,
                            item_lat, nitems, p, ch);
     else
-        hipLaunchKernelGGL((batch_step2_kernel<T, SHIFT, VX, NW, false>), dim3(grid), dim3(64 * NW), 0, st, lats,
+        hipLaunchKernelGGL((batch_step2_kernel<T, SHIFT, VX, NW, false>), dim3(grid), dim3(threads), 0, st, lats,
                            item_lat, nitems, p, ch);
     return hipGetLastError();
 }
@@ -441,17 +626,18 @@ static hipError_t launch_batch2_persistent_t(bool nts, const BatchLat* lats, con
 {
     const void* kern = nts ? (const void*)batch_persistent2_kernel<T, SHIFT, VX, NW, true>
                            : (const void*)batch_persistent2_kernel<T, SHIFT, VX, NW, false>;
+    constexpr int threads = 64 * step2_waves(NW);
     int grid = 0;
     unsigned long long wait_ticks = 0, grace_ticks = 0;
-    hipError_t e = persistent_setup(kern, 64 * NW, max_grid, &ch, &grid, &wait_ticks, &grace_ticks, bar, st);
+    hipError_t e = persistent_setup(kern, threads, max_grid, &ch, &grid, &wait_ticks, &grace_ticks, bar, st);
     if (e != hipSuccess) return e;
     // an ordinary launch: the membership makes it correct whether or not
     // every workgroup is resident at once
     if (nts)
-        hipLaunchKernelGGL((batch_persistent2_kernel<T, SHIFT, VX, NW, true>), dim3(grid), dim3(64 * NW), 0, st,
+        hipLaunchKernelGGL((batch_persistent2_kernel<T, SHIFT, VX, NW, true>), dim3(grid), dim3(threads), 0, st,
                            lats, item_lat, nitems, npasses, ch, bar, wait_ticks, grace_ticks);
     else
-        hipLaunchKernelGGL((batch_persistent2_kernel<T, SHIFT, VX, NW, false>), dim3(grid), dim3(64 * NW), 0, st,
+        hipLaunchKernelGGL((batch_persistent2_kernel<T, SHIFT, VX, NW, false>), dim3(grid), dim3(threads), 0, st,
                            lats, item_lat, nitems, npasses, ch, bar, wait_ticks, grace_ticks);
     return hipGetLastError();
 }
@@ -486,7 +672,7 @@ static hipError_t launch_batch2_vx(int vx, int nw, bool nts, const BatchLat* lat
 // dtype: 0 FP64, 1 FP32, 2 FP32-shifted, 3 FP16-shifted.
 bool step2_shape_supported(int dtype, int vx, int nw)
 {
-    return dtype >= 0 && dtype <= 3 && (vx == 1 || vx == 2) && (nw == 12 || nw == 16);
+    return dtype >= 0 && dtype <= 3 && (vx == 1 || vx == 2) && (nw == 12 || nw == 16 || (nw == 32 && vx == 1 && dtype != 0));
 }
 
 // flags: LBM_TILE_NT_STORE (2) selects non-temporal stores.

@@ -98,12 +98,13 @@ std::vector<TileCand> lattice_candidates(int dtype)
         for (int nw : nws)
             for (int nts = 0; nts < 2; ++nts)
                 v.push_back({vx, nw, 8, LBM_TILE_VSTACK | (nts ? LBM_TILE_NT_STORE : 0), 0});
-    // two steps per launch
-    (void)dtype;
+    // two steps per launch (32-row tiles: one column per lane, 4-byte or
+    // smaller storage)
     for (int vx : {1, 2})
-        for (int nw : {12, 16})
+        for (int nw : {12, 16, 32})
             for (int nts = 0; nts < 2; ++nts)
-                v.push_back({vx, nw, 8, LBM_TILE_VSTACK | LBM_TILE_TWO_STEP | (nts ? LBM_TILE_NT_STORE : 0), 0});
+                if (nw < 32 || (vx == 1 && dtype != LBM_F64))
+                    v.push_back({vx, nw, 8, LBM_TILE_VSTACK | LBM_TILE_TWO_STEP | (nts ? LBM_TILE_NT_STORE : 0), 0});
     // march form: prefetched, row-band order
     for (int vx : {1, 2})
         for (int h : {4, 8})
@@ -123,7 +124,7 @@ std::vector<TileCand> pool_candidates(int dtype)
             for (int nts = 0; nts < 2; ++nts)
                 for (int per : {1, 2})
                     for (int ch : {8, 32}) v.push_back({vx, nw, per, nts ? LBM_TILE_NT_STORE : 0, ch});
-    // two steps per launch (grouped and graph modes)
+    // two steps per launch
     for (int vx : {1, 2})
         for (int nw : {12, 16})
             for (int per : {1, 2})

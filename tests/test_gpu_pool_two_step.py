@@ -51,10 +51,11 @@ def run(dtype, tile, mode=lbm.GROUPED, calls=CALLS, noalloc=False):
 def test_pool_two_step_bitwise(dtype):
     ref_f, ref_tot, ref_t, _ = run(dtype, (4, 8, NT) if dtype == "f16s" else SINGLE)
     assert ref_t == [sum(c[k] for c in CALLS) for k in range(len(SPECS))]
-    for vx, nw in ((1, 12), (1, 16), (2, 12), (2, 16)):
+    shapes = [(1, 12, TWO | NT), (1, 16, TWO | NT), (2, 12, TWO | NT), (2, 16, TWO | NT)]
+    for vx, nw, fl in shapes:
         for mode in (lbm.GROUPED, lbm.GRAPH):
-            f, tot, t, tile = run(dtype, (vx, nw, TWO | NT), mode)
-            assert tile == (vx, nw, TWO | NT)
+            f, tot, t, tile = run(dtype, (vx, nw, fl), mode)
+            assert tile == (vx, nw, fl)
             assert t == ref_t
             for k in range(len(SPECS)):
                 assert np.array_equal(f[k], ref_f[k]), (dtype, vx, nw, mode, SPECS[k])
@@ -85,14 +86,15 @@ def test_pool_switching_tiles_and_modes_between_calls():
     assert all(np.array_equal(a, b) for a, b in zip(got, ref_f))
 
 
-@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("dtype,tile", [("f64", (2, 16, TWO | NT)), ("f32", (2, 16, TWO | NT)),
+                                        ("f32", (1, 12, TWO))])
 @pytest.mark.parametrize("max_grid", [0, 3])
-def test_pool_two_step_persistent_bitwise(dtype, max_grid):
+def test_pool_two_step_persistent_bitwise(dtype, tile, max_grid):
     """One persistent launch per call in two-step tiles (all members, or 3
     workgroups taking every item), across consecutive calls with per-slot
     odd and even counts, equals the single-step grouped pool."""
     ref_f, ref_tot, ref_t, _ = run(dtype, SINGLE)
-    P, slots = make_pool(dtype, (2, 16, TWO | NT), lbm.PERSISTENT)
+    P, slots = make_pool(dtype, tile, lbm.PERSISTENT)
     with P:
         P.set_mode(lbm.PERSISTENT, max_grid)
         for n in CALLS:
@@ -132,7 +134,7 @@ def test_pool_two_step_reinit_and_readd():
 
 def test_pool_two_step_shape_errors():
     with lbm.Pool(1 << 26, "f32") as P:
-        for bad in ((4, 16, TWO), (2, 8, TWO), (2, 16, TWO | 1), (2, 16, 64)):
+        for bad in ((4, 16, TWO), (2, 8, TWO), (2, 16, TWO | 1), (2, 16, 64), (1, 32, TWO)):
             with pytest.raises(lbm.LBMError):
                 P.set_tile(*bad)
         P.set_tile(2, 16, TWO | 16 | NT)  # the vertical-stack bit is accepted

@@ -49,8 +49,14 @@ def test_totals_ring_wraps_and_grows():
     short jobs, the ring wraps (after reading back the queued ticks) and
     grows (when one tick finishes more jobs than half of it); every job's
     FP64 totals are still bitwise those of the job stepped alone."""
-    jobs = serve.job_stream(rate=3000.0, duration=0.025, seed=11, side_log2=(5, 6), steps=(10, 80))
-    assert len(jobs) >= 40
+    # all jobs arrive at once; their step counts end in six different ticks,
+    # each finishing 6-7 jobs (more than half of the ring: it grows), and
+    # the later ticks reuse the ring's rows (it wraps)
+    rng = np.random.default_rng(11)
+    jobs = [serve.Job(id=k, nx=int(rng.choice([32, 48, 64])), ny=int(rng.choice([32, 48, 64])),
+                      tau=float(rng.uniform(0.6, 1.2)), c2=float(rng.uniform(0.1, 0.5)),
+                      amp=float(rng.uniform(0.01, 0.05)), steps=7 * (1 + k % 6) - (k % 2), arrival=0.0)
+            for k in range(40)]
     srv = serve.Server(1 << 28, "f32", tick_steps=7, ring_rows=4)
     st = srv.run(jobs, duration=0.0, drain=True)
     srv.close()

@@ -22,6 +22,11 @@ import paper_0707_2437_amd as lbm  # noqa: E402
 
 VSTACK, TWO_STEP, NT = 16, 32, 2
 SHAPES = [(vx, nw, f) for vx in (1, 2) for nw in (12, 16) for f in (VSTACK | TWO_STEP, VSTACK | TWO_STEP | NT)]
+ROWS32 = [(1, 32, VSTACK | TWO_STEP), (1, 32, VSTACK | TWO_STEP | NT)]  # two rows per wave; not FP64
+
+
+def shapes_for(dtype):
+    return SHAPES + ([] if dtype == "f64" else ROWS32)
 
 
 def run(nx, ny, tau, c2, dtype, steps, fields, tile=None, model=None):
@@ -41,7 +46,7 @@ def test_two_step_bitwise_equals_single_steps(dtype, nx, ny):
     fields = smooth_random_state(nx, ny, seed=nx * 31 + ny)
     for steps in (6, 7):
         ref = run(nx, ny, 0.7, 0.45, dtype, steps, fields)
-        for vx, nw, f in SHAPES:
+        for vx, nw, f in shapes_for(dtype):
             got = run(nx, ny, 0.7, 0.45, dtype, steps, fields, (vx, nw, 0, f))
             assert np.array_equal(got, ref), (dtype, nx, ny, steps, vx, nw, f)
 
@@ -97,11 +102,16 @@ def test_two_step_with_inlet_outlet():
 
 def test_two_step_shape_errors():
     with lbm.Lattice(64, 64, 0.7, 0.3, "f32") as L:
+        L.set_tile(1, 32, 0, VSTACK | TWO_STEP)
         for bad in ((4, 16, 0, VSTACK | TWO_STEP), (2, 8, 0, VSTACK | TWO_STEP), (2, 16, 0, TWO_STEP),
-                    (2, 16, 0, VSTACK | TWO_STEP | 1), (2, 16, 0, 64 | VSTACK)):
+                    (2, 16, 0, VSTACK | TWO_STEP | 1), (2, 16, 0, 64 | VSTACK), (2, 32, 0, VSTACK | TWO_STEP)):
             with pytest.raises(lbm.LBMError):
                 L.set_tile(*bad)
+    with lbm.Lattice(64, 64, 0.7, 0.3, "f64") as L:
+        with pytest.raises(lbm.LBMError):
+            L.set_tile(1, 32, 0, VSTACK | TWO_STEP)  # 32-row tiles: 4-byte or smaller storage
     with lbm.Lattice(64, 64, 0.7, 0.3, "f16s") as L:  # FP16 storage has the two-step form too
+        assert L.get_tile() == (1, 32, 8, VSTACK | TWO_STEP)  # its default
         L.set_tile(2, 16, 0, VSTACK | TWO_STEP)
 
 
@@ -122,7 +132,7 @@ def test_two_step_c2_field_bitwise(dtype, nx, ny):
             return L.init(*fields).step(7).get_f()
 
     ref = go((4, 8, 0, VSTACK | NT) if dtype == "f16s" else (2, 8, 0, VSTACK | NT))
-    for vx, nw, f in SHAPES:
+    for vx, nw, f in shapes_for(dtype):
         assert np.array_equal(go((vx, nw, 0, f)), ref), (dtype, nx, ny, vx, nw, f)
     assert np.array_equal(go(None), ref)  # the default shape
 
