@@ -70,7 +70,7 @@ def test_two_step_parity_with_oracle():
         assert max_rel_err(got, ref) <= tol, dtype
 
 
-@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("dtype", ["f32", "f64", "f16s"])
 def test_two_step_full_size_bitwise(dtype):
     """4096 x 4096, the benchmark's lattice: 10 steps (5 two-step launches)
     in the default two-step shapes against 10 single steps."""
@@ -79,10 +79,14 @@ def test_two_step_full_size_bitwise(dtype):
     rho = 1.0 + 1e-3 * rng.standard_normal((n, n))
     ux = 1e-3 * rng.standard_normal((n, n))
     uy = 1e-3 * rng.standard_normal((n, n))
-    ref = run(n, n, 0.6, 0.25, dtype, 10, (rho, ux, uy), (2, 8, 0, VSTACK | NT))
-    for vx, nw in ((1, 16), (2, 16)):
-        got = run(n, n, 0.6, 0.25, dtype, 10, (rho, ux, uy), (vx, nw, 0, VSTACK | TWO_STEP | NT))
-        assert np.array_equal(got, ref), (dtype, vx, nw)
+    single = (4, 8, 0, VSTACK | NT) if dtype == "f16s" else (2, 8, 0, VSTACK | NT)
+    ref = run(n, n, 0.6, 0.25, dtype, 10, (rho, ux, uy), single)
+    shapes = [(1, 16, VSTACK | TWO_STEP | NT), (2, 16, VSTACK | TWO_STEP | NT)]
+    if dtype != "f64":
+        shapes.append((1, 32, VSTACK | TWO_STEP))  # two rows per wave (FP16's default)
+    for vx, nw, f in shapes:
+        got = run(n, n, 0.6, 0.25, dtype, 10, (rho, ux, uy), (vx, nw, 0, f))
+        assert np.array_equal(got, ref), (dtype, vx, nw, f)
         del got
 
 
