@@ -227,10 +227,10 @@ enum lbm_tile_flags {
 int lbm_set_tile(lbm_lattice* L, int vx, int nw, int h, int flags);
 int lbm_get_tile(const lbm_lattice* L, int* vx, int* nw, int* h, int* flags);
 
-/* Autotuner: time the candidate kernel shapes on this lattice (reps timed
- * launches each, after two warm-up launches; every launch reads the current
- * state and writes the spare buffer, so the state is unchanged) and apply the
- * fastest. With use_cache != 0 a shape found before for the same GPU
+/* Autotuner: time the candidate kernel shapes on this lattice, single- and
+ * two-step, each over two steps (reps timed rounds each, after warm-up
+ * launches; every launch reads the current state and writes the spare
+ * buffer, so the state is unchanged) and apply the fastest. With use_cache != 0 a shape found before for the same GPU
  * architecture, dtype and nx x ny is applied without timing. Results are
  * remembered for the process and, if the environment variable LBM_TUNE_CACHE
  * names a file, appended to it (one JSON object per line). Synchronous.
@@ -240,8 +240,9 @@ int lbm_autotune(lbm_lattice* L, int reps, int use_cache);
 /* ---------------------------------------------------------------------------
  * Pools: the batched and served forms. A pool holds resident lattices
  * (slots) of one dtype, each with its own nx, ny, tau and c2, under a device
- * memory budget, and steps any subset of them together: every step of the
- * listed lattices is one launch over all their tiles (the same per-site code
+ * memory budget, and steps any subset of them together: every step (or two
+ * steps, in two-step tiles) of the listed lattices is one launch over all
+ * their tiles (the same per-site code
  * as the single-lattice kernel, so each slot's result is bitwise identical to
  * stepping it alone with lbm_step). All pool work runs on the pool's stream.
  * A pool is not thread-safe.
